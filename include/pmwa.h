@@ -1,0 +1,158 @@
+/*
+ * pmwa.h -- C ABI of the MI355X (gfx950) implementation of one Monte Carlo
+ * sweep of the parallelized multiple-worm algorithm (PMWA; Masaki-Kato,
+ * Suzuki, Harada, Todo, Kawashima, arXiv:1307.0328) for the hard-core
+ * Bose-Hubbard model with the fictitious source term eta*Q:
+ *
+ *     H_eta = sum_<ij> [ -t (b_i^+ b_j + h.c.) + V n_i n_j ]
+ *             - mu sum_i n_i - eta sum_i (b_i + b_i^+)
+ *
+ * (Eq. (BH), one term per nearest-neighbour bond, and H_eta = H - eta Q of
+ * the introduction).  A sweep is, in this order:
+ *   vertex phase             (pseudo code Step 3)
+ *   worm re-generation       (Step 4, Eq. (worm))
+ *   worm scattering x N_cycle (Steps 5-6, Eq. (DB)) + measurement (Step 6,
+ *                             Supplemental S-I)
+ *   temporal-boundary update (Step 1, Eq. (Para))
+ *   spatial-boundary update  (Step 2, Eq. (ParaSpace)), x bonds then y bonds
+ * The paper's space-time domains (N_beta x N_L^d decomposition, Supplemental
+ * S-II) are work units on one GPU; its neighbour messages are reads and
+ * writes of the neighbours' arrays in device memory.
+ *
+ * Representation (shared with any checker through the canonical state
+ * below): M = 2^ticks_log2 ticks per beta; vertices on integer ticks, worms
+ * on half-tick slots (slot u at u + 1/2); temporal boundary k just below
+ * tick T_k = floor(k M / dom_tau); per site, objects ordered by (tick,
+ * vertices before the worm slot, bond id); site = y*Lx + x, bond id =
+ * 2*site + d (d = 0: +x, 1: +y).  Random numbers: Philox4x32-10 keyed by
+ * `seed`, counter (word pair, unit, sweep, chain_id << 8 | stream kind), so
+ * a chain's trajectory depends only on its parameters, never on how it is
+ * batched.
+ *
+ * Conventions: every entry point returns 0 or a negative PMWA_E* code; no
+ * exception crosses the ABI.  The handle owns all device memory it
+ * allocates (hipMalloc at create, hipFree at destroy).  All pointers are
+ * host pointers unless stated.  The stream in pmwa_opts is borrowed: work is
+ * enqueued on it, and calls that return host data synchronise it.
+ */
+#ifndef PMWA_H
+#define PMWA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PMWA_OK = 0,
+    PMWA_EINVAL = -1,     /* bad argument or parameter outside the limits */
+    PMWA_ENOMEM = -2,     /* device or host allocation failed             */
+    PMWA_EDEVICE = -3,    /* a HIP call failed                            */
+    PMWA_EOVERFLOW = -4,  /* a per-site or per-bond capacity was exceeded; */
+                          /* the state of that chain is no longer valid    */
+    PMWA_ESTATE = -5      /* inconsistent state (set_state input, sampler) */
+};
+
+/* One chain (one Markov chain of one lattice).  Copied at create. */
+typedef struct pmwa_params {
+    int32_t  Lx, Ly;          /* periodic Lx x Ly square lattice, each >= 3       */
+    double   beta;            /* inverse temperature (beta*t with t = 1)          */
+    double   t, V, mu, eta;   /* hopping >= 0, repulsion, chem. potential, eta > 0 */
+    int32_t  dom_x, dom_y;    /* spatial domain grid; Lx % dom_x == 0, extent >= 2 */
+    int32_t  dom_tau;         /* temporal domains N_beta, 1..64                    */
+    int32_t  ticks_log2;      /* M = 2^ticks_log2 ticks per beta, 8..30            */
+    int32_t  n_cycle;         /* scattering cycles per sweep; <= 0: ceil(4 C/eta)  */
+    double   C;               /* diagonal shift; NaN: max_s E_b(s) + t/2          */
+    uint64_t seed;            /* Philox key                                        */
+    uint32_t chain_id;        /* Philox stream id, < 2^24                          */
+    uint32_t pad_;
+} pmwa_params;
+
+/* Launch options.  Zero-initialise for the defaults. */
+typedef struct pmwa_opts {
+    void*   stream;           /* hipStream_t (borrowed); NULL = null stream      */
+    int32_t scatter_mode;     /* 0 auto, 1 domain in LDS, 2 domain in HBM        */
+    int32_t series_cap;       /* per-chain device rows of per-sweep records     */
+    int32_t event_cap;        /* events per (site, slab); 0 = from the density  */
+    int32_t use_graph;        /* 1: replay a captured sweep (hipGraph)          */
+    int32_t reserved[4];
+} pmwa_opts;
+
+/* Raw per-sweep record of one chain (all sums over the whole lattice). */
+typedef struct pmwa_obs {
+    int64_t nv;      /* bond vertices present after the vertex phase          */
+    int64_t nkink;   /* kinks among them (after the worm phase)               */
+    int64_t nw;      /* worms after the scattering phase                       */
+    int64_t occ2;    /* sum_i int n_i dtau after the worm phase, half-ticks    */
+    int64_t nn2;     /* sum_<ij> int n_i n_j dtau before the vertex phase, half-ticks */
+    double  qimp;    /* sum over intervals of l * g_sigma(eta Delta l), g_0 = tanh,
+                        g_1 = coth: the improved worm-density estimator (S-I) */
+} pmwa_obs;
+
+/* Derived constants of one chain. */
+typedef struct pmwa_chain_info {
+    double  C, rho_max, delta, lambda;    /* Delta = beta/M, lambda = eta Delta */
+    int32_t n_cycle, M, event_cap, bond_cap;
+    int64_t n_domains;
+} pmwa_chain_info;
+
+typedef struct pmwa_handle pmwa_t;
+
+/* Validate `chains[0..n_chains)`, build the tables, allocate device memory,
+   enqueue the empty initial configuration (all occupations 0, no vertices,
+   no worms).  *out receives the handle, or NULL on error. */
+int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts,
+                pmwa_t** out);
+
+/* Enqueue n_sweeps full sweeps of every chain on the handle's stream.  The
+   per-sweep records go to a device ring; when it would overflow the call
+   synchronises and drains it to host memory first. */
+int pmwa_sweep(pmwa_t* h, int64_t n_sweeps);
+
+/* Enqueue one phase of a sweep for every chain: 1 vertex, 2 worm
+   re-generation, 3 scattering + measurement, 4 temporal boundaries,
+   5 spatial boundaries (x), 6 spatial boundaries (y), 7 end of sweep
+   (record the measurement, advance the sweep counter).  For tests. */
+int pmwa_phase(pmwa_t* h, int phase);
+
+/* Synchronise and copy up to max_rows unread per-sweep records of `chain`
+   into out[]; *n_rows receives the count.  Returns PMWA_EOVERFLOW if the
+   chain's state was invalidated by a capacity overflow. */
+int pmwa_measure(pmwa_t* h, int chain, pmwa_obs* out, int64_t max_rows,
+                 int64_t* n_rows);
+
+/* Synchronise; return 0 or the first error raised on the device. */
+int pmwa_status(pmwa_t* h);
+
+/* Canonical state of one chain (synchronises).  Layout:
+     bstate[k*N + site]   occupation just above temporal boundary k (uint8)
+     counts[k*N + site]   events of `site` in slab k
+     ticks[], infos[]     events, slab-major, then site, then time order;
+                          info bit0 worm, bit3 occupation above the event,
+                          vertex bits1-2: bond direction from this site
+                          (0 +x, 1 +y, 2 -x, 3 -y); worm bit1: 1 = moving up.
+   N = Lx*Ly.  get: `cap` is the size of ticks/infos; *n_events receives the
+   number of events (PMWA_EINVAL if cap is too small; call with cap = 0 to
+   query).  set: replaces the state (validated: sorted, in range, capacity). */
+int pmwa_get_state(pmwa_t* h, int chain, uint8_t* bstate, int32_t* counts,
+                   int32_t* ticks, uint32_t* infos, int64_t cap,
+                   int64_t* n_events, uint64_t* sweep);
+int pmwa_set_state(pmwa_t* h, int chain, const uint8_t* bstate,
+                   const int32_t* counts, const int32_t* ticks,
+                   const uint32_t* infos, int64_t n_events, uint64_t sweep);
+
+int pmwa_chain_info(pmwa_t* h, int chain, pmwa_chain_info* out);
+
+/* Events per (site, slab) a chain would be given by default. */
+int pmwa_default_event_cap(const pmwa_params* p);
+
+/* Free all device memory of the handle (synchronises first). */
+void pmwa_destroy(pmwa_t* h);
+
+const char* pmwa_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

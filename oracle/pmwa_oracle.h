@@ -1,0 +1,123 @@
+/*
+ * pmwa_oracle.h -- serial CPU oracle for the parallelized multiple-worm
+ * algorithm (PMWA, Masaki-Kato, Suzuki, Harada, Todo, Kawashima,
+ * arXiv:1307.0328).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, serial fp64
+ * implementation of one PMWA Monte Carlo step for the hard-core
+ * Bose-Hubbard model with the source term eta*Q, written from the paper:
+ *   - vertex phase                      (pseudo code, Step 3)
+ *   - worm creation / annihilation      (Eq. (worm), pseudo code Step 4)
+ *   - worm scattering, N_cycle times    (Eq. (DB), Steps 5-6)
+ *   - measurement                       (Step 6; Supplemental S-I)
+ *   - temporal-boundary update          (Eq. (Para), Step 1)
+ *   - spatial-boundary vertex update    (Eq. (ParaSpace), Step 2)
+ * Only tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.  It shares no code with the GPU library.
+ *
+ * Conventions (the discretised continuous-time representation):
+ *   M = 2^ticks_log2 ticks per beta; vertices sit on integer ticks,
+ *   worms on half-tick slots (slot u sits at u + 1/2).  Temporal boundary
+ *   k sits just below tick T_k = floor(k*M/N_tau).  On a site, objects are
+ *   ordered by (tick, vertices before the worm slot, bond id).
+ *   Site id = y*Lx + x; bond id = 2*site + d (d = 0: +x, d = 1: +y).
+ *
+ * Canonical state (the exchange format with the GPU library):
+ *   bstate[k*N + site]  uint8 occupation just above boundary k
+ *   counts[k*N + site]  number of events of `site` in slab k
+ *   events, slab-major then site-major then in time order:
+ *     tick  int32
+ *     info  uint32: bit0 = worm; bit3 = occupation just above the event;
+ *                   vertex: bits1-2 = bond direction seen from this site
+ *                           (0 +x, 1 +y, 2 -x, 3 -y);
+ *                   worm:   bit1 = direction (1 = up, 0 = down).
+ */
+#ifndef PMWA_ORACLE_H
+#define PMWA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_params {
+    int32_t  Lx, Ly;             /* periodic Lx x Ly square lattice, >= 3    */
+    double   beta;               /* inverse temperature                      */
+    double   t, V, mu, eta;      /* hopping, n.n. repulsion, chem. pot., eta */
+    int32_t  dom_x, dom_y, dom_tau; /* domain grid (extent >= 2 each)        */
+    int32_t  ticks_log2;         /* M = 2^ticks_log2 ticks per beta          */
+    int32_t  n_cycle;            /* <= 0: ceil(4 C / eta)                    */
+    double   C;                  /* diagonal shift; NaN: default rule        */
+    uint64_t seed;               /* Philox key                               */
+    uint32_t chain_id;           /* Philox stream id (< 2^24)                */
+    uint32_t pad_;
+} orc_params;
+
+/* Per-sweep raw measurement. */
+typedef struct orc_obs {
+    int64_t nv;      /* bond vertices present                       */
+    int64_t nkink;   /* kinks among them                            */
+    int64_t nw;      /* worms after the scattering phase            */
+    int64_t occ2;    /* sum_i int n_i dtau, in half-ticks           */
+    int64_t nn2;     /* sum_<ij> int n_i n_j dtau, in half-ticks    */
+    double  qimp;    /* sum over intervals of l * g_sigma(eta*Delta*l) */
+} orc_obs;
+
+typedef struct orc_chain orc_chain;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESTATE = -3 };
+
+/* phases, in sweep order */
+enum { ORC_PH_V = 1, ORC_PH_R = 2, ORC_PH_S = 3, ORC_PH_BT = 4,
+       ORC_PH_BSX = 5, ORC_PH_BSY = 6, ORC_PH_END = 7 };
+
+int  orc_create(const orc_params* p, orc_chain** out);
+void orc_destroy(orc_chain* c);
+int  orc_sweep(orc_chain* c, int64_t n_sweeps);
+int  orc_phase(orc_chain* c, int phase);        /* one phase of a sweep */
+int64_t orc_series(orc_chain* c, orc_obs* out, int64_t max_rows);
+int  orc_flags(const orc_chain* c);              /* sticky error flags  */
+
+/* canonical state */
+int64_t orc_state_events(const orc_chain* c);
+int  orc_get_state(const orc_chain* c, uint8_t* bstate, int32_t* counts,
+                   int32_t* ticks, uint32_t* infos, int64_t cap,
+                   uint64_t* sweep);
+int  orc_set_state(orc_chain* c, const uint8_t* bstate, const int32_t* counts,
+                   const int32_t* ticks, const uint32_t* infos, int64_t n_events,
+                   uint64_t sweep);
+int  orc_check(const orc_chain* c);            /* worldline invariants */
+
+/* derived quantities and tables (for pins) */
+typedef struct orc_derived {
+    double C, rho_max, lambda, delta;
+    double wd[4];            /* diagonal weight, index sa | sc<<1         */
+    double acc[4];           /* wd / rho_max                              */
+    int32_t n_cycle, M, ntau;
+    int32_t T[65];
+} orc_derived;
+int  orc_get_derived(const orc_chain* c, orc_derived* d);
+int  orc_get_scatter_table(const orc_chain* c, double* tab /*16*4*4*/,
+                           double* pair /*16*4*4 pair weights W[S0][i][j]*/);
+double orc_vertex_weight(const orc_chain* c, int S);
+double orc_fleg(const orc_chain* c, int sigma, int64_t ell);
+double orc_tanh_ell(const orc_chain* c, int64_t ell);
+int  orc_poisson_table(const orc_chain* c, int k, double* cdf, int cap);
+
+/* samplers driven by a Philox stream (phase, unit) of the current sweep */
+int  orc_test_worms(orc_chain* c, uint32_t phase, uint32_t unit, int32_t ell,
+                    int sigma, int32_t* offsets, uint8_t* dirs, int cap);
+int  orc_test_choose(const double* w, int n, double u);
+double orc_test_temporal_p0(const orc_chain* c, int p, int q, int64_t l1,
+                            int64_t l2);
+
+/* Philox4x32-10 block */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+uint64_t orc_stream_word(const orc_chain* c, uint32_t phase, uint32_t unit,
+                         uint64_t word_index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
