@@ -91,11 +91,11 @@ typedef struct pmwa_obs {
 } pmwa_obs;
 
 /* Derived constants of one chain. */
-typedef struct pmwa_chain_info {
+typedef struct pmwa_info {
     double  C, rho_max, delta, lambda;    /* Delta = beta/M, lambda = eta Delta */
     int32_t n_cycle, M, event_cap, bond_cap;
     int64_t n_domains;
-} pmwa_chain_info;
+} pmwa_info;
 
 typedef struct pmwa_handle pmwa_t;
 
@@ -142,7 +142,7 @@ int pmwa_set_state(pmwa_t* h, int chain, const uint8_t* bstate,
                    const int32_t* counts, const int32_t* ticks,
                    const uint32_t* infos, int64_t n_events, uint64_t sweep);
 
-int pmwa_chain_info(pmwa_t* h, int chain, pmwa_chain_info* out);
+int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out);
 
 /* Events per (site, slab) a chain would be given by default. */
 int pmwa_default_event_cap(const pmwa_params* p);

@@ -1,0 +1,269 @@
+// pmwa_device.h -- device-side data layout and helpers of the gfx950 PMWA
+// sweep (Masaki-Kato et al., arXiv:1307.0328).
+//
+// Layout in device memory, per chain (all offsets are into shared pools):
+//   site-slab unit  u = (k * ndsp + dsp) * nloc + sl      (k temporal slab,
+//                   dsp spatial domain, sl site inside the domain, row-major)
+//   events          ev[ev_off + ((k*ndsp + dsp) * cap + j) * nloc + sl]
+//                   j-th event of the site in slab k, stored {tick, info};
+//                   consecutive sites of a domain are consecutive in memory,
+//                   so lane-per-site kernels read coalesced rows.
+//   counts          cnt[cnt_off + u]
+//   boundary state  bs[bs_off + u]       occupation just above T_k
+//   bond buffer     bv[bv_off + (((k*2 + d)*ndsp + dsp) * capb + j) * nloc + sl]
+//                   new diagonal vertices of bond (site, +d) in slab k:
+//                   tick | s_a << 30 | s_c << 31
+//   event info      bit0 worm; bit3 occupation just above; vertex bits1-2 =
+//                   bond direction seen from this site (0 +x, 1 +y, 2 -x,
+//                   3 -y); worm bit1 = moving up.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pmwa.h"
+
+#define PMWA_DEV __device__ __forceinline__
+
+namespace pmwa {
+
+constexpr int NT_MAX = 64;      // temporal domains
+constexpr int KMAXC = 256;      // Poisson table entries = max candidates per bond-slab
+constexpr int NWL = 48;         // worms drawn on one interval
+constexpr int KINKMAX = 128;    // kinks kept per (site, slab)
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+
+// stream kinds in Philox counter word 3 (low byte)
+enum : uint32_t { RNG_V = 1, RNG_R = 2, RNG_S = 3, RNG_BT = 4, RNG_BS = 5 };
+// sticky per-chain error flags
+enum : uint32_t { FL_OVERFLOW = 1, FL_SAMPLER = 2, FL_STATE = 4 };
+// node flags of the scattering phase (bits 0-3 equal the event info bits)
+enum : uint32_t { F_WORM = 1, F_DIRUP = 2, F_UP = 8, F_SBOT = 16, F_STOP = 32, F_CROSS = 64 };
+
+struct ChainDev {
+    int32_t Lx, Ly, N, ntau, ex, ey, nloc, dom_x, dom_y, ndsp;
+    int32_t M, ncycle, cap, capb, cdf_stride, scr_nodes;
+    uint32_t chain_id, key0, key1, n_dom;
+    double lambda, t;
+    int64_t ev_off, cnt_off, bs_off, bv_off, bvc_off, dom_off, ser_off, cdf_off;
+    int64_t scr_off;   // node scratch of the HBM scattering path (nodes)
+    int32_t T[NT_MAX + 1];
+    int32_t pad_;
+    double E[32];      // expm1(lambda * 2^k)
+    double acc[4];     // w_d / rho_max, index s_a | s_c << 1
+    double vw[16];     // vertex weight by root pattern
+    double scat[256];  // cumulative exit table [S0][entry][exit]
+};
+
+struct DomPart {
+    long long nv, nkink, nw, occ2;
+    double qimp;
+    long long pad_;
+};
+
+struct Pools {
+    const ChainDev* cd;
+    uint2* ev;
+    int32_t* cnt;
+    uint8_t* bs;
+    uint32_t* bv;
+    int32_t* bvc;
+    DomPart* dpart;
+    pmwa_obs* ser;
+    const double* cdf;
+    unsigned long long* sweep;   // per chain
+    unsigned int* flags;         // per chain
+    unsigned long long* nnacc;   // per chain
+    // scattering-phase node scratch in HBM
+    int32_t* s_tick;
+    uint32_t* s_nxt;
+    uint32_t* s_prv;
+    uint32_t* s_aux;
+    uint8_t* s_fl;
+    uint32_t* s_wl;
+    int32_t series_cap;
+    int32_t lds_nodes;           // node capacity of the LDS path (0 = off)
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+PMWA_DEV void philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                       uint32_t k0, uint32_t k1, uint32_t o[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, x0), lo0 = 0xD2511F53u * x0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, x2), lo1 = 0xCD9E8D57u * x2;
+        uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+}
+
+// Word stream of one unit: word 2j = out1:out0, word 2j+1 = out3:out2 of the
+// block with counter (j, unit, sweep, chain_id << 8 | kind).
+struct Stream {
+    uint32_t k0, k1, c1, c2, c3, w, blk;
+    uint32_t o[4];
+    PMWA_DEV void init(const ChainDev& C, uint32_t sweep, uint32_t kind, uint32_t unit)
+    {
+        k0 = C.key0; k1 = C.key1; c1 = unit; c2 = sweep; c3 = (C.chain_id << 8) | kind;
+        w = 0; blk = 0;
+    }
+    PMWA_DEV uint64_t next()
+    {
+        uint32_t j = w >> 1;
+        if (blk != j + 1) { philox10(j, c1, c2, c3, k0, k1, o); blk = j + 1; }
+        uint64_t r = (w & 1) ? (((uint64_t)o[3] << 32) | o[2]) : (((uint64_t)o[1] << 32) | o[0]);
+        w++;
+        return r;
+    }
+};
+
+PMWA_DEV double u53(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+PMWA_DEV uint64_t below(uint64_t w, uint64_t n) { return __umul64hi(w, n); }
+
+// ---------------------------------------------------------------------------
+// lattice
+// ---------------------------------------------------------------------------
+PMWA_DEV int nbr(const ChainDev& C, int site, int d)
+{
+    int x = site % C.Lx, y = site / C.Lx;
+    if (d == 0) x = (x + 1 == C.Lx) ? 0 : x + 1;
+    else if (d == 1) y = (y + 1 == C.Ly) ? 0 : y + 1;
+    else if (d == 2) x = (x == 0) ? C.Lx - 1 : x - 1;
+    else y = (y == 0) ? C.Ly - 1 : y - 1;
+    return y * C.Lx + x;
+}
+PMWA_DEV long long bond_id(const ChainDev& C, int site, int d)
+{
+    if (d < 2) return 2LL * site + d;
+    return 2LL * nbr(C, site, d) + (d - 2);
+}
+PMWA_DEV void site_split(const ChainDev& C, int site, int& dsp, int& sl)
+{
+    int x = site % C.Lx, y = site / C.Lx;
+    dsp = (y / C.ey) * C.dom_x + x / C.ex;
+    sl = (y % C.ey) * C.ex + x % C.ex;
+}
+PMWA_DEV int site_join(const ChainDev& C, int dsp, int sl)
+{
+    int dy = dsp / C.dom_x, dx = dsp - dy * C.dom_x;
+    int ly = sl / C.ex, lx = sl - ly * C.ex;
+    return (dy * C.ey + ly) * C.Lx + dx * C.ex + lx;
+}
+PMWA_DEV long long unit_su(const ChainDev& C, int k, int dsp, int sl)
+{
+    return (long long)(k * C.ndsp + dsp) * C.nloc + sl;
+}
+PMWA_DEV long long ev_base(const ChainDev& C, int k, int dsp, int sl)
+{
+    return C.ev_off + (long long)(k * C.ndsp + dsp) * C.cap * C.nloc + sl;
+}
+
+// ---------------------------------------------------------------------------
+// element functions of the worm law (hard-core f_qp), from the expm1 table
+// ---------------------------------------------------------------------------
+PMWA_DEV double em1(const ChainDev& C, long long ell)
+{
+    double m = 0.0;
+    for (int k = 0; k < 32; k++) {
+        if ((ell >> k) & 1) {
+            double t = C.E[k];
+            m = (m + t) + m * t;
+        }
+    }
+    return m;
+}
+PMWA_DEV double fleg(const ChainDev& C, int sigma, long long ell)
+{
+    double m = em1(C, ell);
+    double d = 2.0 * (1.0 + m);
+    if (sigma) return (m * (2.0 + m)) / d;
+    return 1.0 + (m * m) / d;
+}
+PMWA_DEV double tanh_ell(const ChainDev& C, long long ell)
+{
+    double m = em1(C, ell);
+    double d = 2.0 * (1.0 + m);
+    return (m * (2.0 + m)) / (d + m * m);
+}
+
+// heat-bath choice: first m with W_m > 0 and u*sum < cumulative, else the
+// last m with W_m > 0
+template <int N>
+PMWA_DEV int choose(const double (&W)[N], double u)
+{
+    double tot = 0.0;
+    for (int m = 0; m < N; m++) tot = tot + W[m];
+    double r = u * tot, cum = 0.0;
+    int last = -1, pick = -1;
+    for (int m = 0; m < N; m++) {
+        cum = cum + W[m];
+        if (W[m] > 0.0) {
+            last = m;
+            if (pick < 0 && r < cum) pick = m;
+        }
+    }
+    return pick >= 0 ? pick : last;
+}
+
+// Worms of one interval with `ell` free slots and end-state parity sigma:
+// count by inversion of x^n/n!/f_sigma(x), x = lambda*ell, n <= ell (redraw
+// otherwise); distinct uniform offsets in [0, ell), sorted; one direction
+// bit per worm in ascending order.  Returns n, or -1 on failure (flagged).
+PMWA_DEV int sample_worms(const ChainDev& C, Stream& s, long long ell, int sigma,
+                          int32_t* off, uint8_t* dirs, unsigned int* flag)
+{
+    if (ell == 0) {
+        if (sigma) atomicOr(flag, FL_SAMPLER);
+        return 0;
+    }
+    double f = fleg(C, sigma, ell);
+    double x = C.lambda * (double)ell;
+    double xx = x * x;
+    long long nmax = ell < 4096 ? ell : 4096;
+    int n = -1;
+    for (int tries = 0; tries < 1000; tries++) {
+        double U = u53(s.next()) * f;
+        long long k = sigma;
+        double T = sigma ? x : 1.0;
+        double S = T;
+        while (!(U < S) && k + 2 <= nmax) {
+            T = (T * xx) / (double)((k + 1) * (k + 2));
+            k += 2;
+            S = S + T;
+        }
+        if (U < S && k <= nmax) { n = (int)k; break; }
+    }
+    if (n < 0 || n > NWL) { atomicOr(flag, FL_SAMPLER); return -1; }
+    for (int i = 0; i < n; i++) {
+        int32_t r;
+        bool again;
+        int guard = 0;
+        do {
+            r = (int32_t)below(s.next(), (uint64_t)ell);
+            again = false;
+            for (int j = 0; j < i; j++) again |= (off[j] == r);
+        } while (again && ++guard < 100000);
+        if (again) { atomicOr(flag, FL_SAMPLER); return -1; }
+        off[i] = r;
+    }
+    for (int a = 1; a < n; a++) {
+        int32_t v = off[a];
+        int b = a - 1;
+        while (b >= 0 && off[b] > v) { off[b + 1] = off[b]; b--; }
+        off[b + 1] = v;
+    }
+    for (int i = 0; i < n; i++) dirs[i] = (uint8_t)(s.next() >> 63);
+    return n;
+}
+
+// event encoding
+PMWA_DEV uint32_t ev_worm(uint32_t info) { return info & 1u; }
+PMWA_DEV uint32_t ev_dir(uint32_t info) { return (info >> 1) & 3u; }
+PMWA_DEV uint32_t ev_up(uint32_t info) { return (info >> 3) & 1u; }
+PMWA_DEV long long pos2(uint2 e) { return 2LL * (int)e.x + (long long)(e.y & 1u); }
+
+}  // namespace pmwa

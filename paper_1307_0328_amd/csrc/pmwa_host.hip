@@ -1,0 +1,703 @@
+// pmwa_host.hip -- C ABI of the gfx950 PMWA sweep (see include/pmwa.h).
+//
+// Host tables follow the paper's definitions with a fixed floating-point
+// operation order (no contraction), so that every Monte Carlo decision is
+// reproducible bit for bit by any implementation that uses the same order:
+//   Delta = beta / M, lambda = eta * Delta, E[k] = expm1(lambda * 2^k);
+//   E_b(sa,sc) = V*(sa&sc) - (mu*0.25)*(sa+sc); C = max E_b + t/2 (t > 0) or
+//   + 1/2; w_d = C - E_b; acc = w_d / rho_max;
+//   Poisson candidate counts per slab (inversion table, tail folded into a
+//   final 2.0 entry); directed-loop pair weights w_ij = w_ji with row sums
+//   w_i (minimal bounce), cumulative exit probabilities w_ji / w_i.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "pmwa_device.h"
+
+namespace pmwa {
+__global__ void k_vertex(Pools P, const int2* __restrict__ blk);
+__global__ void k_assemble(Pools P, const int2* __restrict__ blk);
+__global__ void k_scatter(Pools P, const int2* __restrict__ blk);
+__global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
+__global__ void k_bspatial(Pools P, const int2* __restrict__ blk, int d);
+__global__ void k_finish(Pools P);
+}  // namespace pmwa
+
+using namespace pmwa;
+
+namespace {
+
+constexpr int KMAX_TABLE = 1024;   // length bound of the Poisson table construction
+
+struct HostChain {
+    pmwa_params p;
+    ChainDev d;
+    std::vector<double> cdf;        // ntau * cdf_stride
+    double C, rho_max, delta;
+    int64_t n_units_v, n_units_r, n_dom, n_bt, n_bsx, n_bsy;
+    uint64_t enq_sweeps = 0, read_sweeps = 0;
+    std::vector<pmwa_obs> host_rows;   // drained, not yet returned
+};
+
+template <typename T>
+T* dalloc(size_t n, int* rc)
+{
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) { *rc = PMWA_ENOMEM; return nullptr; }
+    return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct pmwa_handle {
+    hipStream_t stream = nullptr;
+    pmwa_opts opts{};
+    std::vector<HostChain> ch;
+    Pools P{};
+    ChainDev* d_cd = nullptr;
+    double* d_cdf = nullptr;
+    int2 *d_blk_v = nullptr, *d_blk_r = nullptr, *d_blk_s = nullptr, *d_blk_bt = nullptr,
+         *d_blk_bsx = nullptr, *d_blk_bsy = nullptr;
+    int nblk_v = 0, nblk_r = 0, nblk_s = 0, nblk_bt = 0, nblk_bsx = 0, nblk_bsy = 0;
+    size_t lds_bytes = 0;
+    int64_t ev_total = 0, site_slabs = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool own_stream = false;
+};
+
+// ---------------------------------------------------------------------------
+// tables
+// ---------------------------------------------------------------------------
+static double vertex_weight(const double wd[4], double t, int S)
+{
+    if ((S & 3) == (S >> 2)) return wd[S & 3];
+    if (S == 9 || S == 6) return t;
+    return 0.0;
+}
+
+// w_ij = w_ji, sum_j w_ij = w_i over the allowed exits, fewest bounces
+static void pair_weights(const double w[4], double W[4][4])
+{
+    std::memset(W, 0, sizeof(double) * 16);
+    int idx[4], n = 0;
+    for (int j = 0; j < 4; j++)
+        if (w[j] > 0.0) idx[n++] = j;
+    for (int a = 1; a < n; a++) {   // stable, descending weight
+        int v = idx[a], b = a - 1;
+        while (b >= 0 && w[idx[b]] < w[v]) { idx[b + 1] = idx[b]; b--; }
+        idx[b + 1] = v;
+    }
+    if (n == 0) return;
+    if (n == 1) { W[idx[0]][idx[0]] = w[idx[0]]; return; }
+    const int ja = idx[0], jb = idx[1], jc = n == 3 ? idx[2] : -1;
+    const double a = w[ja], b = w[jb], c = n == 3 ? w[jc] : 0.0;
+    if (a <= b + c) {
+        W[ja][jb] = W[jb][ja] = ((a + b) - c) * 0.5;
+        if (jc >= 0) {
+            W[ja][jc] = W[jc][ja] = ((a + c) - b) * 0.5;
+            W[jb][jc] = W[jc][jb] = ((b + c) - a) * 0.5;
+        }
+    } else {
+        W[ja][ja] = (a - b) - c;
+        W[ja][jb] = W[jb][ja] = b;
+        if (jc >= 0) W[ja][jc] = W[jc][ja] = c;
+    }
+}
+
+static int validate(const pmwa_params& p)
+{
+    if (p.Lx < 3 || p.Ly < 3) return 0;
+    if (!(p.beta > 0.0) || !(p.eta > 0.0) || !(p.t >= 0.0)) return 0;
+    if (!std::isfinite(p.V) || !std::isfinite(p.mu) || !std::isfinite(p.beta) || !std::isfinite(p.t)) return 0;
+    if (p.dom_x < 1 || p.dom_y < 1 || p.dom_tau < 1 || p.dom_tau > NT_MAX) return 0;
+    if (p.Lx % p.dom_x || p.Ly % p.dom_y) return 0;
+    if (p.Lx / p.dom_x < 2 || p.Ly / p.dom_y < 2) return 0;
+    if (p.ticks_log2 < 8 || p.ticks_log2 > 30) return 0;
+    if ((int64_t(1) << p.ticks_log2) / p.dom_tau < 2) return 0;
+    if (p.chain_id >= (1u << 24)) return 0;
+    if ((int64_t)p.Lx * p.Ly >= (int64_t(1) << 28)) return 0;
+    if (p.eta * p.beta > 8.0) return 0;     // worms per interval fit the sampler
+    return 1;
+}
+
+// mean events per (site, slab): four bonds, each with at most rho_max
+// diagonal vertices per unit time plus kinks (~ t), and worms
+static double mean_events(const pmwa_params& p, double rho_max)
+{
+    const double dbeta = p.beta / p.dom_tau;
+    return 4.0 * (rho_max + p.t) * dbeta + 2.0 * p.eta * dbeta + 1.0;
+}
+
+extern "C" int pmwa_default_event_cap(const pmwa_params* p)
+{
+    if (!p || !validate(*p)) return PMWA_EINVAL;
+    double Eb[4], Emax = 0.0;
+    for (int s = 0; s < 4; s++) {
+        const int sa = s & 1, sc = s >> 1;
+        Eb[s] = p->V * (double)(sa & sc) - (p->mu * 0.25) * (double)(sa + sc);
+        if (s == 0 || Eb[s] > Emax) Emax = Eb[s];
+    }
+    const double C = std::isnan(p->C) ? Emax + (p->t > 0.0 ? 0.5 * p->t : 0.5) : p->C;
+    double rho = 0.0;
+    for (int s = 0; s < 4; s++) rho = (s == 0 || C - Eb[s] > rho) ? C - Eb[s] : rho;
+    const double m = mean_events(*p, rho);
+    int cap = (int)std::ceil(m + 10.0 * std::sqrt(m) + 32.0);
+    return (cap + 7) & ~7;
+}
+
+static int build_chain(const pmwa_params& p, uint32_t cap_override, HostChain& hc)
+{
+    if (!validate(p)) return PMWA_EINVAL;
+    hc.p = p;
+    ChainDev& d = hc.d;
+    std::memset(&d, 0, sizeof(d));
+    d.Lx = p.Lx; d.Ly = p.Ly; d.N = p.Lx * p.Ly; d.ntau = p.dom_tau;
+    d.ex = p.Lx / p.dom_x; d.ey = p.Ly / p.dom_y; d.nloc = d.ex * d.ey;
+    d.dom_x = p.dom_x; d.dom_y = p.dom_y; d.ndsp = p.dom_x * p.dom_y;
+    d.M = 1 << p.ticks_log2;
+    d.chain_id = p.chain_id;
+    d.key0 = (uint32_t)p.seed; d.key1 = (uint32_t)(p.seed >> 32);
+    hc.delta = p.beta / (double)d.M;
+    d.lambda = p.eta * hc.delta;
+    d.t = p.t;
+    for (int k = 0; k < 32; k++) d.E[k] = std::expm1(d.lambda * std::ldexp(1.0, k));
+
+    double Eb[4], Emax = 0.0;
+    for (int s = 0; s < 4; s++) {
+        const int sa = s & 1, sc = s >> 1;
+        Eb[s] = p.V * (double)(sa & sc) - (p.mu * 0.25) * (double)(sa + sc);
+        if (s == 0 || Eb[s] > Emax) Emax = Eb[s];
+    }
+    hc.C = std::isnan(p.C) ? Emax + (p.t > 0.0 ? 0.5 * p.t : 0.5) : p.C;
+    double wd[4];
+    hc.rho_max = 0.0;
+    for (int s = 0; s < 4; s++) {
+        wd[s] = hc.C - Eb[s];
+        if (!(wd[s] > 0.0)) return PMWA_EINVAL;
+        if (s == 0 || wd[s] > hc.rho_max) hc.rho_max = wd[s];
+    }
+    for (int s = 0; s < 4; s++) d.acc[s] = wd[s] / hc.rho_max;
+    for (int S = 0; S < 16; S++) d.vw[S] = vertex_weight(wd, p.t, S);
+    for (int k = 0; k <= d.ntau; k++) d.T[k] = (int32_t)(((int64_t)k * (int64_t)d.M) / d.ntau);
+
+    // Poisson(rho_max * Delta * dT_k) CDF of candidate counts
+    std::vector<std::vector<double>> tabs(d.ntau);
+    int stride = 0;
+    for (int k = 0; k < d.ntau; k++) {
+        const double mu = hc.rho_max * (hc.delta * (double)(d.T[k + 1] - d.T[k]));
+        if (!(mu < 500.0)) return PMWA_EINVAL;
+        std::vector<double>& t = tabs[k];
+        double pj = std::exp(-mu), cum = pj;
+        t.push_back(cum);
+        int j = 0;
+        for (;;) {
+            j++;
+            pj = (pj * mu) / (double)j;
+            if ((double)j > mu && pj < 0x1.0p-64) break;
+            if (j >= KMAX_TABLE - 1) break;
+            cum = cum + pj;
+            t.push_back(cum);
+        }
+        t.push_back(2.0);
+        if ((int)t.size() > KMAXC) return PMWA_EINVAL;
+        stride = std::max(stride, (int)t.size());
+    }
+    d.cdf_stride = stride;
+    d.capb = stride;
+    hc.cdf.assign((size_t)d.ntau * stride, 2.0);
+    for (int k = 0; k < d.ntau; k++)
+        std::copy(tabs[k].begin(), tabs[k].end(), hc.cdf.begin() + (size_t)k * stride);
+
+    // scattering exits
+    for (int S0 = 0; S0 < 16; S0++) {
+        double w[4];
+        for (int j = 0; j < 4; j++) w[j] = vertex_weight(wd, p.t, S0 ^ (1 << j));
+        double W[4][4];
+        pair_weights(w, W);
+        for (int i = 0; i < 4; i++) {
+            double* row = &d.scat[S0 * 16 + i * 4];
+            if (!(w[i] > 0.0)) { for (int j = 0; j < 4; j++) row[j] = 2.0; continue; }
+            int jlast = 0;
+            for (int j = 0; j < 4; j++) if (W[j][i] > 0.0) jlast = j;
+            double cum = 0.0;
+            for (int j = 0; j < 4; j++) {
+                cum = cum + W[j][i] / w[i];
+                row[j] = (j >= jlast) ? 2.0 : cum;
+            }
+        }
+    }
+    const long long nc = p.n_cycle > 0 ? p.n_cycle : (long long)std::ceil(4.0 * hc.C / p.eta);
+    if (nc < 1 || nc > 10000000) return PMWA_EINVAL;
+    d.ncycle = (int32_t)nc;
+
+    d.cap = cap_override ? (int)cap_override : pmwa_default_event_cap(&p);
+    if (d.cap < 4 || (int64_t)d.nloc * (d.cap + 2) >= (int64_t)0x7FFFFFFF) return PMWA_EINVAL;
+    hc.n_units_v = 2LL * d.ntau * d.N;
+    hc.n_units_r = (int64_t)d.ntau * d.N;
+    hc.n_dom = (int64_t)d.ntau * d.ndsp;
+    d.n_dom = (uint32_t)hc.n_dom;
+    hc.n_bt = d.N;
+    hc.n_bsx = p.dom_x > 1 ? (int64_t)p.Ly * p.dom_x : 0;
+    hc.n_bsy = p.dom_y > 1 ? (int64_t)p.Lx * p.dom_y : 0;
+    return PMWA_OK;
+}
+
+static void block_table(const std::vector<HostChain>& ch, int per_block, int64_t HostChain::*units,
+                        std::vector<int2>& out)
+{
+    out.clear();
+    for (size_t c = 0; c < ch.size(); c++) {
+        const int64_t n = ch[c].*units;
+        for (int64_t b = 0; b < n; b += per_block) out.push_back(make_int2((int)c, (int)b));
+    }
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return PMWA_EDEVICE; \
+    } while (0)
+
+static int upload_table(const std::vector<int2>& t, int2** dst, int* n)
+{
+    *n = (int)t.size();
+    if (t.empty()) { *dst = nullptr; return PMWA_OK; }
+    if (hipMalloc(dst, t.size() * sizeof(int2)) != hipSuccess) return PMWA_ENOMEM;
+    HIPCHK(hipMemcpy(*dst, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice));
+    return PMWA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+static int launch_phase(pmwa_t* h, int phase)
+{
+    hipStream_t s = h->stream;
+    switch (phase) {
+    case 1:
+        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(256), 0, s, h->P, h->d_blk_v);
+        break;
+    case 2:
+        if (h->nblk_r) hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(256), 0, s, h->P, h->d_blk_r);
+        break;
+    case 3:
+        if (h->nblk_s) hipLaunchKernelGGL(k_scatter, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
+        break;
+    case 4:
+        if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(128), 0, s, h->P, h->d_blk_bt);
+        break;
+    case 5:
+        if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(128), 0, s, h->P, h->d_blk_bsx, 0);
+        break;
+    case 6:
+        if (h->nblk_bsy) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsy), dim3(128), 0, s, h->P, h->d_blk_bsy, 1);
+        break;
+    case 7:
+        hipLaunchKernelGGL(k_finish, dim3((unsigned)h->ch.size()), dim3(256), 0, s, h->P);
+        break;
+    default:
+        return PMWA_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? PMWA_OK : PMWA_EDEVICE;
+}
+
+static int drain(pmwa_t* h)
+{
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int cap = h->opts.series_cap;
+    for (size_t c = 0; c < h->ch.size(); c++) {
+        HostChain& hc = h->ch[c];
+        while (hc.read_sweeps < hc.enq_sweeps) {
+            const uint64_t slot = hc.read_sweeps % (uint64_t)cap;
+            const uint64_t n = std::min<uint64_t>(hc.enq_sweeps - hc.read_sweeps, (uint64_t)cap - slot);
+            const size_t o = hc.host_rows.size();
+            hc.host_rows.resize(o + n);
+            HIPCHK(hipMemcpy(hc.host_rows.data() + o, h->P.ser + hc.d.ser_off + slot,
+                             n * sizeof(pmwa_obs), hipMemcpyDeviceToHost));
+            hc.read_sweeps += n;
+        }
+    }
+    return PMWA_OK;
+}
+
+static int read_flags(pmwa_t* h, std::vector<unsigned int>& f)
+{
+    HIPCHK(hipStreamSynchronize(h->stream));
+    f.resize(h->ch.size());
+    HIPCHK(hipMemcpy(f.data(), h->P.flags, f.size() * sizeof(unsigned int), hipMemcpyDeviceToHost));
+    return PMWA_OK;
+}
+
+static int flag_code(unsigned int f)
+{
+    if (f & FL_OVERFLOW) return PMWA_EOVERFLOW;
+    if (f) return PMWA_ESTATE;
+    return PMWA_OK;
+}
+
+extern "C" {
+
+const char* pmwa_strerror(int code)
+{
+    switch (code) {
+    case PMWA_OK: return "ok";
+    case PMWA_EINVAL: return "invalid argument";
+    case PMWA_ENOMEM: return "out of memory";
+    case PMWA_EDEVICE: return "HIP error";
+    case PMWA_EOVERFLOW: return "capacity overflow (chain state invalid)";
+    case PMWA_ESTATE: return "inconsistent state";
+    default: return "unknown error";
+    }
+}
+
+void pmwa_destroy(pmwa_t* h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
+                    h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
+                    h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->d_blk_v, h->d_blk_r,
+                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete h;
+}
+
+int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, pmwa_t** out)
+{
+    if (!out) return PMWA_EINVAL;
+    *out = nullptr;
+    if (!chains || n_chains < 1 || n_chains > (1 << 20)) return PMWA_EINVAL;
+    pmwa_t* h = new (std::nothrow) pmwa_handle();
+    if (!h) return PMWA_ENOMEM;
+    if (opts) h->opts = *opts;
+    if (h->opts.series_cap <= 0) h->opts.series_cap = 4096;
+    if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0) { delete h; return PMWA_EINVAL; }
+    h->stream = (hipStream_t)h->opts.stream;
+    if (!h->stream) {
+        // work goes to a stream of the handle (default priority)
+        if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return PMWA_EDEVICE; }
+        h->own_stream = true;
+    }
+    h->ch.resize(n_chains);
+    int rc = PMWA_OK;
+    int64_t ev = 0, su = 0, bv = 0, bvc = 0, dom = 0, cdf = 0, scr = 0;
+    int max_nloc = 1;
+    for (int c = 0; c < n_chains && rc == PMWA_OK; c++) {
+        HostChain& hc = h->ch[c];
+        rc = build_chain(chains[c], (uint32_t)h->opts.event_cap, hc);
+        if (rc) break;
+        ChainDev& d = hc.d;
+        d.ev_off = ev; ev += (int64_t)d.ntau * d.N * d.cap;
+        d.cnt_off = su; d.bs_off = su; su += (int64_t)d.ntau * d.N;
+        d.bv_off = bv; bv += 2LL * d.ntau * d.N * d.capb;
+        d.bvc_off = bvc; bvc += 2LL * d.ntau * d.N;
+        d.dom_off = dom; dom += hc.n_dom;
+        d.ser_off = (int64_t)c * h->opts.series_cap;
+        d.cdf_off = cdf; cdf += (int64_t)hc.cdf.size();
+        max_nloc = std::max(max_nloc, d.nloc);
+    }
+    if (rc) { pmwa_destroy(h); return rc; }
+
+    // LDS budget of the scattering kernel
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        pmwa_destroy(h);
+        return PMWA_EDEVICE;
+    }
+    size_t lds_max = prop.sharedMemPerBlock;
+    if (prop.maxSharedMemoryPerMultiProcessor > lds_max) lds_max = prop.maxSharedMemoryPerMultiProcessor;
+    if (lds_max > 160 * 1024) lds_max = 160 * 1024;
+    const size_t fixed = 256 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
+    const size_t fixed_al = (fixed + 15) & ~(size_t)15;
+    const size_t per_node = 5 * 4 + 1;
+    // nodes wanted: the largest expected domain with margin
+    double want = 0.0;
+    for (auto& hc : h->ch) {
+        const double m = mean_events(hc.p, hc.rho_max) * 0.75;
+        want = std::max(want, hc.d.nloc * (m * 1.3 + 2.0) + 64.0);
+    }
+    size_t lds_nodes = 0;
+    if (h->opts.scatter_mode != 2 && fixed_al + 64 * per_node < lds_max) {
+        lds_nodes = (lds_max - fixed_al) / per_node;
+        lds_nodes = std::min<size_t>(lds_nodes, (size_t)std::ceil(want));
+        lds_nodes &= ~(size_t)15;
+    }
+    h->P.lds_nodes = (int32_t)lds_nodes;
+    h->lds_bytes = fixed_al + lds_nodes * per_node + 16;
+    if (h->lds_bytes > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)h->lds_bytes);
+    // HBM node scratch for domains beyond the LDS capacity
+    for (auto& hc : h->ch) {
+        ChainDev& d = hc.d;
+        const double m = mean_events(hc.p, hc.rho_max);
+        int64_t nodes = (int64_t)std::ceil(d.nloc * (m + 4.0 * std::sqrt(m) + 8.0)) + 2 * d.nloc + 64;
+        nodes = std::min<int64_t>(nodes, (int64_t)d.nloc * (d.cap + 2));
+        d.scr_nodes = (int32_t)nodes;
+        d.scr_off = scr;
+        scr += nodes * hc.n_dom;
+    }
+
+    h->ev_total = ev;
+    h->site_slabs = su;
+    h->P.ev = dalloc<uint2>(ev, &rc);
+    h->P.cnt = dalloc<int32_t>(su, &rc);
+    h->P.bs = dalloc<uint8_t>(su, &rc);
+    h->P.bv = dalloc<uint32_t>(bv, &rc);
+    h->P.bvc = dalloc<int32_t>(bvc, &rc);
+    h->P.dpart = dalloc<DomPart>(dom, &rc);
+    h->P.ser = dalloc<pmwa_obs>((size_t)n_chains * h->opts.series_cap, &rc);
+    h->P.sweep = dalloc<unsigned long long>(n_chains, &rc);
+    h->P.flags = dalloc<unsigned int>(n_chains, &rc);
+    h->P.nnacc = dalloc<unsigned long long>(n_chains, &rc);
+    h->P.s_tick = dalloc<int32_t>(scr, &rc);
+    h->P.s_nxt = dalloc<uint32_t>(scr, &rc);
+    h->P.s_prv = dalloc<uint32_t>(scr, &rc);
+    h->P.s_aux = dalloc<uint32_t>(scr, &rc);
+    h->P.s_fl = dalloc<uint8_t>(scr, &rc);
+    h->P.s_wl = dalloc<uint32_t>(scr, &rc);
+    h->d_cd = dalloc<ChainDev>(n_chains, &rc);
+    h->d_cdf = dalloc<double>(cdf, &rc);
+    if (rc) { pmwa_destroy(h); return rc; }
+    h->P.cd = h->d_cd;
+    h->P.cdf = h->d_cdf;
+    h->P.series_cap = h->opts.series_cap;
+
+    std::vector<ChainDev> cds(n_chains);
+    std::vector<double> cdfs(std::max<int64_t>(cdf, 1));
+    for (int c = 0; c < n_chains; c++) {
+        cds[c] = h->ch[c].d;
+        std::copy(h->ch[c].cdf.begin(), h->ch[c].cdf.end(), cdfs.begin() + h->ch[c].d.cdf_off);
+    }
+    std::vector<int2> t;
+    int r2 = PMWA_OK;
+    if (hipMemcpy(h->d_cd, cds.data(), n_chains * sizeof(ChainDev), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_cdf, cdfs.data(), cdf * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        r2 = PMWA_EDEVICE;
+    if (!r2) { block_table(h->ch, 256, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
+    if (!r2) { block_table(h->ch, 256, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
+    if (!r2) { block_table(h->ch, 1, &HostChain::n_dom, t); r2 = upload_table(t, &h->d_blk_s, &h->nblk_s); }
+    if (!r2) { block_table(h->ch, 128, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
+    if (!r2) { block_table(h->ch, 128, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
+    if (!r2) { block_table(h->ch, 128, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
+    if (r2) { pmwa_destroy(h); return r2; }
+    // the empty configuration
+    if (hipMemsetAsync(h->P.cnt, 0, su * sizeof(int32_t), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.bs, 0, su, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.sweep, 0, n_chains * sizeof(unsigned long long), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.flags, 0, n_chains * sizeof(unsigned int), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.nnacc, 0, n_chains * sizeof(unsigned long long), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.bvc, 0, std::max<int64_t>(bvc, 1) * sizeof(int32_t), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.dpart, 0, std::max<int64_t>(dom, 1) * sizeof(DomPart), h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        pmwa_destroy(h);
+        return PMWA_EDEVICE;
+    }
+    *out = h;
+    return PMWA_OK;
+}
+
+int pmwa_phase(pmwa_t* h, int phase)
+{
+    if (!h || phase < 1 || phase > 7) return PMWA_EINVAL;
+    if (phase == 7) {
+        for (auto& hc : h->ch)
+            if (hc.enq_sweeps - hc.read_sweeps >= (uint64_t)h->opts.series_cap) {
+                int rc = drain(h);
+                if (rc) return rc;
+                break;
+            }
+    }
+    int rc = launch_phase(h, phase);
+    if (rc == PMWA_OK && phase == 7)
+        for (auto& hc : h->ch) hc.enq_sweeps++;
+    return rc;
+}
+
+static int build_graph(pmwa_t* h)
+{
+    hipStream_t s = h->stream;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = PMWA_OK;
+    for (int ph = 1; ph <= 7 && rc == PMWA_OK; ph++) rc = launch_phase(h, ph);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return PMWA_EDEVICE;
+    }
+    h->graph = g;
+    HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    return PMWA_OK;
+}
+
+int pmwa_sweep(pmwa_t* h, int64_t n)
+{
+    if (!h || n < 0) return PMWA_EINVAL;
+    const bool graph = h->opts.use_graph != 0;
+    if (graph && !h->gexec) {
+        int rc = build_graph(h);
+        if (rc) return rc;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        for (auto& hc : h->ch)
+            if (hc.enq_sweeps - hc.read_sweeps >= (uint64_t)h->opts.series_cap) {
+                int rc = drain(h);
+                if (rc) return rc;
+                break;
+            }
+        if (graph) {
+            HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+        } else {
+            for (int ph = 1; ph <= 7; ph++) {
+                int rc = launch_phase(h, ph);
+                if (rc) return rc;
+            }
+        }
+        for (auto& hc : h->ch) hc.enq_sweeps++;
+    }
+    return PMWA_OK;
+}
+
+int pmwa_status(pmwa_t* h)
+{
+    if (!h) return PMWA_EINVAL;
+    std::vector<unsigned int> f;
+    int rc = read_flags(h, f);
+    if (rc) return rc;
+    for (unsigned int x : f)
+        if (x) return flag_code(x);
+    return PMWA_OK;
+}
+
+int pmwa_measure(pmwa_t* h, int chain, pmwa_obs* out, int64_t max_rows, int64_t* n_rows)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size() || !n_rows || max_rows < 0 || (!out && max_rows)) return PMWA_EINVAL;
+    int rc = drain(h);
+    if (rc) return rc;
+    HostChain& hc = h->ch[chain];
+    const int64_t n = std::min<int64_t>(max_rows, (int64_t)hc.host_rows.size());
+    if (n > 0) std::memcpy(out, hc.host_rows.data(), n * sizeof(pmwa_obs));
+    hc.host_rows.erase(hc.host_rows.begin(), hc.host_rows.begin() + n);
+    *n_rows = n;
+    std::vector<unsigned int> f;
+    rc = read_flags(h, f);
+    if (rc) return rc;
+    return flag_code(f[chain]);
+}
+
+int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out)
+{
+    if (!h || !out || chain < 0 || chain >= (int)h->ch.size()) return PMWA_EINVAL;
+    const HostChain& hc = h->ch[chain];
+    out->C = hc.C;
+    out->rho_max = hc.rho_max;
+    out->delta = hc.delta;
+    out->lambda = hc.d.lambda;
+    out->n_cycle = hc.d.ncycle;
+    out->M = hc.d.M;
+    out->event_cap = hc.d.cap;
+    out->bond_cap = hc.d.capb;
+    out->n_domains = hc.n_dom;
+    return PMWA_OK;
+}
+
+// canonical layout <-> device layout
+int pmwa_get_state(pmwa_t* h, int chain, uint8_t* bstate, int32_t* counts, int32_t* ticks,
+                   uint32_t* infos, int64_t cap, int64_t* n_events, uint64_t* sweep)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size() || !n_events) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const ChainDev& d = h->ch[chain].d;
+    const int64_t su = (int64_t)d.ntau * d.N;
+    std::vector<int32_t> cnt(su);
+    std::vector<uint8_t> bs(su);
+    std::vector<uint2> ev((size_t)su * d.cap);
+    HIPCHK(hipMemcpy(cnt.data(), h->P.cnt + d.cnt_off, su * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(bs.data(), h->P.bs + d.bs_off, su, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ev.data(), h->P.ev + d.ev_off, ev.size() * sizeof(uint2), hipMemcpyDeviceToHost));
+    unsigned long long sw = 0;
+    HIPCHK(hipMemcpy(&sw, h->P.sweep + chain, sizeof(sw), hipMemcpyDeviceToHost));
+    int64_t total = 0;
+    for (int64_t i = 0; i < su; i++) total += cnt[i];
+    *n_events = total;
+    if (sweep) *sweep = sw;
+    if (cap == 0) return PMWA_OK;
+    if (cap < total || !bstate || !counts || !ticks || !infos) return PMWA_EINVAL;
+    int64_t o = 0;
+    for (int k = 0; k < d.ntau; k++)
+        for (int site = 0; site < d.N; site++) {
+            const int x = site % d.Lx, y = site / d.Lx;
+            const int dsp = (y / d.ey) * d.dom_x + x / d.ex, sl = (y % d.ey) * d.ex + x % d.ex;
+            const int64_t u = (int64_t)(k * d.ndsp + dsp) * d.nloc + sl;
+            bstate[(int64_t)k * d.N + site] = bs[u];
+            counts[(int64_t)k * d.N + site] = cnt[u];
+            for (int j = 0; j < cnt[u]; j++) {
+                const uint2 e = ev[((int64_t)(k * d.ndsp + dsp) * d.cap + j) * d.nloc + sl];
+                ticks[o] = (int32_t)e.x;
+                infos[o] = e.y;
+                o++;
+            }
+        }
+    return PMWA_OK;
+}
+
+int pmwa_set_state(pmwa_t* h, int chain, const uint8_t* bstate, const int32_t* counts,
+                   const int32_t* ticks, const uint32_t* infos, int64_t n_events, uint64_t sweep)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size() || !bstate || !counts || n_events < 0) return PMWA_EINVAL;
+    if (n_events > 0 && (!ticks || !infos)) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const ChainDev& d = h->ch[chain].d;
+    const int64_t su = (int64_t)d.ntau * d.N;
+    std::vector<int32_t> cnt(su);
+    std::vector<uint8_t> bs(su);
+    std::vector<uint2> ev((size_t)su * d.cap, make_uint2(0, 0));
+    int64_t o = 0;
+    for (int k = 0; k < d.ntau; k++)
+        for (int site = 0; site < d.N; site++) {
+            const int x = site % d.Lx, y = site / d.Lx;
+            const int dsp = (y / d.ey) * d.dom_x + x / d.ex, sl = (y % d.ey) * d.ex + x % d.ex;
+            const int64_t u = (int64_t)(k * d.ndsp + dsp) * d.nloc + sl;
+            const int n = counts[(int64_t)k * d.N + site];
+            if (n < 0 || n > d.cap || o + n > n_events) return n > d.cap ? PMWA_EOVERFLOW : PMWA_EINVAL;
+            if (bstate[(int64_t)k * d.N + site] > 1) return PMWA_ESTATE;
+            bs[u] = bstate[(int64_t)k * d.N + site];
+            cnt[u] = n;
+            int64_t prevkey = -1;
+            for (int j = 0; j < n; j++, o++) {
+                const int32_t tk = ticks[o];
+                const uint32_t inf = infos[o];
+                if (tk < d.T[k] || tk >= d.T[k + 1] || (inf & ~15u) || ((inf & 1u) && (inf & 4u))) return PMWA_ESTATE;
+                const int64_t key = 2LL * tk + (inf & 1u);
+                if (key < prevkey) return PMWA_ESTATE;
+                prevkey = key;
+                ev[((int64_t)(k * d.ndsp + dsp) * d.cap + j) * d.nloc + sl] = make_uint2((uint32_t)tk, inf);
+            }
+        }
+    if (o != n_events) return PMWA_EINVAL;
+    HIPCHK(hipMemcpy(h->P.cnt + d.cnt_off, cnt.data(), su * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->P.bs + d.bs_off, bs.data(), su, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->P.ev + d.ev_off, ev.data(), ev.size() * sizeof(uint2), hipMemcpyHostToDevice));
+    const unsigned long long sw = sweep;
+    HIPCHK(hipMemcpy(h->P.sweep + chain, &sw, sizeof(sw), hipMemcpyHostToDevice));
+    const unsigned long long z = 0;
+    HIPCHK(hipMemcpy(h->P.nnacc + chain, &z, sizeof(z), hipMemcpyHostToDevice));
+    HostChain& hc = h->ch[chain];
+    hc.enq_sweeps = hc.read_sweeps = sweep;
+    hc.host_rows.clear();
+    return PMWA_OK;
+}
+
+}  // extern "C"

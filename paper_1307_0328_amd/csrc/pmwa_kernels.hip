@@ -1,0 +1,811 @@
+// pmwa_kernels.hip -- gfx950 kernels of one PMWA sweep (Masaki-Kato et al.,
+// arXiv:1307.0328): vertex phase (Step 3), worm re-generation (Step 4),
+// worm scattering with measurement (Steps 5-6, Supplemental S-I), temporal
+// (Step 1, Eq. (Para)) and spatial (Step 2, Eq. (ParaSpace)) boundary updates.
+//
+// Every kernel takes a block table {chain, first unit}: a block never spans
+// two chains, so one launch advances any mix of lattices.
+#include "pmwa_device.h"
+
+namespace pmwa {
+
+// ===========================================================================
+// Step 3: vertex phase.  One lane per (bond, slab): keep the kinks, draw a
+// Poisson(rho_max * Delta * dT_k) number of candidate ticks, and accept each
+// with w_d(state)/rho_max (thinning gives the density of the diagonal matrix
+// element).  Also integrates n_a n_c over the slab (before the update).
+// ===========================================================================
+PMWA_DEV bool key_before(const ChainDev& C, int site, uint2 e, int32_t tick, long long bid)
+{
+    int32_t et = (int32_t)e.x;
+    if (et != tick) return et < tick;
+    if (ev_worm(e.y)) return false;
+    return bond_id(C, site, (int)ev_dir(e.y)) < bid;
+}
+
+__global__ void __launch_bounds__(256) k_vertex(Pools P, const int2* __restrict__ blk)
+{
+    const int2 bt = blk[blockIdx.x];
+    const ChainDev& C = P.cd[bt.x];
+    const int u = bt.y + (int)threadIdx.x;
+    long long nn = 0;
+    if (u < 2 * C.ntau * C.N && P.flags[bt.x] == 0) {
+        const int sl = u % C.nloc;
+        int r = u / C.nloc;
+        const int dsp = r % C.ndsp;
+        r /= C.ndsp;
+        const int d = r & 1, k = r >> 1;
+        const int a = site_join(C, dsp, sl);
+        const int c = nbr(C, a, d);
+        int dspc, slc;
+        site_split(C, c, dspc, slc);
+        const long long bid = 2LL * a + d;
+        const uint32_t sweep = (uint32_t)P.sweep[bt.x];
+        const int na = P.cnt[C.cnt_off + unit_su(C, k, dsp, sl)];
+        const int nc = P.cnt[C.cnt_off + unit_su(C, k, dspc, slc)];
+        const int sa0 = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
+        const int sc0 = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
+        const uint2* Ea = P.ev + ev_base(C, k, dsp, sl);
+        const uint2* Ec = P.ev + ev_base(C, k, dspc, slc);
+        const int st = C.nloc;
+        const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
+
+        // integral of n_a n_c over the slab, half-tick units
+        {
+            int ia = 0, ic = 0, s_a = sa0, s_c = sc0;
+            long long last = 2LL * Tk;
+            uint2 ea = ia < na ? Ea[0] : make_uint2(0, 0);
+            uint2 ec = ic < nc ? Ec[0] : make_uint2(0, 0);
+            while (ia < na || ic < nc) {
+                bool takea = (ic >= nc) || (ia < na && pos2(ea) <= pos2(ec));
+                uint2 e = takea ? ea : ec;
+                long long p = pos2(e);
+                nn += (long long)(s_a & s_c) * (p - last);
+                last = p;
+                if (takea) { s_a = (int)ev_up(e.y); ia++; if (ia < na) ea = Ea[(long long)ia * st]; }
+                else { s_c = (int)ev_up(e.y); ic++; if (ic < nc) ec = Ec[(long long)ic * st]; }
+            }
+            nn += (long long)(s_a & s_c) * (2LL * Tk1 - last);
+        }
+
+        // kinks of this bond survive
+        int32_t kinks[KINKMAX];
+        int nk = 0;
+        {
+            int s = sa0;
+            for (int j = 0; j < na; j++) {
+                uint2 e = Ea[(long long)j * st];
+                int up = (int)ev_up(e.y);
+                if (!ev_worm(e.y) && (int)ev_dir(e.y) == d && up != s) {
+                    if (nk < KINKMAX) kinks[nk++] = (int32_t)e.x;
+                    else atomicOr(&P.flags[bt.x], FL_OVERFLOW);
+                }
+                s = up;
+            }
+        }
+
+        Stream rs;
+        rs.init(C, sweep, RNG_V, (uint32_t)(bid * C.ntau + k));
+        const double* cdf = P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
+        const double u0 = u53(rs.next());
+        int n = 0;
+        while (!(u0 < cdf[n])) n++;
+        int32_t cand[KMAXC];
+        const uint64_t dT = (uint64_t)(Tk1 - Tk);
+        for (int i = 0; i < n; i++) {
+            int32_t tau;
+            bool again;
+            int guard = 0;
+            do {
+                tau = Tk + (int32_t)below(rs.next(), dT);
+                again = false;
+                for (int j = 0; j < nk; j++) again |= (kinks[j] == tau);
+                for (int j = 0; j < i; j++) again |= (cand[j] == tau);
+            } while (again && ++guard < 100000);
+            if (again) { atomicOr(&P.flags[bt.x], FL_SAMPLER); n = i; break; }
+            cand[i] = tau;
+        }
+        for (int x = 1; x < n; x++) {
+            int32_t v = cand[x];
+            int y = x - 1;
+            while (y >= 0 && cand[y] > v) { cand[y + 1] = cand[y]; y--; }
+            cand[y + 1] = v;
+        }
+        // occupations seen at each candidate (sorted), then acceptance
+        uint32_t* out = P.bv + C.bv_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.capb * C.nloc + sl;
+        int ia = 0, ic = 0, s_a = sa0, s_c = sc0, nacc = 0;
+        for (int i = 0; i < n; i++) {
+            const int32_t tau = cand[i];
+            while (ia < na) {
+                uint2 e = Ea[(long long)ia * st];
+                if (!key_before(C, a, e, tau, bid)) break;
+                s_a = (int)ev_up(e.y);
+                ia++;
+            }
+            while (ic < nc) {
+                uint2 e = Ec[(long long)ic * st];
+                if (!key_before(C, c, e, tau, bid)) break;
+                s_c = (int)ev_up(e.y);
+                ic++;
+            }
+            const double uu = u53(rs.next());
+            if (uu < C.acc[s_a | (s_c << 1)]) {
+                if (nacc < C.capb)
+                    out[(long long)nacc * st] = (uint32_t)tau | ((uint32_t)s_a << 30) | ((uint32_t)s_c << 31);
+                nacc++;
+            }
+        }
+        if (nacc > C.capb) { atomicOr(&P.flags[bt.x], FL_OVERFLOW); nacc = C.capb; }
+        P.bvc[C.bvc_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.nloc + sl] = nacc;
+    }
+    // block sum of the bond occupation integral -> one atomic per block
+    __shared__ long long red[4];
+    for (int o = 32; o > 0; o >>= 1) nn += __shfl_down(nn, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long s = red[0] + red[1] + red[2] + red[3];
+        if (s) atomicAdd(&P.nnacc[bt.x], (unsigned long long)s);
+    }
+}
+
+// ===========================================================================
+// Step 4: per (site, slab) merge the surviving kinks with the new diagonal
+// vertices of the four bonds of the site, erase all worms, and regenerate
+// them on every interval with Eq. (worm).  Written in place.
+// ===========================================================================
+__global__ void __launch_bounds__(256) k_assemble(Pools P, const int2* __restrict__ blk)
+{
+    const int2 bt = blk[blockIdx.x];
+    const ChainDev& C = P.cd[bt.x];
+    const int u = bt.y + (int)threadIdx.x;
+    if (u >= C.ntau * C.N || P.flags[bt.x] != 0) return;
+    unsigned int* flag = &P.flags[bt.x];
+    const int sl = u % C.nloc;
+    const int r = u / C.nloc;
+    const int dsp = r % C.ndsp, k = r / C.ndsp;
+    const int i = site_join(C, dsp, sl);
+    const int st = C.nloc;
+    uint2* E = P.ev + ev_base(C, k, dsp, sl);
+    const long long cu = C.cnt_off + unit_su(C, k, dsp, sl);
+    const int n_old = P.cnt[cu];
+    const int s_lo = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
+    const int s_hi = P.bs[C.bs_off + unit_su(C, (k + 1) % C.ntau, dsp, sl)];
+
+    // surviving kinks: tick, dir | below << 2 | above << 3
+    int32_t kt[KINKMAX];
+    uint8_t kf[KINKMAX];
+    int nk = 0;
+    {
+        int s = s_lo;
+        for (int j = 0; j < n_old; j++) {
+            uint2 e = E[(long long)j * st];
+            int up = (int)ev_up(e.y);
+            if (!ev_worm(e.y) && up != s) {
+                if (nk < KINKMAX) { kt[nk] = (int32_t)e.x; kf[nk] = (uint8_t)(ev_dir(e.y) | (s << 2) | (up << 3)); nk++; }
+                else { atomicOr(flag, FL_OVERFLOW); return; }
+            }
+            s = up;
+        }
+    }
+    // the four bond buffers of this site: (i,+x), (i,+y), (i-x,+x), (i-y,+y)
+    const uint32_t* src[4];
+    int ns[4], ps[4];
+    long long bids[4];
+    for (int d = 0; d < 4; d++) {
+        int a = (d < 2) ? i : nbr(C, i, d);
+        int dspa, sla;
+        site_split(C, a, dspa, sla);
+        int bd = d & 1;
+        long long row = (long long)((k * 2 + bd) * C.ndsp + dspa);
+        src[d] = P.bv + C.bv_off + row * C.capb * C.nloc + sla;
+        ns[d] = P.bvc[C.bvc_off + row * C.nloc + sla];
+        ps[d] = 0;
+        bids[d] = 2LL * a + bd;
+    }
+    int pk = 0;
+    Stream rs;
+    rs.init(C, (uint32_t)P.sweep[bt.x], RNG_R, (uint32_t)((long long)i * C.ntau + k));
+    int32_t lo = C.T[k];
+    int p = s_lo;
+    int out = 0;
+    int32_t off[NWL];
+    uint8_t dirs[NWL];
+    for (;;) {
+        // next vertex in (tick, bond id) order
+        int best = -1;
+        int32_t bt_tick = 0;
+        long long bt_bid = 0;
+        if (pk < nk) { best = 4; bt_tick = kt[pk]; bt_bid = bond_id(C, i, kf[pk] & 3); }
+        for (int d = 0; d < 4; d++) {
+            if (ps[d] >= ns[d]) continue;
+            int32_t tk = (int32_t)(src[d][(long long)ps[d] * st] & 0x3FFFFFFFu);
+            if (best < 0 || tk < bt_tick || (tk == bt_tick && bids[d] < bt_bid)) {
+                best = d; bt_tick = tk; bt_bid = bids[d];
+            }
+        }
+        int32_t hi;
+        int q, above = 0, vdir = 0;
+        if (best < 0) { hi = C.T[k + 1]; q = s_hi; }
+        else if (best == 4) {
+            hi = bt_tick; q = (kf[pk] >> 2) & 1; above = (kf[pk] >> 3) & 1; vdir = kf[pk] & 3; pk++;
+        } else {
+            uint32_t v = src[best][(long long)ps[best] * st];
+            ps[best]++;
+            hi = bt_tick;
+            q = (int)((best < 2) ? (v >> 30) & 1u : (v >> 31) & 1u);
+            above = q;
+            vdir = best;
+        }
+        int n = sample_worms(C, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
+        if (n < 0) return;
+        if (out + n + (best >= 0 ? 1 : 0) > C.cap) { atomicOr(flag, FL_OVERFLOW); return; }
+        int s = p;
+        for (int w = 0; w < n; w++) {
+            s ^= 1;
+            E[(long long)out * st] = make_uint2((uint32_t)(lo + off[w]), 1u | ((uint32_t)dirs[w] << 1) | ((uint32_t)s << 3));
+            out++;
+        }
+        if (best < 0) break;
+        E[(long long)out * st] = make_uint2((uint32_t)hi, ((uint32_t)vdir << 1) | ((uint32_t)above << 3));
+        out++;
+        lo = hi;
+        p = above;
+    }
+    P.cnt[cu] = out;
+}
+
+// ===========================================================================
+// Steps 5-6: worm scattering, N_cycle cycles over the domain's worm list,
+// then the measurement.  One wavefront per space-time domain; the domain's
+// worldlines become doubly linked node lists (per site, between two boundary
+// sentinels) held in LDS when they fit, else in an HBM scratch region.
+// ===========================================================================
+struct Nodes {
+    int32_t* tick;
+    uint32_t* nxt;
+    uint32_t* prv;
+    uint32_t* aux;   // partner end of a vertex
+    uint8_t* fl;
+    uint32_t* wl;    // worm list
+};
+
+// One attempt of one worm (Step 5), with legs measured with the moving worm
+// removed so that L_min is the same before and after (Eq. (DB)).
+PMWA_DEV void worm_step(Nodes& A, uint32_t w, Stream& rs, const double* __restrict__ scat)
+{
+    const uint32_t fw = A.fl[w];
+    const bool up = fw & F_DIRUP;
+    const uint32_t x = up ? A.nxt[w] : A.prv[w];
+    const uint32_t fx = A.fl[x];
+    if (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) { A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
+    const int vd = (int)((fx >> 1) & 3u);
+    const bool xa = vd < 2;
+    const uint32_t y = A.aux[x];
+    const uint32_t Va = xa ? x : y, Vc = xa ? y : x;
+    const int32_t t = A.tick[x];
+    const uint32_t pw = A.prv[w], nw = A.nxt[w];
+    const uint32_t pa0 = A.prv[Va], na0 = A.nxt[Va], pc0 = A.prv[Vc], nc0 = A.nxt[Vc];
+    const uint32_t pa = pa0 == w ? pw : pa0, na = na0 == w ? nw : na0;
+    const uint32_t pc = pc0 == w ? pw : pc0, nc = nc0 == w ? nw : nc0;
+    long long L[4];
+    L[0] = (long long)t - (A.tick[pa] + (long long)(A.fl[pa] & F_WORM));
+    L[1] = (long long)t - (A.tick[pc] + (long long)(A.fl[pc] & F_WORM));
+    L[2] = (long long)A.tick[na] - t;
+    L[3] = (long long)A.tick[nc] - t;
+    const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
+    long long Lmin = L[0];
+    for (int j = 1; j < 4; j++) Lmin = L[j] < Lmin ? L[j] : Lmin;
+    const long long Li = L[i];
+    const uint64_t r = below(rs.next(), (uint64_t)Li);
+    if ((long long)r >= Lmin) { A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
+    // vertex roots with the worm in place
+    const int S = (int)(((A.fl[pa0] >> 3) & 1u) | (((A.fl[pc0] >> 3) & 1u) << 1)
+                      | (((A.fl[Va] >> 3) & 1u) << 2) | (((A.fl[Vc] >> 3) & 1u) << 3));
+    const int S0 = S ^ (1 << i);
+    const double uu = u53(rs.next());
+    int j = 0;
+    while (j < 3 && !(uu < scat[S0 * 16 + i * 4 + j])) j++;
+    const long long Lj = j == 0 ? L[0] : j == 1 ? L[1] : j == 2 ? L[2] : L[3];
+    const uint64_t r2 = below(rs.next(), (uint64_t)Lj);
+    // remove the worm from leg i
+    if (i >= 2) A.fl[x] = (uint8_t)((A.fl[x] & ~F_UP) | (fw & F_UP));
+    A.nxt[pw] = nw;
+    A.prv[nw] = pw;
+    // insert it on leg j, next to the vertex end Vy
+    const uint32_t Vy = (j & 1) ? Vc : Va;
+    uint32_t Pn, Nn;
+    uint32_t newup;
+    if (j >= 2) {
+        Pn = Vy; Nn = A.nxt[Vy];
+        newup = A.fl[Vy] & F_UP;
+        A.fl[Vy] = (uint8_t)(A.fl[Vy] ^ F_UP);
+    } else {
+        Nn = Vy; Pn = A.prv[Vy];
+        newup = (A.fl[Pn] & F_UP) ^ F_UP;
+    }
+    A.tick[w] = (j >= 2) ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
+    A.fl[w] = (uint8_t)(F_WORM | (j >= 2 ? F_DIRUP : 0u) | newup);
+    A.prv[w] = Pn;
+    A.nxt[w] = Nn;
+    A.nxt[Pn] = w;
+    A.prv[Nn] = w;
+}
+
+// block-wide (one wavefront) exclusive scan helper
+PMWA_DEV int wave_excl_scan(int v, int& total)
+{
+    const int lane = (int)threadIdx.x;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D,
+                             Nodes A, const int* __restrict__ off, const int* __restrict__ cnt,
+                             const double* __restrict__ scat, int NE)
+{
+    const int lane = (int)threadIdx.x;
+    const int k = D / C.ndsp, dsp = D - k * C.ndsp;
+    const int nloc = C.nloc, ex = C.ex, ey = C.ey;
+    const uint32_t BOT = (uint32_t)NE, TOP = (uint32_t)(NE + nloc);
+
+    // 1. nodes from the events of the domain's sites
+    for (int idx = lane; idx < NE; idx += 64) {
+        int lo = 0, hi = nloc - 1;           // site s with off[s] <= idx < off[s+1]
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= idx) lo = mid; else hi = mid - 1;
+        }
+        const int s = lo, j = idx - off[s];
+        const uint2 e = P.ev[ev_base(C, k, dsp, s) + (long long)j * nloc];
+        A.tick[idx] = (int32_t)e.x;
+        A.fl[idx] = (uint8_t)(e.y & 15u);
+        A.prv[idx] = j > 0 ? (uint32_t)idx - 1 : BOT + s;
+        A.nxt[idx] = j + 1 < cnt[s] ? (uint32_t)idx + 1 : TOP + s;
+        A.aux[idx] = NONE;
+    }
+    for (int s = lane; s < nloc; s += 64) {
+        const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
+        A.tick[BOT + s] = C.T[k];
+        A.fl[BOT + s] = (uint8_t)(F_SBOT | (bsv ? F_UP : 0u));
+        A.nxt[BOT + s] = cnt[s] ? (uint32_t)off[s] : TOP + s;
+        A.prv[BOT + s] = NONE;
+        A.aux[BOT + s] = NONE;
+        A.tick[TOP + s] = C.T[k + 1];
+        A.fl[TOP + s] = (uint8_t)F_STOP;
+        A.prv[TOP + s] = cnt[s] ? (uint32_t)(off[s] + cnt[s] - 1) : BOT + s;
+        A.nxt[TOP + s] = NONE;
+        A.aux[TOP + s] = NONE;
+    }
+    __syncthreads();
+    // 2. partner ends of vertices; bonds leaving the domain are boundary
+    //    vertices (a worm bounces off them)
+    for (int idx = lane; idx < NE; idx += 64) {
+        const uint32_t f = A.fl[idx];
+        if (f & F_WORM) continue;
+        int lo = 0, hi = nloc - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= idx) lo = mid; else hi = mid - 1;
+        }
+        const int s = lo, lx = s % ex, ly = s / ex;
+        const int vd = (int)((f >> 1) & 3u);
+        int s2;
+        bool cross;
+        if (vd == 0) { cross = C.dom_x > 1 && lx == ex - 1; s2 = lx == ex - 1 ? s - (ex - 1) : s + 1; }
+        else if (vd == 2) { cross = C.dom_x > 1 && lx == 0; s2 = lx == 0 ? s + (ex - 1) : s - 1; }
+        else if (vd == 1) { cross = C.dom_y > 1 && ly == ey - 1; s2 = ly == ey - 1 ? s - (ey - 1) * ex : s + ex; }
+        else { cross = C.dom_y > 1 && ly == 0; s2 = ly == 0 ? s + (ey - 1) * ex : s - ex; }
+        if (cross) { A.fl[idx] = (uint8_t)(f | F_CROSS); continue; }
+        const int32_t t = A.tick[idx];
+        int a = off[s2], b = off[s2] + cnt[s2];   // first node of s2 with tick >= t
+        while (a < b) {
+            int mid = (a + b) >> 1;
+            if (A.tick[mid] < t) a = mid + 1; else b = mid;
+        }
+        uint32_t found = NONE;
+        for (int m = a; m < off[s2] + cnt[s2] && A.tick[m] == t; m++) {
+            uint32_t g = A.fl[m];
+            if (!(g & F_WORM) && (int)((g >> 1) & 3u) == (vd ^ 2)) { found = (uint32_t)m; break; }
+        }
+        if (found == NONE) atomicOr(&P.flags[chain], FL_STATE);
+        A.aux[idx] = found;
+    }
+    // 3. worm list in (site, slot) order = node order
+    int nw = 0;
+    for (int base = 0; base < NE; base += 64) {
+        const int idx = base + lane;
+        const int isw = (idx < NE) && (A.fl[idx] & F_WORM);
+        int tot;
+        const int pos = wave_excl_scan(isw, tot);
+        if (isw) A.wl[nw + pos] = (uint32_t)idx;
+        nw += tot;
+    }
+    __syncthreads();
+    if (__any(P.flags[chain] != 0)) return;
+
+    // 4. N_cycle cycles, worms in list order (every lane runs the same
+    //    serial chain of decisions)
+    Stream rs;
+    rs.init(C, (uint32_t)P.sweep[chain], RNG_S, (uint32_t)D);
+    for (int cyc = 0; cyc < C.ncycle; cyc++)
+        for (int iw = 0; iw < nw; iw++) worm_step(A, A.wl[iw], rs, scat);
+    __syncthreads();
+
+    // 5. measurement (Step 6) and write-back, one lane per site
+    long long nv = 0, nkink = 0, nwc = 0, occ = 0;
+    double qimp = 0.0;
+    bool bad = false;
+    for (int s = lane; s < nloc; s += 64) {
+        const long long ebase = ev_base(C, k, dsp, s);
+        int stt = (A.fl[BOT + s] >> 3) & 1;
+        long long last = 2LL * C.T[k];
+        int32_t ilo = C.T[k];
+        int par = 0, j = 0;
+        uint32_t node = A.nxt[BOT + s];
+        int guard = 0;
+        for (;;) {
+            if (node == TOP + (uint32_t)s) {
+                occ += (long long)stt * (2LL * C.T[k + 1] - last);
+                const long long ell = (long long)C.T[k + 1] - ilo;
+                if (ell > 0) {
+                    const double th = tanh_ell(C, ell);
+                    qimp += (double)ell * (par ? 1.0 / th : th);
+                }
+                break;
+            }
+            if (node >= (uint32_t)NE || ++guard > NE) { bad = true; break; }
+            const uint32_t f = A.fl[node];
+            const int32_t tk = A.tick[node];
+            const long long pos = 2LL * tk + (f & F_WORM);
+            occ += (long long)stt * (pos - last);
+            last = pos;
+            if (f & F_WORM) {
+                nwc++;
+                par ^= 1;
+            } else {
+                const long long ell = (long long)tk - ilo;
+                if (ell > 0) {
+                    const double th = tanh_ell(C, ell);
+                    qimp += (double)ell * (par ? 1.0 / th : th);
+                }
+                if (((f >> 1) & 3u) < 2) {
+                    nv++;
+                    if ((int)((f >> 3) & 1u) != stt) nkink++;
+                }
+                ilo = tk;
+                par = 0;
+            }
+            stt = (int)((f >> 3) & 1u);
+            if (j < C.cap) P.ev[ebase + (long long)j * nloc] = make_uint2((uint32_t)tk, f & 15u);
+            j++;
+            node = A.nxt[node];
+        }
+        if (j > C.cap) bad = true;
+        P.cnt[C.cnt_off + unit_su(C, k, dsp, s)] = j > C.cap ? C.cap : j;
+    }
+    if (bad) atomicOr(&P.flags[chain], FL_OVERFLOW);
+    for (int o = 32; o > 0; o >>= 1) {
+        nv += __shfl_down(nv, o, 64);
+        nkink += __shfl_down(nkink, o, 64);
+        nwc += __shfl_down(nwc, o, 64);
+        occ += __shfl_down(occ, o, 64);
+        qimp += __shfl_down(qimp, o, 64);
+    }
+    if (lane == 0) {
+        DomPart dp;
+        dp.nv = nv; dp.nkink = nkink; dp.nw = nwc; dp.occ2 = occ; dp.qimp = qimp; dp.pad_ = 0;
+        P.dpart[C.dom_off + D] = dp;
+    }
+}
+
+// dynamic LDS: [scat 256 doubles][off nloc+1][cnt nloc][nodes...]
+__global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict__ blk)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blk[blockIdx.x];
+    const ChainDev& C = P.cd[bt.x];
+    const int D = bt.y;
+    const int lane = (int)threadIdx.x;
+    if (D >= C.ntau * C.ndsp) return;
+    const int k = D / C.ndsp, dsp = D - k * C.ndsp;
+    const int nloc = C.nloc;
+    double* scat = reinterpret_cast<double*>(smem);
+    int* off = reinterpret_cast<int*>(smem + 256 * sizeof(double));
+    int* cnt = off + (nloc + 1);
+    for (int i = lane; i < 256; i += 64) scat[i] = C.scat[i];
+    for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
+    __syncthreads();
+    // exclusive scan of the per-site counts
+    int carry = 0;
+    for (int base = 0; base < nloc; base += 64) {
+        const int s = base + lane;
+        const int v = s < nloc ? cnt[s] : 0;
+        int tot;
+        const int ex = wave_excl_scan(v, tot);
+        if (s < nloc) off[s] = carry + ex;
+        carry += tot;
+    }
+    if (lane == 0) off[nloc] = carry;
+    __syncthreads();
+    const int NE = carry;
+    const int NN = NE + 2 * nloc;
+    if (P.flags[bt.x] != 0) return;
+
+    const size_t fixed = 256 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
+    const size_t fixed_al = (fixed + 15) & ~(size_t)15;
+    if (NN <= P.lds_nodes) {
+        unsigned char* p = smem + fixed_al;
+        Nodes A;
+        A.tick = reinterpret_cast<int32_t*>(p); p += (size_t)P.lds_nodes * 4;
+        A.nxt = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
+        A.prv = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
+        A.aux = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
+        A.wl = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
+        A.fl = reinterpret_cast<uint8_t*>(p);
+        scatter_domain(P, C, bt.x, D, A, off, cnt, scat, NE);
+    } else {
+        if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
+        const long long b = C.scr_off + (long long)D * C.scr_nodes;
+        Nodes A;
+        A.tick = P.s_tick + b;
+        A.nxt = P.s_nxt + b;
+        A.prv = P.s_prv + b;
+        A.aux = P.s_aux + b;
+        A.fl = P.s_fl + b;
+        A.wl = P.s_wl + b;
+        scatter_domain(P, C, bt.x, D, A, off, cnt, scat, NE);
+    }
+}
+
+// ===========================================================================
+// Boundary updates on the global arrays
+// ===========================================================================
+struct SiteArr {
+    uint2* e;
+    int st, n, cap;
+    PMWA_DEV uint2 get(int j) const { return e[(long long)j * st]; }
+    PMWA_DEV void put(int j, uint2 v) { e[(long long)j * st] = v; }
+    // replace events [lo, hi) by nw[0..m)
+    PMWA_DEV bool replace(int lo, int hi, const uint2* nw, int m)
+    {
+        const int delta = m - (hi - lo);
+        if (n + delta > cap) return false;
+        if (delta > 0) for (int j = n - 1; j >= hi; j--) put(j + delta, get(j));
+        else if (delta < 0) for (int j = hi; j < n; j++) put(j + delta, get(j));
+        for (int j = 0; j < m; j++) put(lo + j, nw[j]);
+        n += delta;
+        return true;
+    }
+};
+
+// worms of one interval as events (slot base + offset), occupation starting at p
+PMWA_DEV int gen_worms(const ChainDev& C, Stream& rs, int32_t base, long long ell, int sigma,
+                       int p, uint2* out, unsigned int* flag)
+{
+    int32_t off[NWL];
+    uint8_t dirs[NWL];
+    const int n = sample_worms(C, rs, ell, sigma, off, dirs, flag);
+    int s = p;
+    for (int w = 0; w < n; w++) {
+        s ^= 1;
+        out[w] = make_uint2((uint32_t)(base + off[w]), 1u | ((uint32_t)dirs[w] << 1) | ((uint32_t)s << 3));
+    }
+    return n;
+}
+
+// Step 1, Eq. (Para): one lane per site, temporal boundaries k = 0.. in order;
+// the upper domain's stream (site, k) makes the choice, then the worms of the
+// two legs I_1 (above) and I_2 (below) are regenerated.
+__global__ void __launch_bounds__(128) k_btemporal(Pools P, const int2* __restrict__ blk)
+{
+    const int2 bt = blk[blockIdx.x];
+    const ChainDev& C = P.cd[bt.x];
+    const int u = bt.y + (int)threadIdx.x;
+    if (u >= C.N || P.flags[bt.x] != 0) return;
+    unsigned int* flag = &P.flags[bt.x];
+    const int dsp = u / C.nloc, sl = u % C.nloc;
+    const int site = site_join(C, dsp, sl);
+    const int nt = C.ntau;
+    const uint32_t sweep = (uint32_t)P.sweep[bt.x];
+    uint2 b1[NWL], b2[NWL];
+    for (int k = 0; k < nt; k++) {
+        Stream rs;
+        rs.init(C, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
+        const long long cuk = C.cnt_off + unit_su(C, k, dsp, sl);
+        SiteArr Ak{P.ev + ev_base(C, k, dsp, sl), C.nloc, P.cnt[cuk], C.cap};
+        uint8_t* sk = &P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
+        if (nt == 1) {
+            bool hasv = false;
+            for (int j = 0; j < Ak.n; j++) hasv |= !ev_worm(Ak.get(j).y);
+            if (!hasv) {
+                // the circle is one interval through the boundary
+                const double W[2] = {1.0, 1.0};
+                const int sp = choose(W, u53(rs.next()));
+                const int m = gen_worms(C, rs, 0, C.M, 0, sp, b1, flag);
+                if (m < 0) return;
+                if (!Ak.replace(0, Ak.n, b1, m)) { atomicOr(flag, FL_OVERFLOW); return; }
+                P.cnt[cuk] = Ak.n;
+                *sk = (uint8_t)sp;
+                continue;
+            }
+        }
+        // I_1: boundary up to the first vertex of slab k
+        int jv = 0;
+        while (jv < Ak.n && ev_worm(Ak.get(jv).y)) jv++;
+        int32_t t1;
+        int q;
+        if (jv < Ak.n) { t1 = (int32_t)Ak.get(jv).x; q = jv > 0 ? (int)ev_up(Ak.get(jv - 1).y) : (int)*sk; }
+        else { t1 = C.T[k + 1]; q = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dsp, sl)]; }
+        const long long l1 = (long long)t1 - C.T[k];
+        // I_2: last vertex of slab k-1 up to the boundary
+        const int kp = (k + nt - 1) % nt;
+        const long long cukp = C.cnt_off + unit_su(C, kp, dsp, sl);
+        SiteArr Bk{P.ev + ev_base(C, kp, dsp, sl), C.nloc, P.cnt[cukp], C.cap};
+        int jl = Bk.n - 1;
+        while (jl >= 0 && ev_worm(Bk.get(jl).y)) jl--;
+        int32_t t2;
+        int p;
+        if (jl >= 0) { t2 = (int32_t)Bk.get(jl).x; p = (int)ev_up(Bk.get(jl).y); }
+        else { t2 = C.T[kp]; p = P.bs[C.bs_off + unit_su(C, kp, dsp, sl)]; }
+        const long long l2 = (long long)C.T[kp + 1] - t2;
+        double W[2];
+        for (int sp = 0; sp < 2; sp++) W[sp] = fleg(C, sp ^ q, l1) * fleg(C, p ^ sp, l2);
+        const int sp = choose(W, u53(rs.next()));
+        const int m1 = gen_worms(C, rs, C.T[k], l1, sp ^ q, sp, b1, flag);
+        if (m1 < 0) return;
+        const int m2 = gen_worms(C, rs, t2, l2, p ^ sp, p, b2, flag);
+        if (m2 < 0) return;
+        if (nt == 1) {
+            // same array: suffix first, then prefix
+            if (!Ak.replace(jl + 1, Ak.n, b2, m2) || !Ak.replace(0, jv, b1, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
+            P.cnt[cuk] = Ak.n;
+        } else {
+            if (!Ak.replace(0, jv, b1, m1) || !Bk.replace(jl + 1, Bk.n, b2, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
+            P.cnt[cuk] = Ak.n;
+            P.cnt[cukp] = Bk.n;
+        }
+        *sk = (uint8_t)sp;
+    }
+}
+
+// Step 2, Eq. (ParaSpace): one lane per bond crossing a spatial domain
+// boundary in direction d (owned by the left/lower domain), its vertices in
+// tick order; heat bath over the six allowed root states with the leg
+// weights f, then the worms of the four legs are regenerated.
+__global__ void __launch_bounds__(128) k_bspatial(Pools P, const int2* __restrict__ blk, int d)
+{
+    const int2 bt = blk[blockIdx.x];
+    const ChainDev& C = P.cd[bt.x];
+    const int u = bt.y + (int)threadIdx.x;
+    const int nb_units = d == 0 ? (C.dom_x > 1 ? C.Ly * C.dom_x : 0) : (C.dom_y > 1 ? C.Lx * C.dom_y : 0);
+    if (u >= nb_units || P.flags[bt.x] != 0) return;
+    unsigned int* flag = &P.flags[bt.x];
+    int a;
+    if (d == 0) { const int y = u / C.dom_x, dx = u % C.dom_x; a = y * C.Lx + dx * C.ex + C.ex - 1; }
+    else { const int dy = u / C.Lx, x = u % C.Lx; a = (dy * C.ey + C.ey - 1) * C.Lx + x; }
+    const int c = nbr(C, a, d);
+    int dspa, sla, dspc, slc;
+    site_split(C, a, dspa, sla);
+    site_split(C, c, dspc, slc);
+    const int nt = C.ntau;
+    Stream rs;
+    rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)(2LL * a + d));
+    const int ALLOWED[6] = {0, 5, 6, 9, 10, 15};
+    uint2 w0[NWL], w1[NWL], w2[NWL], w3[NWL];
+    for (int k = 0; k < nt; k++) {
+        const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
+        const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
+        SiteArr A{P.ev + ev_base(C, k, dspa, sla), C.nloc, P.cnt[cua], C.cap};
+        SiteArr B{P.ev + ev_base(C, k, dspc, slc), C.nloc, P.cnt[cuc], C.cap};
+        const int bsa = P.bs[C.bs_off + unit_su(C, k, dspa, sla)];
+        const int bsc = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
+        const int bsa1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspa, sla)];
+        const int bsc1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspc, slc)];
+        int ja = 0;
+        for (;;) {
+            while (ja < A.n) {
+                const uint2 e = A.get(ja);
+                if (!ev_worm(e.y) && (int)ev_dir(e.y) == d) break;
+                ja++;
+            }
+            if (ja >= A.n) break;
+            const int32_t t = (int32_t)A.get(ja).x;
+            int jc = 0;
+            while (jc < B.n) {
+                const uint2 e = B.get(jc);
+                if ((int32_t)e.x == t && !ev_worm(e.y) && (int)ev_dir(e.y) == d + 2) break;
+                jc++;
+            }
+            if (jc >= B.n) { atomicOr(flag, FL_STATE); return; }
+            // legs, worms ignored
+            int la = ja - 1; while (la >= 0 && ev_worm(A.get(la).y)) la--;
+            int lc = jc - 1; while (lc >= 0 && ev_worm(B.get(lc).y)) lc--;
+            int ha = ja + 1; while (ha < A.n && ev_worm(A.get(ha).y)) ha++;
+            int hc = jc + 1; while (hc < B.n && ev_worm(B.get(hc).y)) hc++;
+            const int32_t lo_a = la >= 0 ? (int32_t)A.get(la).x : C.T[k];
+            const int p1 = la >= 0 ? (int)ev_up(A.get(la).y) : bsa;
+            const int32_t lo_c = lc >= 0 ? (int32_t)B.get(lc).x : C.T[k];
+            const int p2 = lc >= 0 ? (int)ev_up(B.get(lc).y) : bsc;
+            const int32_t hi_a = ha < A.n ? (int32_t)A.get(ha).x : C.T[k + 1];
+            const int q1 = ha < A.n ? (int)ev_up(A.get(ha - 1).y) : bsa1;
+            const int32_t hi_c = hc < B.n ? (int32_t)B.get(hc).x : C.T[k + 1];
+            const int q2 = hc < B.n ? (int)ev_up(B.get(hc - 1).y) : bsc1;
+            const long long l0 = (long long)t - lo_a, l1 = (long long)t - lo_c;
+            const long long l2 = (long long)hi_a - t, l3 = (long long)hi_c - t;
+            double W[6];
+            for (int m = 0; m < 6; m++) {
+                const int S = ALLOWED[m];
+                const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
+                W[m] = (((fleg(C, p1 ^ s1, l0) * fleg(C, p2 ^ s2, l1)) * fleg(C, s1p ^ q1, l2))
+                        * fleg(C, s2p ^ q2, l3)) * C.vw[S];
+            }
+            const int m = choose(W, u53(rs.next()));
+            const int S = ALLOWED[m];
+            const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
+            const int n0 = gen_worms(C, rs, lo_a, l0, p1 ^ s1, p1, w0, flag);
+            const int n1 = n0 < 0 ? -1 : gen_worms(C, rs, lo_c, l1, p2 ^ s2, p2, w1, flag);
+            const int n2 = n1 < 0 ? -1 : gen_worms(C, rs, t, l2, s1p ^ q1, s1p, w2, flag);
+            const int n3 = n2 < 0 ? -1 : gen_worms(C, rs, t, l3, s2p ^ q2, s2p, w3, flag);
+            if (n3 < 0) return;
+            uint2 va = A.get(ja), vc = B.get(jc);
+            va.y = (va.y & ~8u) | ((uint32_t)s1p << 3);
+            vc.y = (vc.y & ~8u) | ((uint32_t)s2p << 3);
+            A.put(ja, va);
+            B.put(jc, vc);
+            const int na_before = A.n;
+            if (!A.replace(ja + 1, ha, w2, n2) || !A.replace(la + 1, ja, w0, n0) ||
+                !B.replace(jc + 1, hc, w3, n3) || !B.replace(lc + 1, jc, w1, n1)) {
+                atomicOr(flag, FL_OVERFLOW);
+                return;
+            }
+            // the vertex moved by the change of the lower leg's worm count
+            ja = ja + (n0 - (ja - (la + 1))) + 1;
+            (void)na_before;
+        }
+        P.cnt[cua] = A.n;
+        P.cnt[cuc] = B.n;
+    }
+}
+
+// ===========================================================================
+// End of sweep: per chain, sum the domain partials in domain order, append
+// the record to the series ring, advance the sweep counter.
+// ===========================================================================
+__global__ void __launch_bounds__(256) k_finish(Pools P)
+{
+    const int chain = blockIdx.x;
+    const ChainDev& C = P.cd[chain];
+    const int nd = (int)C.n_dom;
+    const int tid = (int)threadIdx.x;
+    const int per = (nd + 255) / 256;
+    long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    double q = 0.0;
+    for (int i = tid * per; i < nd && i < (tid + 1) * per; i++) {
+        const DomPart dp = P.dpart[C.dom_off + i];
+        a0 += dp.nv; a1 += dp.nkink; a2 += dp.nw; a3 += dp.occ2; q += dp.qimp;
+    }
+    __shared__ long long s0[256], s1[256], s2[256], s3[256];
+    __shared__ double sq[256];
+    s0[tid] = a0; s1[tid] = a1; s2[tid] = a2; s3[tid] = a3; sq[tid] = q;
+    __syncthreads();
+    if (tid == 0) {
+        pmwa_obs o;
+        o.nv = 0; o.nkink = 0; o.nw = 0; o.occ2 = 0; o.qimp = 0.0;
+        for (int i = 0; i < 256; i++) {
+            o.nv += s0[i]; o.nkink += s1[i]; o.nw += s2[i]; o.occ2 += s3[i]; o.qimp += sq[i];
+        }
+        o.nn2 = (long long)P.nnacc[chain];
+        P.nnacc[chain] = 0ULL;
+        const unsigned long long sw = P.sweep[chain];
+        P.ser[C.ser_off + (long long)(sw % (unsigned long long)P.series_cap)] = o;
+        P.sweep[chain] = sw + 1ULL;
+    }
+}
+
+}  // namespace pmwa

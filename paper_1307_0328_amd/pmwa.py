@@ -1,0 +1,229 @@
+"""ctypes binding of libpmwa.so (include/pmwa.h): argument marshalling only.
+
+Every step of the sweep runs in the HIP kernels of the library; there is no
+fallback.  If the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmwa.so")
+
+PMWA_OK, PMWA_EINVAL, PMWA_ENOMEM, PMWA_EDEVICE, PMWA_EOVERFLOW, PMWA_ESTATE = 0, -1, -2, -3, -4, -5
+PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
+
+EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
+           "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
+           "pmwa_destroy", "pmwa_strerror"]
+
+
+class pmwa_params(C.Structure):
+    _fields_ = [("Lx", C.c_int32), ("Ly", C.c_int32), ("beta", C.c_double),
+                ("t", C.c_double), ("V", C.c_double), ("mu", C.c_double), ("eta", C.c_double),
+                ("dom_x", C.c_int32), ("dom_y", C.c_int32), ("dom_tau", C.c_int32),
+                ("ticks_log2", C.c_int32), ("n_cycle", C.c_int32), ("C", C.c_double),
+                ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("pad_", C.c_uint32)]
+
+
+class pmwa_opts(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("scatter_mode", C.c_int32), ("series_cap", C.c_int32),
+                ("event_cap", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class pmwa_obs(C.Structure):
+    _fields_ = [("nv", C.c_int64), ("nkink", C.c_int64), ("nw", C.c_int64),
+                ("occ2", C.c_int64), ("nn2", C.c_int64), ("qimp", C.c_double)]
+
+
+class pmwa_info(C.Structure):
+    _fields_ = [("C", C.c_double), ("rho_max", C.c_double), ("delta", C.c_double),
+                ("lam", C.c_double), ("n_cycle", C.c_int32), ("M", C.c_int32),
+                ("event_cap", C.c_int32), ("bond_cap", C.c_int32), ("n_domains", C.c_int64)]
+
+
+OBS_DTYPE = np.dtype([("nv", "<i8"), ("nkink", "<i8"), ("nw", "<i8"),
+                      ("occ2", "<i8"), ("nn2", "<i8"), ("qimp", "<f8")])
+
+_lib = None
+
+
+def lib():
+    """Load libpmwa.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1307_0328_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.pmwa_create.argtypes = [P(pmwa_params), C.c_int, P(pmwa_opts), P(C.c_void_p)]
+        L.pmwa_sweep.argtypes = [C.c_void_p, C.c_int64]
+        L.pmwa_phase.argtypes = [C.c_void_p, C.c_int]
+        L.pmwa_measure.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.pmwa_status.argtypes = [C.c_void_p]
+        L.pmwa_get_state.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int64, P(C.c_int64), P(C.c_uint64)]
+        L.pmwa_set_state.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int64, C.c_uint64]
+        L.pmwa_chain_info.argtypes = [C.c_void_p, C.c_int, P(pmwa_info)]
+        L.pmwa_default_event_cap.argtypes = [P(pmwa_params)]
+        L.pmwa_destroy.argtypes = [C.c_void_p]
+        L.pmwa_destroy.restype = None
+        L.pmwa_strerror.argtypes = [C.c_int]
+        L.pmwa_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class PmwaError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lib().pmwa_strerror(code).decode()} ({code})")
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise PmwaError(rc, where)
+
+
+def make_params(**kw) -> pmwa_params:
+    d = dict(Lx=4, Ly=4, beta=2.0, t=1.0, V=0.0, mu=0.0, eta=0.1, dom_x=1, dom_y=1,
+             dom_tau=1, ticks_log2=24, n_cycle=0, C=math.nan, seed=1, chain_id=0)
+    if "L" in kw:
+        L = kw.pop("L")
+        d["Lx"] = d["Ly"] = L
+    d.update(kw)
+    p = pmwa_params()
+    for k, v in d.items():
+        setattr(p, k, v)
+    return p
+
+
+# --- thin wrappers with the C names -------------------------------------
+def pmwa_create(chains, opts=None):
+    arr = (pmwa_params * len(chains))(*chains)
+    o = opts if opts is not None else pmwa_opts()
+    h = C.c_void_p()
+    _check(lib().pmwa_create(arr, len(chains), C.byref(o), C.byref(h)), "pmwa_create")
+    return h
+
+
+def pmwa_sweep(h, n):
+    _check(lib().pmwa_sweep(h, int(n)), "pmwa_sweep")
+
+
+def pmwa_phase(h, phase):
+    _check(lib().pmwa_phase(h, int(phase)), "pmwa_phase")
+
+
+def pmwa_measure(h, chain, max_rows=1 << 22):
+    buf = np.zeros(max_rows, dtype=OBS_DTYPE)
+    n = C.c_int64()
+    rc = lib().pmwa_measure(h, chain, buf.ctypes.data, max_rows, C.byref(n))
+    _check(rc, "pmwa_measure")
+    return buf[: n.value].copy()
+
+
+def pmwa_status(h):
+    return lib().pmwa_status(h)
+
+
+def pmwa_get_state(h, chain, n_sites, ntau):
+    ne = C.c_int64()
+    sw = C.c_uint64()
+    _check(lib().pmwa_get_state(h, chain, None, None, None, None, 0, C.byref(ne), C.byref(sw)),
+           "pmwa_get_state")
+    bstate = np.zeros(n_sites * ntau, np.uint8)
+    counts = np.zeros(n_sites * ntau, np.int32)
+    ticks = np.zeros(max(ne.value, 1), np.int32)
+    infos = np.zeros(max(ne.value, 1), np.uint32)
+    _check(lib().pmwa_get_state(h, chain, bstate.ctypes.data, counts.ctypes.data, ticks.ctypes.data,
+                                infos.ctypes.data, len(ticks), C.byref(ne), C.byref(sw)),
+           "pmwa_get_state")
+    return dict(bstate=bstate, counts=counts, ticks=ticks[: ne.value], infos=infos[: ne.value],
+                sweep=int(sw.value))
+
+
+def pmwa_set_state(h, chain, st):
+    bstate = np.ascontiguousarray(st["bstate"], np.uint8)
+    counts = np.ascontiguousarray(st["counts"], np.int32)
+    ticks = np.ascontiguousarray(st["ticks"], np.int32)
+    infos = np.ascontiguousarray(st["infos"], np.uint32)
+    _check(lib().pmwa_set_state(h, chain, bstate.ctypes.data, counts.ctypes.data, ticks.ctypes.data,
+                                infos.ctypes.data, len(ticks), int(st["sweep"])), "pmwa_set_state")
+
+
+def pmwa_chain_info(h, chain):
+    info = pmwa_info()
+    _check(lib().pmwa_chain_info(h, chain, C.byref(info)), "pmwa_chain_info")
+    return info
+
+
+def pmwa_default_event_cap(p):
+    return lib().pmwa_default_event_cap(C.byref(p))
+
+
+def pmwa_destroy(h):
+    if h:
+        lib().pmwa_destroy(h)
+
+
+class Sim:
+    """A handle of one or more chains (convenience around the calls above)."""
+
+    def __init__(self, chains, stream=None, scatter_mode=0, series_cap=4096, event_cap=0,
+                 use_graph=False):
+        if isinstance(chains, pmwa_params):
+            chains = [chains]
+        self.chains = list(chains)
+        o = pmwa_opts()
+        o.stream = stream
+        o.scatter_mode = scatter_mode
+        o.series_cap = series_cap
+        o.event_cap = event_cap
+        o.use_graph = 1 if use_graph else 0
+        self.h = pmwa_create(self.chains, o)
+
+    def close(self):
+        if self.h:
+            pmwa_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n=1):
+        pmwa_sweep(self.h, n)
+
+    def phase(self, ph):
+        pmwa_phase(self.h, ph)
+
+    def measure(self, chain=0):
+        return pmwa_measure(self.h, chain)
+
+    def status(self):
+        return pmwa_status(self.h)
+
+    def get_state(self, chain=0):
+        p = self.chains[chain]
+        return pmwa_get_state(self.h, chain, p.Lx * p.Ly, p.dom_tau)
+
+    def set_state(self, st, chain=0):
+        pmwa_set_state(self.h, chain, st)
+
+    def info(self, chain=0):
+        return pmwa_chain_info(self.h, chain)

@@ -1,0 +1,162 @@
+"""Bit-exact parity of the HIP sweep with the serial oracle, through the C ABI.
+
+Both sides start from the same state (the empty configuration, or a state the
+oracle produced) and run the same phases; the canonical states (boundary
+occupations, per-site event lists) must be identical and the per-sweep
+records equal (integers exactly, the improved worm-density sum to 1e-12
+relative: its summation order differs).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _pm():
+    from paper_1307_0328_amd import pmwa as P
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def assert_state_equal(sg, so, where):
+    for key in ("bstate", "counts", "ticks", "infos"):
+        a, b = np.asarray(sg[key]), np.asarray(so[key])
+        if a.shape != b.shape or not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0] if a.shape == b.shape else None
+            raise AssertionError(f"{where}: {key} differs (shapes {a.shape} {b.shape}, "
+                                 f"first index {None if bad is None or len(bad) == 0 else bad[0]})")
+    assert sg["sweep"] == so["sweep"], where
+
+
+def assert_series_equal(rg, ro, where):
+    assert len(rg) == len(ro), where
+    for f in ("nv", "nkink", "nw", "occ2", "nn2"):
+        np.testing.assert_array_equal(rg[f], ro[f], err_msg=f"{where}: {f}")
+    np.testing.assert_allclose(rg["qimp"], ro["qimp"], rtol=1e-12, atol=0, err_msg=f"{where}: qimp")
+
+
+CASES = {
+    # the small plain workload: 4x4, beta*t = 2, eta = 0.1, one domain
+    "4x4_b2": dict(L=4, beta=2.0, t=1.0, V=0.0, mu=0.0, eta=0.1, seed=1),
+    "8x8_grid2x2x2": dict(L=8, beta=4.0, V=1.0, mu=0.5, eta=0.05, dom_x=2, dom_y=2, dom_tau=2, seed=2),
+    "6x4_grid3x2x3": dict(Lx=6, Ly=4, beta=3.0, V=0.5, mu=-0.5, eta=0.3, dom_x=3, dom_y=2, dom_tau=3, seed=3),
+    "t0_single_site": dict(L=4, beta=2.0, t=0.0, mu=0.7, eta=0.4, dom_tau=2, dom_x=2, seed=4),
+    "3x3_short_ticks": dict(L=3, beta=1.0, eta=0.5, ticks_log2=10, seed=5),
+    "12x8_grid4x2x1": dict(Lx=12, Ly=8, beta=6.0, V=2.0, mu=1.0, eta=0.1, dom_x=4, dom_y=2, dom_tau=1, seed=6),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_sweeps_bit_exact(name):
+    P = _pm()
+    cfg = CASES[name]
+    n_sweeps = 40
+    ch = O.Chain(**cfg)
+    say(f"[parity] case={name} cfg={cfg}")
+    with P.Sim(P.make_params(**cfg)) as sim:
+        for s in range(n_sweeps):
+            sim.sweep(1)
+            ch.sweep(1)
+            assert sim.status() == 0, f"{name} sweep {s}: device flags"
+            if s % 10 == 9 or s < 3:
+                assert_state_equal(sim.get_state(), ch.get_state(), f"{name} after sweep {s}")
+        assert_series_equal(sim.measure(), ch.series(), name)
+
+
+@pytest.mark.parametrize("name", ["8x8_grid2x2x2", "6x4_grid3x2x3", "3x3_short_ticks"])
+def test_each_phase_bit_exact(name):
+    """Load an oracle state, run one phase at a time on both sides."""
+    P = _pm()
+    cfg = CASES[name]
+    ch = O.Chain(**cfg)
+    ch.sweep(7)
+    ch.series()
+    say(f"[parity-phase] case={name}")
+    with P.Sim(P.make_params(**cfg)) as sim:
+        sim.set_state(ch.get_state())
+        assert_state_equal(sim.get_state(), ch.get_state(), "after set_state")
+        for rep in range(3):
+            for ph in range(O.PH_V, O.PH_END + 1):
+                say(f"[parity-phase] case={name} rep={rep} phase={ph}")
+                sim.phase(ph)
+                ch.phase(ph)
+                assert sim.status() == 0
+                assert_state_equal(sim.get_state(), ch.get_state(), f"{name} rep {rep} phase {ph}")
+        assert_series_equal(sim.measure(), ch.series(), name)
+
+
+def test_workload_64x64_grid8x8x2_bit_exact():
+    """The single-chain 64x64 workload (beta*t = 16, V = 1, mu = 0.5, eta = 0.05,
+    8x8 spatial x 2 temporal domains), a few sweeps."""
+    P = _pm()
+    cfg = dict(L=64, beta=16.0, t=1.0, V=1.0, mu=0.5, eta=0.05, dom_x=8, dom_y=8, dom_tau=2, seed=2)
+    ch = O.Chain(**cfg)
+    say("[parity] 64x64 workload")
+    with P.Sim(P.make_params(**cfg)) as sim:
+        for s in range(4):
+            sim.sweep(1)
+            ch.sweep(1)
+            assert sim.status() == 0
+            assert_state_equal(sim.get_state(), ch.get_state(), f"64x64 sweep {s}")
+        assert_series_equal(sim.measure(), ch.series(), "64x64")
+
+
+def test_batched_equals_alone_and_oracle():
+    """Chains of different shapes in one handle: each is identical to itself
+    alone and to the oracle (the stream is keyed by chain_id, not by slot)."""
+    P = _pm()
+    cfgs = [dict(L=4, beta=2.0, eta=0.1, seed=7, chain_id=3),
+            dict(Lx=6, Ly=4, beta=3.0, V=0.5, mu=-0.5, eta=0.3, dom_x=3, dom_y=2, dom_tau=3, seed=7, chain_id=9),
+            dict(L=8, beta=4.0, V=1.0, mu=0.5, eta=0.05, dom_x=2, dom_y=2, dom_tau=2, seed=7, chain_id=11),
+            dict(L=4, beta=2.0, eta=0.1, seed=7, chain_id=4)]
+    say("[batched] 4 chains")
+    with P.Sim([P.make_params(**c) for c in cfgs]) as sim:
+        sim.sweep(20)
+        assert sim.status() == 0
+        for i, c in enumerate(cfgs):
+            ch = O.Chain(**c)
+            ch.sweep(20)
+            assert_state_equal(sim.get_state(i), ch.get_state(), f"batched chain {i}")
+            assert_series_equal(sim.measure(i), ch.series(), f"batched chain {i}")
+
+
+def test_graph_and_hbm_scatter_paths_match():
+    P = _pm()
+    cfg = CASES["8x8_grid2x2x2"]
+    ch = O.Chain(**cfg)
+    ch.sweep(15)
+    ref = ch.get_state()
+    for mode, graph in [(2, False), (0, True), (2, True)]:
+        say(f"[paths] scatter_mode={mode} graph={graph}")
+        with P.Sim(P.make_params(**cfg), scatter_mode=mode, use_graph=graph) as sim:
+            sim.sweep(15)
+            assert sim.status() == 0
+            assert_state_equal(sim.get_state(), ref, f"mode {mode} graph {graph}")
+
+
+def test_series_ring_drains():
+    """More sweeps than the device ring holds: records are drained in order."""
+    P = _pm()
+    cfg = CASES["4x4_b2"]
+    ch = O.Chain(**cfg)
+    ch.sweep(70)
+    with P.Sim(P.make_params(**cfg), series_cap=16) as sim:
+        sim.sweep(70)
+        assert_series_equal(sim.measure(), ch.series(), "ring")
+
+
+def test_overflow_is_reported():
+    """An event capacity far too small is detected, not written past."""
+    P = _pm()
+    cfg = dict(L=8, beta=8.0, V=0.0, mu=0.0, eta=0.1, seed=1)
+    with P.Sim(P.make_params(**cfg), event_cap=8) as sim:
+        sim.sweep(3)
+        assert sim.status() == P.PMWA_EOVERFLOW
