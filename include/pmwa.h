@@ -144,6 +144,15 @@ int pmwa_set_state(pmwa_t* h, int chain, const uint8_t* bstate,
 
 int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out);
 
+/* Device time per phase.  While enabled, every phase launched by pmwa_sweep
+   or pmwa_phase is bracketed by two HIP events recorded on the handle's
+   stream (graph replay is bypassed so each kernel has its own pair; recording
+   does not synchronise).  pmwa_phase_times synchronises, returns the summed
+   milliseconds and launch counts of phases 1..7 in ms[0..6] and
+   launches[0..6], and resets the accumulators. */
+int pmwa_set_timing(pmwa_t* h, int enable);
+int pmwa_phase_times(pmwa_t* h, double* ms, int64_t* launches);
+
 /* Events per (site, slab) a chain would be given by default. */
 int pmwa_default_event_cap(const pmwa_params* p);
 

@@ -67,10 +67,16 @@ struct pmwa_handle {
          *d_blk_bsx = nullptr, *d_blk_bsy = nullptr;
     int nblk_v = 0, nblk_r = 0, nblk_s = 0, nblk_bt = 0, nblk_bsx = 0, nblk_bsy = 0;
     size_t lds_bytes = 0;
+    size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
     int64_t ev_total = 0, site_slabs = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool own_stream = false;
+    // phase timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_phase;          // phase of the pair (2i, 2i+1)
+    size_t ev_used = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -277,7 +283,29 @@ static int upload_table(const std::vector<int2>& t, int2** dst, int* n)
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
+static int launch_kernel(pmwa_t* h, int phase);
+
 static int launch_phase(pmwa_t* h, int phase)
+{
+    if (!h->timing) return launch_kernel(h, phase);
+    if (h->ev_used + 2 > h->ev_pool.size()) {
+        for (int i = 0; i < 2; i++) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            h->ev_pool.push_back(e);
+        }
+    }
+    hipEvent_t e0 = h->ev_pool[h->ev_used], e1 = h->ev_pool[h->ev_used + 1];
+    HIPCHK(hipEventRecord(e0, h->stream));
+    int rc = launch_kernel(h, phase);
+    HIPCHK(hipEventRecord(e1, h->stream));
+    if (h->ev_phase.size() < h->ev_used / 2 + 1) h->ev_phase.resize(h->ev_used / 2 + 1);
+    h->ev_phase[h->ev_used / 2] = phase;
+    h->ev_used += 2;
+    return rc;
+}
+
+static int launch_kernel(pmwa_t* h, int phase)
 {
     hipStream_t s = h->stream;
     switch (phase) {
@@ -294,10 +322,10 @@ static int launch_phase(pmwa_t* h, int phase)
         if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(128), 0, s, h->P, h->d_blk_bt);
         break;
     case 5:
-        if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(128), 0, s, h->P, h->d_blk_bsx, 0);
+        if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsx, 0);
         break;
     case 6:
-        if (h->nblk_bsy) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsy), dim3(128), 0, s, h->P, h->d_blk_bsy, 1);
+        if (h->nblk_bsy) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsy), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsy, 1);
         break;
     case 7:
         hipLaunchKernelGGL(k_finish, dim3((unsigned)h->ch.size()), dim3(256), 0, s, h->P);
@@ -363,6 +391,7 @@ void pmwa_destroy(pmwa_t* h)
     (void)hipStreamSynchronize(h->stream);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
@@ -421,7 +450,7 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     if (lds_max > 160 * 1024) lds_max = 160 * 1024;
     const size_t fixed = 256 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
-    const size_t per_node = 5 * 4 + 1;
+    const size_t per_node = 4 + 4 * 2 + 1;   // tick, nxt, prv, aux, wl (16-bit), flags
     // nodes wanted: the largest expected domain with margin
     double want = 0.0;
     for (auto& hc : h->ch) {
@@ -432,6 +461,7 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     if (h->opts.scatter_mode != 2 && fixed_al + 64 * per_node < lds_max) {
         lds_nodes = (lds_max - fixed_al) / per_node;
         lds_nodes = std::min<size_t>(lds_nodes, (size_t)std::ceil(want));
+        lds_nodes = std::min<size_t>(lds_nodes, 65520);
         lds_nodes &= ~(size_t)15;
     }
     h->P.lds_nodes = (int32_t)lds_nodes;
@@ -490,8 +520,16 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     if (!r2) { block_table(h->ch, 256, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_dom, t); r2 = upload_table(t, &h->d_blk_s, &h->nblk_s); }
     if (!r2) { block_table(h->ch, 128, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
-    if (!r2) { block_table(h->ch, 128, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
-    if (!r2) { block_table(h->ch, 128, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
+    if (!r2) { block_table(h->ch, 1, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
+    if (!r2) { block_table(h->ch, 1, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
+    {
+        int maxcap = 0;
+        for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
+        h->bs_lds = (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2);
+        if (h->bs_lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)h->bs_lds);
+    }
     if (r2) { pmwa_destroy(h); return r2; }
     // the empty configuration
     if (hipMemsetAsync(h->P.cnt, 0, su * sizeof(int32_t), h->stream) != hipSuccess ||
@@ -545,7 +583,7 @@ static int build_graph(pmwa_t* h)
 int pmwa_sweep(pmwa_t* h, int64_t n)
 {
     if (!h || n < 0) return PMWA_EINVAL;
-    const bool graph = h->opts.use_graph != 0;
+    const bool graph = h->opts.use_graph != 0 && !h->timing;
     if (graph && !h->gexec) {
         int rc = build_graph(h);
         if (rc) return rc;
@@ -595,6 +633,29 @@ int pmwa_measure(pmwa_t* h, int chain, pmwa_obs* out, int64_t max_rows, int64_t*
     rc = read_flags(h, f);
     if (rc) return rc;
     return flag_code(f[chain]);
+}
+
+int pmwa_set_timing(pmwa_t* h, int enable)
+{
+    if (!h) return PMWA_EINVAL;
+    h->timing = enable != 0;
+    return PMWA_OK;
+}
+
+int pmwa_phase_times(pmwa_t* h, double* ms, int64_t* launches)
+{
+    if (!h || !ms || !launches) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < 7; i++) { ms[i] = 0.0; launches[i] = 0; }
+    for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, h->ev_pool[i], h->ev_pool[i + 1]));
+        const int ph = h->ev_phase[i / 2];
+        ms[ph - 1] += t;
+        launches[ph - 1] += 1;
+    }
+    h->ev_used = 0;
+    return PMWA_OK;
 }
 
 int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out)

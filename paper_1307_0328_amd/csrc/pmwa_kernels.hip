@@ -259,80 +259,157 @@ __global__ void __launch_bounds__(256) k_assemble(Pools P, const int2* __restric
 // Steps 5-6: worm scattering, N_cycle cycles over the domain's worm list,
 // then the measurement.  One wavefront per space-time domain; the domain's
 // worldlines become doubly linked node lists (per site, between two boundary
-// sentinels) held in LDS when they fit, else in an HBM scratch region.
+// sentinels) held in LDS with 16-bit links when they fit, else in an HBM
+// scratch region with 32-bit links.
 // ===========================================================================
+template <typename Idx>
 struct Nodes {
     int32_t* tick;
-    uint32_t* nxt;
-    uint32_t* prv;
-    uint32_t* aux;   // partner end of a vertex
+    Idx* nxt;
+    Idx* prv;
+    Idx* aux;        // partner end of a vertex
     uint8_t* fl;
-    uint32_t* wl;    // worm list
+    Idx* wl;         // worm list
 };
 
-// One attempt of one worm (Step 5), with legs measured with the moving worm
-// removed so that L_min is the same before and after (Eq. (DB)).
-PMWA_DEV void worm_step(Nodes& A, uint32_t w, Stream& rs, const double* __restrict__ scat)
-{
-    const uint32_t fw = A.fl[w];
-    const bool up = fw & F_DIRUP;
-    const uint32_t x = up ? A.nxt[w] : A.prv[w];
-    const uint32_t fx = A.fl[x];
-    if (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) { A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
-    const int vd = (int)((fx >> 1) & 3u);
-    const bool xa = vd < 2;
-    const uint32_t y = A.aux[x];
-    const uint32_t Va = xa ? x : y, Vc = xa ? y : x;
-    const int32_t t = A.tick[x];
-    const uint32_t pw = A.prv[w], nw = A.nxt[w];
-    const uint32_t pa0 = A.prv[Va], na0 = A.nxt[Va], pc0 = A.prv[Vc], nc0 = A.nxt[Vc];
-    const uint32_t pa = pa0 == w ? pw : pa0, na = na0 == w ? nw : na0;
-    const uint32_t pc = pc0 == w ? pw : pc0, nc = nc0 == w ? nw : nc0;
-    long long L[4];
-    L[0] = (long long)t - (A.tick[pa] + (long long)(A.fl[pa] & F_WORM));
-    L[1] = (long long)t - (A.tick[pc] + (long long)(A.fl[pc] & F_WORM));
-    L[2] = (long long)A.tick[na] - t;
-    L[3] = (long long)A.tick[nc] - t;
-    const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
-    long long Lmin = L[0];
-    for (int j = 1; j < 4; j++) Lmin = L[j] < Lmin ? L[j] : Lmin;
-    const long long Li = L[i];
-    const uint64_t r = below(rs.next(), (uint64_t)Li);
-    if ((long long)r >= Lmin) { A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
-    // vertex roots with the worm in place
-    const int S = (int)(((A.fl[pa0] >> 3) & 1u) | (((A.fl[pc0] >> 3) & 1u) << 1)
-                      | (((A.fl[Va] >> 3) & 1u) << 2) | (((A.fl[Vc] >> 3) & 1u) << 3));
-    const int S0 = S ^ (1 << i);
-    const double uu = u53(rs.next());
-    int j = 0;
-    while (j < 3 && !(uu < scat[S0 * 16 + i * 4 + j])) j++;
-    const long long Lj = j == 0 ? L[0] : j == 1 ? L[1] : j == 2 ? L[2] : L[3];
-    const uint64_t r2 = below(rs.next(), (uint64_t)Lj);
-    // remove the worm from leg i
-    if (i >= 2) A.fl[x] = (uint8_t)((A.fl[x] & ~F_UP) | (fw & F_UP));
-    A.nxt[pw] = nw;
-    A.prv[nw] = pw;
-    // insert it on leg j, next to the vertex end Vy
-    const uint32_t Vy = (j & 1) ? Vc : Va;
-    uint32_t Pn, Nn;
-    uint32_t newup;
-    if (j >= 2) {
-        Pn = Vy; Nn = A.nxt[Vy];
-        newup = A.fl[Vy] & F_UP;
-        A.fl[Vy] = (uint8_t)(A.fl[Vy] ^ F_UP);
-    } else {
-        Nn = Vy; Pn = A.prv[Vy];
-        newup = (A.fl[Pn] & F_UP) ^ F_UP;
+// Random words of one unit, 128 at a time: lane l holds block 64*b + l of
+// batch b (words 2j, 2j+1 of block j); the serial chain reads them with
+// readlane.  Same words, same order as Stream::next().
+struct RngBatch {
+    uint32_t k0, k1, c1, c2, c3, cursor;
+    uint32_t o0, o1, o2, o3;
+    PMWA_DEV void init(const ChainDev& C, uint32_t sweep, uint32_t kind, uint32_t unit)
+    {
+        k0 = C.key0; k1 = C.key1; c1 = unit; c2 = sweep; c3 = (C.chain_id << 8) | kind;
+        cursor = 0;
     }
-    A.tick[w] = (j >= 2) ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
-    A.fl[w] = (uint8_t)(F_WORM | (j >= 2 ? F_DIRUP : 0u) | newup);
-    A.prv[w] = Pn;
-    A.nxt[w] = Nn;
-    A.nxt[Pn] = w;
-    A.prv[Nn] = w;
+    PMWA_DEV uint64_t next()
+    {
+        const uint32_t b = cursor & 127u;
+        if (b == 0) {
+            uint32_t o[4];
+            philox10(((cursor >> 7) << 6) + (uint32_t)threadIdx.x, c1, c2, c3, k0, k1, o);
+            o0 = o[0]; o1 = o[1]; o2 = o[2]; o3 = o[3];
+        }
+        const int ln = (int)(b >> 1);
+        uint32_t lo, hi;
+        if (b & 1u) { lo = __builtin_amdgcn_readlane(o2, ln); hi = __builtin_amdgcn_readlane(o3, ln); }
+        else { lo = __builtin_amdgcn_readlane(o0, ln); hi = __builtin_amdgcn_readlane(o1, ln); }
+        cursor++;
+        return ((uint64_t)hi << 32) | lo;
+    }
+};
+
+// floor(w * n / 2^64) for n < 2^32, exact
+PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
+{
+    const uint64_t lo = (uint64_t)(uint32_t)w * n;
+    const uint64_t hi = (uint64_t)(uint32_t)(w >> 32) * n + (lo >> 32);
+    return (uint32_t)(hi >> 32);
 }
 
-// block-wide (one wavefront) exclusive scan helper
+// One attempt of one worm (Step 5).  Legs are measured with the moving worm
+// removed so that L_min is the same before and after the move (Eq. (DB)).
+// Loads come in four dependent levels; every neighbour needed for the move
+// is kept in registers.
+template <typename Idx>
+PMWA_DEV void worm_step(Nodes<Idx>& A, uint32_t w, RngBatch& rb, const double* __restrict__ scat)
+{
+    // level 1: the worm
+    const uint32_t fw = A.fl[w];
+    const uint32_t pw = A.prv[w], nw = A.nxt[w];
+    const bool up = fw & F_DIRUP;
+    const uint32_t x = up ? nw : pw;          // object ahead
+    const uint32_t wf = up ? pw : nw;         // object behind the worm
+    // level 2: the object ahead, and the one behind
+    const uint32_t fx = A.fl[x];
+    const bool lead = threadIdx.x == 0;   // one lane stores; every lane reads
+    if (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) { if (lead) A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
+    const int32_t t = A.tick[x];
+    const uint32_t y = A.aux[x];
+    const uint32_t xf = up ? A.nxt[x] : A.prv[x];   // far neighbour of the vertex end on x
+    const int32_t t_wf = A.tick[wf];
+    const uint32_t f_wf = A.fl[wf];
+    // level 3: the partner end and the far neighbour
+    const uint32_t fy = A.fl[y];
+    const uint32_t yp = A.prv[y], yn = A.nxt[y];
+    const int32_t t_xf = A.tick[xf];
+    const uint32_t f_xf = A.fl[xf];
+    // level 4: the partner's neighbours
+    const int32_t t_yp = A.tick[yp], t_yn = A.tick[yn];
+    const uint32_t f_yp = A.fl[yp];
+
+    const bool xa = ((fx >> 1) & 3u) < 2u;
+    // legs on x (worm excluded): below delimiter, above delimiter
+    long long Lxb, Lxa;
+    if (up) {   // worm below the vertex end: lower delimiter = wf, upper = xf
+        Lxb = (long long)t - (t_wf + (long long)(f_wf & F_WORM));
+        Lxa = (long long)t_xf - t;
+    } else {    // worm above: upper delimiter = wf, lower = xf
+        Lxa = (long long)t_wf - t;
+        Lxb = (long long)t - (t_xf + (long long)(f_xf & F_WORM));
+    }
+    const long long Lyb = (long long)t - (t_yp + (long long)(f_yp & F_WORM));
+    const long long Lya = (long long)t_yn - t;
+    long long L[4];
+    L[0] = xa ? Lxb : Lyb;
+    L[1] = xa ? Lyb : Lxb;
+    L[2] = xa ? Lxa : Lya;
+    L[3] = xa ? Lya : Lxa;
+    const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
+    long long Lmin = L[0];
+    Lmin = L[1] < Lmin ? L[1] : Lmin;
+    Lmin = L[2] < Lmin ? L[2] : Lmin;
+    Lmin = L[3] < Lmin ? L[3] : Lmin;
+    const long long Li = up ? Lxb : Lxa;
+    const uint32_t r = below32(rb.next(), (uint32_t)Li);
+    if ((long long)r >= Lmin) { if (lead) A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
+    // roots with the worm in place
+    const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;    // below the end on x
+    const uint32_t rxa = (fx >> 3) & 1u;
+    const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
+    const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
+                     : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
+    const int S0 = S ^ (1 << i);
+    const double uu = u53(rb.next());
+    const double* row = scat + S0 * 16 + i * 4;
+    const double c0 = row[0], c1 = row[1], c2 = row[2];
+    const int j = uu < c0 ? 0 : uu < c1 ? 1 : uu < c2 ? 2 : 3;
+    const long long Lj = j == 0 ? L[0] : j == 1 ? L[1] : j == 2 ? L[2] : L[3];
+    const uint32_t r2 = below32(rb.next(), (uint32_t)Lj);
+    // move: leave leg i, enter leg j next to the end Vy
+    const uint32_t fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
+    const bool on_x = ((j & 1) != 0) != xa;     // leg j lies on site x
+    const bool above = j >= 2;
+    uint32_t Pn, Nn, newup, fv = 0;
+    if (above) {
+        Pn = on_x ? x : y;
+        Nn = on_x ? (up ? xf : wf) : yn;
+        fv = on_x ? fx_now : fy;
+        newup = fv & F_UP;
+    } else {
+        Nn = on_x ? x : y;
+        Pn = on_x ? (up ? wf : xf) : yp;
+        const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
+        newup = (fp & F_UP) ^ F_UP;
+    }
+    if (lead) {
+        // the worm was above the end on x: that segment takes the worm's state
+        if (!up) A.fl[x] = (uint8_t)fx_now;
+        A.nxt[pw] = (Idx)nw;
+        A.prv[nw] = (Idx)pw;
+        if (above) A.fl[Pn] = (uint8_t)(fv ^ F_UP);
+        A.tick[w] = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
+        A.fl[w] = (uint8_t)(F_WORM | (above ? F_DIRUP : 0u) | newup);
+        A.prv[w] = (Idx)Pn;
+        A.nxt[w] = (Idx)Nn;
+        A.nxt[Pn] = (Idx)w;
+        A.prv[Nn] = (Idx)w;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// one-wavefront exclusive scan
 PMWA_DEV int wave_excl_scan(int v, int& total)
 {
     const int lane = (int)threadIdx.x;
@@ -345,42 +422,58 @@ PMWA_DEV int wave_excl_scan(int v, int& total)
     return x - v;
 }
 
+// expm1(lambda*ell) over the set bits of ell, ascending
+PMWA_DEV double em1_bits(const ChainDev& C, long long ell)
+{
+    double m = 0.0;
+    unsigned long long b = (unsigned long long)ell;
+    while (b) {
+        const int k = __ffsll((long long)b) - 1;
+        const double t = C.E[k];
+        m = (m + t) + m * t;
+        b &= b - 1;
+    }
+    return m;
+}
+
+template <typename Idx>
 PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D,
-                             Nodes A, const int* __restrict__ off, const int* __restrict__ cnt,
+                             Nodes<Idx> A, const int* __restrict__ off, const int* __restrict__ cnt,
                              const double* __restrict__ scat, int NE)
 {
     const int lane = (int)threadIdx.x;
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
     const int nloc = C.nloc, ex = C.ex, ey = C.ey;
     const uint32_t BOT = (uint32_t)NE, TOP = (uint32_t)(NE + nloc);
+    const Idx NIL = (Idx)~(Idx)0;
 
     // 1. nodes from the events of the domain's sites
     for (int idx = lane; idx < NE; idx += 64) {
         int lo = 0, hi = nloc - 1;           // site s with off[s] <= idx < off[s+1]
         while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
+            const int mid = (lo + hi + 1) >> 1;
             if (off[mid] <= idx) lo = mid; else hi = mid - 1;
         }
         const int s = lo, j = idx - off[s];
         const uint2 e = P.ev[ev_base(C, k, dsp, s) + (long long)j * nloc];
         A.tick[idx] = (int32_t)e.x;
         A.fl[idx] = (uint8_t)(e.y & 15u);
-        A.prv[idx] = j > 0 ? (uint32_t)idx - 1 : BOT + s;
-        A.nxt[idx] = j + 1 < cnt[s] ? (uint32_t)idx + 1 : TOP + s;
-        A.aux[idx] = NONE;
+        A.prv[idx] = (Idx)(j > 0 ? (uint32_t)idx - 1 : BOT + s);
+        A.nxt[idx] = (Idx)(j + 1 < cnt[s] ? (uint32_t)idx + 1 : TOP + s);
+        A.aux[idx] = NIL;
     }
     for (int s = lane; s < nloc; s += 64) {
         const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
         A.tick[BOT + s] = C.T[k];
         A.fl[BOT + s] = (uint8_t)(F_SBOT | (bsv ? F_UP : 0u));
-        A.nxt[BOT + s] = cnt[s] ? (uint32_t)off[s] : TOP + s;
-        A.prv[BOT + s] = NONE;
-        A.aux[BOT + s] = NONE;
+        A.nxt[BOT + s] = (Idx)(cnt[s] ? (uint32_t)off[s] : TOP + s);
+        A.prv[BOT + s] = NIL;
+        A.aux[BOT + s] = NIL;
         A.tick[TOP + s] = C.T[k + 1];
         A.fl[TOP + s] = (uint8_t)F_STOP;
-        A.prv[TOP + s] = cnt[s] ? (uint32_t)(off[s] + cnt[s] - 1) : BOT + s;
-        A.nxt[TOP + s] = NONE;
-        A.aux[TOP + s] = NONE;
+        A.prv[TOP + s] = (Idx)(cnt[s] ? (uint32_t)(off[s] + cnt[s] - 1) : BOT + s);
+        A.nxt[TOP + s] = NIL;
+        A.aux[TOP + s] = NIL;
     }
     __syncthreads();
     // 2. partner ends of vertices; bonds leaving the domain are boundary
@@ -390,7 +483,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         if (f & F_WORM) continue;
         int lo = 0, hi = nloc - 1;
         while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
+            const int mid = (lo + hi + 1) >> 1;
             if (off[mid] <= idx) lo = mid; else hi = mid - 1;
         }
         const int s = lo, lx = s % ex, ly = s / ex;
@@ -405,16 +498,16 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         const int32_t t = A.tick[idx];
         int a = off[s2], b = off[s2] + cnt[s2];   // first node of s2 with tick >= t
         while (a < b) {
-            int mid = (a + b) >> 1;
+            const int mid = (a + b) >> 1;
             if (A.tick[mid] < t) a = mid + 1; else b = mid;
         }
         uint32_t found = NONE;
         for (int m = a; m < off[s2] + cnt[s2] && A.tick[m] == t; m++) {
-            uint32_t g = A.fl[m];
+            const uint32_t g = A.fl[m];
             if (!(g & F_WORM) && (int)((g >> 1) & 3u) == (vd ^ 2)) { found = (uint32_t)m; break; }
         }
         if (found == NONE) atomicOr(&P.flags[chain], FL_STATE);
-        A.aux[idx] = found;
+        A.aux[idx] = (Idx)found;
     }
     // 3. worm list in (site, slot) order = node order
     int nw = 0;
@@ -423,7 +516,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         const int isw = (idx < NE) && (A.fl[idx] & F_WORM);
         int tot;
         const int pos = wave_excl_scan(isw, tot);
-        if (isw) A.wl[nw + pos] = (uint32_t)idx;
+        if (isw) A.wl[nw + pos] = (Idx)idx;
         nw += tot;
     }
     __syncthreads();
@@ -431,10 +524,10 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
 
     // 4. N_cycle cycles, worms in list order (every lane runs the same
     //    serial chain of decisions)
-    Stream rs;
-    rs.init(C, (uint32_t)P.sweep[chain], RNG_S, (uint32_t)D);
+    RngBatch rb;
+    rb.init(C, (uint32_t)P.sweep[chain], RNG_S, (uint32_t)D);
     for (int cyc = 0; cyc < C.ncycle; cyc++)
-        for (int iw = 0; iw < nw; iw++) worm_step(A, A.wl[iw], rs, scat);
+        for (int iw = 0; iw < nw; iw++) worm_step(A, (uint32_t)A.wl[iw], rb, scat);
     __syncthreads();
 
     // 5. measurement (Step 6) and write-back, one lane per site
@@ -454,7 +547,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                 occ += (long long)stt * (2LL * C.T[k + 1] - last);
                 const long long ell = (long long)C.T[k + 1] - ilo;
                 if (ell > 0) {
-                    const double th = tanh_ell(C, ell);
+                    const double m = em1_bits(C, ell);
+                    const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
                     qimp += (double)ell * (par ? 1.0 / th : th);
                 }
                 break;
@@ -471,7 +565,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             } else {
                 const long long ell = (long long)tk - ilo;
                 if (ell > 0) {
-                    const double th = tanh_ell(C, ell);
+                    const double m = em1_bits(C, ell);
+                    const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
                     qimp += (double)ell * (par ? 1.0 / th : th);
                 }
                 if (((f >> 1) & 3u) < 2) {
@@ -504,7 +599,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     }
 }
 
-// dynamic LDS: [scat 256 doubles][off nloc+1][cnt nloc][nodes...]
+// dynamic LDS: [scat 256 doubles][off nloc+1][cnt nloc][nodes: tick 4B, nxt, prv,
+// aux, wl 2B each, fl 1B]
 __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict__ blk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -539,20 +635,21 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
 
     const size_t fixed = 256 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
-    if (NN <= P.lds_nodes) {
+    const int cap_l = P.lds_nodes;
+    if (NN <= cap_l && NN < 65535) {
         unsigned char* p = smem + fixed_al;
-        Nodes A;
-        A.tick = reinterpret_cast<int32_t*>(p); p += (size_t)P.lds_nodes * 4;
-        A.nxt = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
-        A.prv = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
-        A.aux = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
-        A.wl = reinterpret_cast<uint32_t*>(p); p += (size_t)P.lds_nodes * 4;
+        Nodes<uint16_t> A;
+        A.tick = reinterpret_cast<int32_t*>(p); p += (size_t)cap_l * 4;
+        A.nxt = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
+        A.prv = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
+        A.aux = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
+        A.wl = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
         A.fl = reinterpret_cast<uint8_t*>(p);
         scatter_domain(P, C, bt.x, D, A, off, cnt, scat, NE);
     } else {
         if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
         const long long b = C.scr_off + (long long)D * C.scr_nodes;
-        Nodes A;
+        Nodes<uint32_t> A;
         A.tick = P.s_tick + b;
         A.nxt = P.s_nxt + b;
         A.prv = P.s_prv + b;
@@ -674,15 +771,103 @@ __global__ void __launch_bounds__(128) k_btemporal(Pools P, const int2* __restri
     }
 }
 
-// Step 2, Eq. (ParaSpace): one lane per bond crossing a spatial domain
-// boundary in direction d (owned by the left/lower domain), its vertices in
-// tick order; heat bath over the six allowed root states with the leg
-// weights f, then the worms of the four legs are regenerated.
-__global__ void __launch_bounds__(128) k_bspatial(Pools P, const int2* __restrict__ blk, int d)
+// Step 2, Eq. (ParaSpace): one wavefront per bond crossing a spatial domain
+// boundary in direction d (owned by the left/lower domain).  The two site
+// arrays of the bond, slab by slab, sit in LDS; its vertices are visited in
+// tick order; a heat bath over the six allowed root states with the leg
+// weights f picks the new roots, then the worms of the four legs are
+// regenerated.  Searches are wave ballots, edits are wave-parallel shifts;
+// the chain of decisions is the same on every lane.
+PMWA_DEV int wave_first(const uint2* A, int from, int n, int mode, uint32_t arg0, int32_t arg1)
 {
+    // mode 0: vertex with bond direction arg0;  mode 1: vertex with tick arg1 and direction arg0
+    // mode 2: any vertex
+    const int lane = (int)threadIdx.x;
+    for (int base = from; base < n; base += 64) {
+        const int j = base + lane;
+        bool hit = false;
+        if (j < n) {
+            const uint2 e = A[j];
+            const bool v = !ev_worm(e.y);
+            if (mode == 0) hit = v && ev_dir(e.y) == arg0;
+            else if (mode == 1) hit = v && ev_dir(e.y) == arg0 && (int32_t)e.x == arg1;
+            else hit = v;
+        }
+        const unsigned long long m = __ballot(hit);
+        if (m) return base + __ffsll((long long)m) - 1;
+    }
+    return n;
+}
+
+PMWA_DEV int wave_last_vertex(const uint2* A, int upto)
+{
+    const int lane = (int)threadIdx.x;
+    for (int top = upto; top > 0; top -= 64) {
+        const int j = top - 64 + lane;
+        const bool hit = j >= 0 && !ev_worm(A[j].y);
+        const unsigned long long m = __ballot(hit);
+        if (m) return top - 64 + (63 - __clzll((long long)m));
+    }
+    return -1;
+}
+
+// replace A[lo, hi) by nw[0..m) in LDS, one wavefront
+PMWA_DEV bool wave_replace(uint2* A, int& n, int cap, int lo, int hi, const uint2* nw, int m)
+{
+    const int lane = (int)threadIdx.x;
+    const int delta = m - (hi - lo);
+    if (n + delta > cap) return false;
+    if (delta > 0) {
+        for (int top = n; top > hi; top -= 64) {
+            const int j = top - 64 + lane;
+            uint2 v = make_uint2(0, 0);
+            const bool ok = j >= hi;
+            if (ok) v = A[j];
+            __builtin_amdgcn_wave_barrier();
+            if (ok) A[j + delta] = v;
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else if (delta < 0) {
+        for (int base = hi; base < n; base += 64) {
+            const int j = base + lane;
+            uint2 v = make_uint2(0, 0);
+            const bool ok = j < n;
+            if (ok) v = A[j];
+            __builtin_amdgcn_wave_barrier();
+            if (ok) A[j + delta] = v;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    for (int j = lane; j < m; j += 64) A[lo + j] = nw[j];
+    __builtin_amdgcn_wave_barrier();
+    n += delta;
+    return true;
+}
+
+// worms of one interval written to LDS (all lanes write the same values)
+PMWA_DEV int gen_worms_lds(const ChainDev& C, Stream& rs, int32_t base, long long ell, int sigma,
+                           int p, uint2* out, unsigned int* flag)
+{
+    int32_t off[NWL];
+    uint8_t dirs[NWL];
+    const int n = sample_worms(C, rs, ell, sigma, off, dirs, flag);
+    int s = p;
+    for (int w = 0; w < n; w++) {
+        s ^= 1;
+        if (threadIdx.x == 0)
+            out[w] = make_uint2((uint32_t)(base + off[w]), 1u | ((uint32_t)dirs[w] << 1) | ((uint32_t)s << 3));
+    }
+    return n;
+}
+
+// dynamic LDS: A[cap] B[cap] W[4][NWL]
+__global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict__ blk, int d)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
-    const int u = bt.y + (int)threadIdx.x;
+    const int u = bt.y;
+    const int lane = (int)threadIdx.x;
     const int nb_units = d == 0 ? (C.dom_x > 1 ? C.Ly * C.dom_x : 0) : (C.dom_y > 1 ? C.Lx * C.dom_y : 0);
     if (u >= nb_units || P.flags[bt.x] != 0) return;
     unsigned int* flag = &P.flags[bt.x];
@@ -693,83 +878,101 @@ __global__ void __launch_bounds__(128) k_bspatial(Pools P, const int2* __restric
     int dspa, sla, dspc, slc;
     site_split(C, a, dspa, sla);
     site_split(C, c, dspc, slc);
-    const int nt = C.ntau;
+    const int nt = C.ntau, cap = C.cap;
+    uint2* A = reinterpret_cast<uint2*>(smem);
+    uint2* B = A + cap;
+    uint2* Wk = B + cap;       // 4 legs x NWL new worms
     Stream rs;
     rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)(2LL * a + d));
-    const int ALLOWED[6] = {0, 5, 6, 9, 10, 15};
-    uint2 w0[NWL], w1[NWL], w2[NWL], w3[NWL];
     for (int k = 0; k < nt; k++) {
         const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
         const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
-        SiteArr A{P.ev + ev_base(C, k, dspa, sla), C.nloc, P.cnt[cua], C.cap};
-        SiteArr B{P.ev + ev_base(C, k, dspc, slc), C.nloc, P.cnt[cuc], C.cap};
+        const uint2* GA = P.ev + ev_base(C, k, dspa, sla);
+        const uint2* GB = P.ev + ev_base(C, k, dspc, slc);
+        int na = P.cnt[cua], nb = P.cnt[cuc];
+        for (int j = lane; j < na; j += 64) A[j] = GA[(long long)j * C.nloc];
+        for (int j = lane; j < nb; j += 64) B[j] = GB[(long long)j * C.nloc];
+        __syncthreads();
         const int bsa = P.bs[C.bs_off + unit_su(C, k, dspa, sla)];
         const int bsc = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
         const int bsa1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspa, sla)];
         const int bsc1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspc, slc)];
+        bool dirty = false, fail = false;
         int ja = 0;
         for (;;) {
-            while (ja < A.n) {
-                const uint2 e = A.get(ja);
-                if (!ev_worm(e.y) && (int)ev_dir(e.y) == d) break;
-                ja++;
-            }
-            if (ja >= A.n) break;
-            const int32_t t = (int32_t)A.get(ja).x;
-            int jc = 0;
-            while (jc < B.n) {
-                const uint2 e = B.get(jc);
-                if ((int32_t)e.x == t && !ev_worm(e.y) && (int)ev_dir(e.y) == d + 2) break;
-                jc++;
-            }
-            if (jc >= B.n) { atomicOr(flag, FL_STATE); return; }
+            ja = wave_first(A, ja, na, 0, (uint32_t)d, 0);
+            if (ja >= na) break;
+            dirty = true;
+            const int32_t t = (int32_t)A[ja].x;
+            const int jc = wave_first(B, 0, nb, 1, (uint32_t)(d + 2), t);
+            if (jc >= nb) { if (lane == 0) atomicOr(flag, FL_STATE); fail = true; break; }
             // legs, worms ignored
-            int la = ja - 1; while (la >= 0 && ev_worm(A.get(la).y)) la--;
-            int lc = jc - 1; while (lc >= 0 && ev_worm(B.get(lc).y)) lc--;
-            int ha = ja + 1; while (ha < A.n && ev_worm(A.get(ha).y)) ha++;
-            int hc = jc + 1; while (hc < B.n && ev_worm(B.get(hc).y)) hc++;
-            const int32_t lo_a = la >= 0 ? (int32_t)A.get(la).x : C.T[k];
-            const int p1 = la >= 0 ? (int)ev_up(A.get(la).y) : bsa;
-            const int32_t lo_c = lc >= 0 ? (int32_t)B.get(lc).x : C.T[k];
-            const int p2 = lc >= 0 ? (int)ev_up(B.get(lc).y) : bsc;
-            const int32_t hi_a = ha < A.n ? (int32_t)A.get(ha).x : C.T[k + 1];
-            const int q1 = ha < A.n ? (int)ev_up(A.get(ha - 1).y) : bsa1;
-            const int32_t hi_c = hc < B.n ? (int32_t)B.get(hc).x : C.T[k + 1];
-            const int q2 = hc < B.n ? (int)ev_up(B.get(hc - 1).y) : bsc1;
+            const int la = wave_last_vertex(A, ja);
+            const int lc = wave_last_vertex(B, jc);
+            const int ha = wave_first(A, ja + 1, na, 2, 0, 0);
+            const int hc = wave_first(B, jc + 1, nb, 2, 0, 0);
+            const int32_t lo_a = la >= 0 ? (int32_t)A[la].x : C.T[k];
+            const int p1 = la >= 0 ? (int)ev_up(A[la].y) : bsa;
+            const int32_t lo_c = lc >= 0 ? (int32_t)B[lc].x : C.T[k];
+            const int p2 = lc >= 0 ? (int)ev_up(B[lc].y) : bsc;
+            const int32_t hi_a = ha < na ? (int32_t)A[ha].x : C.T[k + 1];
+            const int q1 = ha < na ? (int)ev_up(A[ha - 1].y) : bsa1;
+            const int32_t hi_c = hc < nb ? (int32_t)B[hc].x : C.T[k + 1];
+            const int q2 = hc < nb ? (int)ev_up(B[hc - 1].y) : bsc1;
             const long long l0 = (long long)t - lo_a, l1 = (long long)t - lo_c;
             const long long l2 = (long long)hi_a - t, l3 = (long long)hi_c - t;
+            // f_0 = cosh, f_1 = sinh of eta*Delta*l for the four legs
+            double f[4][2];
+            {
+                const long long ls[4] = {l0, l1, l2, l3};
+                for (int g = 0; g < 4; g++) {
+                    const double m = em1(C, ls[g]);
+                    const double dd = 2.0 * (1.0 + m);
+                    f[g][0] = 1.0 + (m * m) / dd;
+                    f[g][1] = (m * (2.0 + m)) / dd;
+                }
+            }
             double W[6];
+            const int ALLOWED[6] = {0, 5, 6, 9, 10, 15};
             for (int m = 0; m < 6; m++) {
                 const int S = ALLOWED[m];
                 const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-                W[m] = (((fleg(C, p1 ^ s1, l0) * fleg(C, p2 ^ s2, l1)) * fleg(C, s1p ^ q1, l2))
-                        * fleg(C, s2p ^ q2, l3)) * C.vw[S];
+                W[m] = (((f[0][p1 ^ s1] * f[1][p2 ^ s2]) * f[2][s1p ^ q1]) * f[3][s2p ^ q2]) * C.vw[S];
             }
             const int m = choose(W, u53(rs.next()));
             const int S = ALLOWED[m];
             const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-            const int n0 = gen_worms(C, rs, lo_a, l0, p1 ^ s1, p1, w0, flag);
-            const int n1 = n0 < 0 ? -1 : gen_worms(C, rs, lo_c, l1, p2 ^ s2, p2, w1, flag);
-            const int n2 = n1 < 0 ? -1 : gen_worms(C, rs, t, l2, s1p ^ q1, s1p, w2, flag);
-            const int n3 = n2 < 0 ? -1 : gen_worms(C, rs, t, l3, s2p ^ q2, s2p, w3, flag);
-            if (n3 < 0) return;
-            uint2 va = A.get(ja), vc = B.get(jc);
-            va.y = (va.y & ~8u) | ((uint32_t)s1p << 3);
-            vc.y = (vc.y & ~8u) | ((uint32_t)s2p << 3);
-            A.put(ja, va);
-            B.put(jc, vc);
-            const int na_before = A.n;
-            if (!A.replace(ja + 1, ha, w2, n2) || !A.replace(la + 1, ja, w0, n0) ||
-                !B.replace(jc + 1, hc, w3, n3) || !B.replace(lc + 1, jc, w1, n1)) {
-                atomicOr(flag, FL_OVERFLOW);
-                return;
+            const int n0 = gen_worms_lds(C, rs, lo_a, l0, p1 ^ s1, p1, Wk, flag);
+            const int n1 = n0 < 0 ? -1 : gen_worms_lds(C, rs, lo_c, l1, p2 ^ s2, p2, Wk + NWL, flag);
+            const int n2 = n1 < 0 ? -1 : gen_worms_lds(C, rs, t, l2, s1p ^ q1, s1p, Wk + 2 * NWL, flag);
+            const int n3 = n2 < 0 ? -1 : gen_worms_lds(C, rs, t, l3, s2p ^ q2, s2p, Wk + 3 * NWL, flag);
+            if (n3 < 0) { fail = true; break; }
+            __syncthreads();
+            if (lane == 0) {
+                A[ja].y = (A[ja].y & ~8u) | ((uint32_t)s1p << 3);
+                B[jc].y = (B[jc].y & ~8u) | ((uint32_t)s2p << 3);
             }
-            // the vertex moved by the change of the lower leg's worm count
-            ja = ja + (n0 - (ja - (la + 1))) + 1;
-            (void)na_before;
+            __syncthreads();
+            if (!wave_replace(A, na, cap, ja + 1, ha, Wk + 2 * NWL, n2) ||
+                !wave_replace(A, na, cap, la + 1, ja, Wk, n0) ||
+                !wave_replace(B, nb, cap, jc + 1, hc, Wk + 3 * NWL, n3) ||
+                !wave_replace(B, nb, cap, lc + 1, jc, Wk + NWL, n1)) {
+                if (lane == 0) atomicOr(flag, FL_OVERFLOW);
+                fail = true;
+                break;
+            }
+            __syncthreads();
+            ja = la + 1 + n0 + 1;   // just past the vertex
         }
-        P.cnt[cua] = A.n;
-        P.cnt[cuc] = B.n;
+        if (fail) return;
+        if (dirty) {
+            uint2* OA = P.ev + ev_base(C, k, dspa, sla);
+            uint2* OB = P.ev + ev_base(C, k, dspc, slc);
+            for (int j = lane; j < na; j += 64) OA[(long long)j * C.nloc] = A[j];
+            for (int j = lane; j < nb; j += 64) OB[(long long)j * C.nloc] = B[j];
+            if (lane == 0) { P.cnt[cua] = na; P.cnt[cuc] = nb; }
+        }
+        __syncthreads();
     }
 }
 

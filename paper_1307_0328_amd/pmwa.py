@@ -19,7 +19,7 @@ PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
 
 EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
-           "pmwa_destroy", "pmwa_strerror"]
+           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times"]
 
 
 class pmwa_params(C.Structure):
@@ -74,6 +74,8 @@ def lib():
         L.pmwa_default_event_cap.argtypes = [P(pmwa_params)]
         L.pmwa_destroy.argtypes = [C.c_void_p]
         L.pmwa_destroy.restype = None
+        L.pmwa_set_timing.argtypes = [C.c_void_p, C.c_int]
+        L.pmwa_phase_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -168,6 +170,17 @@ def pmwa_default_event_cap(p):
     return lib().pmwa_default_event_cap(C.byref(p))
 
 
+def pmwa_set_timing(h, enable):
+    _check(lib().pmwa_set_timing(h, 1 if enable else 0), "pmwa_set_timing")
+
+
+def pmwa_phase_times(h):
+    ms = np.zeros(7)
+    n = np.zeros(7, np.int64)
+    _check(lib().pmwa_phase_times(h, ms.ctypes.data, n.ctypes.data), "pmwa_phase_times")
+    return ms, n
+
+
 def pmwa_destroy(h):
     if h:
         lib().pmwa_destroy(h)
@@ -227,3 +240,9 @@ class Sim:
 
     def info(self, chain=0):
         return pmwa_chain_info(self.h, chain)
+
+    def set_timing(self, enable=True):
+        pmwa_set_timing(self.h, enable)
+
+    def phase_times(self):
+        return pmwa_phase_times(self.h)

@@ -1,0 +1,75 @@
+"""Seeded, synthetic workloads: chain parameters only.
+
+This module holds no arithmetic of the method; it only lists lattice sizes,
+couplings, domain grids, seeds and stream ids.  Both the GPU library and the
+oracle consume these parameter sets.
+
+The paper's workloads are model parameters of the hard-core Bose-Hubbard
+model on square lattices (its Figs. 2-3 and Supplemental S-II: beta*t up to
+128, eta 0.002-0.06, V = 0 or 3, 4-8 domains per edge); the sets below
+follow those shapes at sizes one GPU holds.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def plain_4x4() -> list[dict]:
+    """4x4 periodic lattice, t=1, V=0, mu=0, eta=0.1, beta*t=2, one domain."""
+    return [dict(Lx=4, Ly=4, beta=2.0, t=1.0, V=0.0, mu=0.0, eta=0.1,
+                 dom_x=1, dom_y=1, dom_tau=1, ticks_log2=24, seed=1, chain_id=0)]
+
+
+def single_64() -> list[dict]:
+    """64x64, beta*t=16, t=1, V=1, mu=0.5, eta=0.05, domains 8x8 x 2."""
+    return [dict(Lx=64, Ly=64, beta=16.0, t=1.0, V=1.0, mu=0.5, eta=0.05,
+                 dom_x=8, dom_y=8, dom_tau=2, ticks_log2=24, seed=2, chain_id=0)]
+
+
+def batched_256(n_chains: int = 256, seed: int = 3) -> list[dict]:
+    """Independent chains of uneven shape: L from {16,24,32,48}, beta*t from
+    {4,8,16}, mu from the 16-point grid -2 + 4k/15; V=0, eta=0.05, 4x4
+    spatial domains, one temporal domain.  chain_id = index."""
+    rng = np.random.default_rng(seed)
+    Ls = rng.choice([16, 24, 32, 48], size=n_chains)
+    betas = rng.choice([4.0, 8.0, 16.0], size=n_chains)
+    mus = -2.0 + 4.0 * rng.integers(0, 16, size=n_chains) / 15.0
+    out = []
+    for c in range(n_chains):
+        out.append(dict(Lx=int(Ls[c]), Ly=int(Ls[c]), beta=float(betas[c]), t=1.0, V=0.0,
+                        mu=float(mus[c]), eta=0.05, dom_x=4, dom_y=4, dom_tau=1,
+                        ticks_log2=24, seed=3, chain_id=c))
+    return out
+
+
+def large_2048(L: int = 2048) -> list[dict]:
+    """One large system: L x L at beta*t=16, t=1, V=0, mu=0, eta=0.02, 32x32
+    sites x beta*t 4 per domain (64x64 x 4 domains at L = 2048)."""
+    return [dict(Lx=L, Ly=L, beta=16.0, t=1.0, V=0.0, mu=0.0, eta=0.02,
+                 dom_x=L // 32, dom_y=L // 32, dom_tau=4, ticks_log2=24, seed=4, chain_id=0)]
+
+
+def serving_jobs(n_jobs: int, rate: float = 50.0, seed: int = 4, max_L: int = 256,
+                 sweeps_lo: float = 1e3, sweeps_hi: float = 1e5) -> list[dict]:
+    """Poisson arrivals (mean `rate` per second); each job a chain with L
+    uniform in [16, max_L] (a multiple of 8, domain edge 8 or 16), beta*t
+    uniform in [2, 32], mu uniform in [-2, 2], V in {0, 1}, eta=0.05, sweeps
+    log-uniform in [sweeps_lo, sweeps_hi].  The domain grid is a function of
+    the job's own parameters only."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    jobs = []
+    for j in range(n_jobs):
+        t += rng.exponential(1.0 / rate)
+        L = int(rng.integers(2, max_L // 8 + 1)) * 8
+        beta = float(rng.uniform(2.0, 32.0))
+        mu = float(rng.uniform(-2.0, 2.0))
+        V = float(rng.integers(0, 2))
+        sweeps = int(round(np.exp(rng.uniform(np.log(sweeps_lo), np.log(sweeps_hi)))))
+        edge = 16 if L % 16 == 0 and L >= 32 else 8
+        ntau = max(1, int(np.ceil(beta / 8.0)))
+        jobs.append(dict(arrival=t, sweeps=sweeps,
+                         params=dict(Lx=L, Ly=L, beta=beta, t=1.0, V=V, mu=mu, eta=0.05,
+                                     dom_x=L // edge, dom_y=L // edge, dom_tau=ntau,
+                                     ticks_log2=24, seed=5, chain_id=j)))
+    return jobs
