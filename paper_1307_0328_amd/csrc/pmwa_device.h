@@ -80,6 +80,7 @@ struct Pools {
     uint32_t* s_aux;
     uint8_t* s_fl;
     uint32_t* s_wl;
+    uint32_t* s_own;
     int32_t series_cap;
     int32_t lds_nodes;           // node capacity of the LDS path (0 = off)
 };
@@ -165,27 +166,29 @@ PMWA_DEV long long ev_base(const ChainDev& C, int k, int dsp, int sl)
 // ---------------------------------------------------------------------------
 // element functions of the worm law (hard-core f_qp), from the expm1 table
 // ---------------------------------------------------------------------------
-PMWA_DEV double em1(const ChainDev& C, long long ell)
+// E[k] = expm1(lambda * 2^k) (a copy in LDS); bits of ell in ascending order
+PMWA_DEV double em1(const double* __restrict__ E, long long ell)
 {
     double m = 0.0;
-    for (int k = 0; k < 32; k++) {
-        if ((ell >> k) & 1) {
-            double t = C.E[k];
-            m = (m + t) + m * t;
-        }
+    unsigned long long b = (unsigned long long)ell;
+    while (b) {
+        const int k = __ffsll((long long)b) - 1;
+        const double t = E[k];
+        m = (m + t) + m * t;
+        b &= b - 1;
     }
     return m;
 }
-PMWA_DEV double fleg(const ChainDev& C, int sigma, long long ell)
+PMWA_DEV double fleg(const double* __restrict__ E, int sigma, long long ell)
 {
-    double m = em1(C, ell);
+    double m = em1(E, ell);
     double d = 2.0 * (1.0 + m);
     if (sigma) return (m * (2.0 + m)) / d;
     return 1.0 + (m * m) / d;
 }
-PMWA_DEV double tanh_ell(const ChainDev& C, long long ell)
+PMWA_DEV double tanh_ell(const double* __restrict__ E, long long ell)
 {
-    double m = em1(C, ell);
+    double m = em1(E, ell);
     double d = 2.0 * (1.0 + m);
     return (m * (2.0 + m)) / (d + m * m);
 }
@@ -213,15 +216,15 @@ PMWA_DEV int choose(const double (&W)[N], double u)
 // count by inversion of x^n/n!/f_sigma(x), x = lambda*ell, n <= ell (redraw
 // otherwise); distinct uniform offsets in [0, ell), sorted; one direction
 // bit per worm in ascending order.  Returns n, or -1 on failure (flagged).
-PMWA_DEV int sample_worms(const ChainDev& C, Stream& s, long long ell, int sigma,
-                          int32_t* off, uint8_t* dirs, unsigned int* flag)
+PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, Stream& s, long long ell,
+                          int sigma, int32_t* off, uint8_t* dirs, unsigned int* flag)
 {
     if (ell == 0) {
         if (sigma) atomicOr(flag, FL_SAMPLER);
         return 0;
     }
-    double f = fleg(C, sigma, ell);
-    double x = C.lambda * (double)ell;
+    double f = fleg(E, sigma, ell);
+    double x = lambda * (double)ell;
     double xx = x * x;
     long long nmax = ell < 4096 ? ell : 4096;
     int n = -1;

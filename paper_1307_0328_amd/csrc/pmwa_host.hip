@@ -310,16 +310,16 @@ static int launch_kernel(pmwa_t* h, int phase)
     hipStream_t s = h->stream;
     switch (phase) {
     case 1:
-        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(256), 0, s, h->P, h->d_blk_v);
+        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), 0, s, h->P, h->d_blk_v);
         break;
     case 2:
-        if (h->nblk_r) hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(256), 0, s, h->P, h->d_blk_r);
+        if (h->nblk_r) hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(64), 0, s, h->P, h->d_blk_r);
         break;
     case 3:
         if (h->nblk_s) hipLaunchKernelGGL(k_scatter, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
         break;
     case 4:
-        if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(128), 0, s, h->P, h->d_blk_bt);
+        if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(64), 0, s, h->P, h->d_blk_bt);
         break;
     case 5:
         if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsx, 0);
@@ -395,7 +395,7 @@ void pmwa_destroy(pmwa_t* h)
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
-                    h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->d_blk_v, h->d_blk_r,
+                    h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->d_blk_v, h->d_blk_r,
                     h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -448,9 +448,9 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     size_t lds_max = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds_max) lds_max = prop.maxSharedMemoryPerMultiProcessor;
     if (lds_max > 160 * 1024) lds_max = 160 * 1024;
-    const size_t fixed = 256 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
+    const size_t fixed = 800 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
-    const size_t per_node = 4 + 4 * 2 + 1;   // tick, nxt, prv, aux, wl (16-bit), flags
+    const size_t per_node = 4 + 4 * 2 + 4 + 1;   // tick, nxt, prv, aux, wl (16-bit), owner stamp, flags
     // nodes wanted: the largest expected domain with margin
     double want = 0.0;
     for (auto& hc : h->ch) {
@@ -498,6 +498,7 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     h->P.s_aux = dalloc<uint32_t>(scr, &rc);
     h->P.s_fl = dalloc<uint8_t>(scr, &rc);
     h->P.s_wl = dalloc<uint32_t>(scr, &rc);
+    h->P.s_own = dalloc<uint32_t>(scr, &rc);
     h->d_cd = dalloc<ChainDev>(n_chains, &rc);
     h->d_cdf = dalloc<double>(cdf, &rc);
     if (rc) { pmwa_destroy(h); return rc; }
@@ -516,16 +517,16 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     if (hipMemcpy(h->d_cd, cds.data(), n_chains * sizeof(ChainDev), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_cdf, cdfs.data(), cdf * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         r2 = PMWA_EDEVICE;
-    if (!r2) { block_table(h->ch, 256, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
-    if (!r2) { block_table(h->ch, 256, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
+    if (!r2) { block_table(h->ch, 64, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
+    if (!r2) { block_table(h->ch, 64, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_dom, t); r2 = upload_table(t, &h->d_blk_s, &h->nblk_s); }
-    if (!r2) { block_table(h->ch, 128, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
+    if (!r2) { block_table(h->ch, 64, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
     {
         int maxcap = 0;
         for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
-        h->bs_lds = (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2);
+        h->bs_lds = 32 * sizeof(double) + (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2);
         if (h->bs_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->bs_lds);

@@ -23,11 +23,19 @@ PMWA_DEV bool key_before(const ChainDev& C, int site, uint2 e, int32_t tick, lon
     return bond_id(C, site, (int)ev_dir(e.y)) < bid;
 }
 
-__global__ void __launch_bounds__(256) k_vertex(Pools P, const int2* __restrict__ blk)
+__global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__ blk)
 {
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
+    // Poisson tables of the (at most two) first slabs this block touches
+    __shared__ double s_cdf[2 * KMAXC];
+    const int k_first = bt.y / (2 * C.N);
+    for (int i = (int)threadIdx.x; i < 2 * C.cdf_stride; i += 64) {
+        const int kk = k_first + i / C.cdf_stride;
+        s_cdf[i] = kk < C.ntau ? P.cdf[C.cdf_off + (long long)kk * C.cdf_stride + i % C.cdf_stride] : 2.0;
+    }
+    __syncthreads();
     long long nn = 0;
     if (u < 2 * C.ntau * C.N && P.flags[bt.x] == 0) {
         const int sl = u % C.nloc;
@@ -86,7 +94,9 @@ __global__ void __launch_bounds__(256) k_vertex(Pools P, const int2* __restrict_
 
         Stream rs;
         rs.init(C, sweep, RNG_V, (uint32_t)(bid * C.ntau + k));
-        const double* cdf = P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
+        const double* cdf = (k - k_first < 2) ? s_cdf + (k - k_first) * C.cdf_stride
+                                              : P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
+        const double acc0 = C.acc[0], acc1 = C.acc[1], acc2 = C.acc[2], acc3 = C.acc[3];
         const double u0 = u53(rs.next());
         int n = 0;
         while (!(u0 < cdf[n])) n++;
@@ -129,7 +139,9 @@ __global__ void __launch_bounds__(256) k_vertex(Pools P, const int2* __restrict_
                 ic++;
             }
             const double uu = u53(rs.next());
-            if (uu < C.acc[s_a | (s_c << 1)]) {
+            const int sidx = s_a | (s_c << 1);
+            const double accv = sidx == 0 ? acc0 : sidx == 1 ? acc1 : sidx == 2 ? acc2 : acc3;
+            if (uu < accv) {
                 if (nacc < C.capb)
                     out[(long long)nacc * st] = (uint32_t)tau | ((uint32_t)s_a << 30) | ((uint32_t)s_c << 31);
                 nacc++;
@@ -138,15 +150,9 @@ __global__ void __launch_bounds__(256) k_vertex(Pools P, const int2* __restrict_
         if (nacc > C.capb) { atomicOr(&P.flags[bt.x], FL_OVERFLOW); nacc = C.capb; }
         P.bvc[C.bvc_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.nloc + sl] = nacc;
     }
-    // block sum of the bond occupation integral -> one atomic per block
-    __shared__ long long red[4];
+    // wave sum of the bond occupation integral -> one atomic per block
     for (int o = 32; o > 0; o >>= 1) nn += __shfl_down(nn, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long s = red[0] + red[1] + red[2] + red[3];
-        if (s) atomicAdd(&P.nnacc[bt.x], (unsigned long long)s);
-    }
+    if (threadIdx.x == 0 && nn) atomicAdd(&P.nnacc[bt.x], (unsigned long long)nn);
 }
 
 // ===========================================================================
@@ -154,13 +160,17 @@ __global__ void __launch_bounds__(256) k_vertex(Pools P, const int2* __restrict_
 // vertices of the four bonds of the site, erase all worms, and regenerate
 // them on every interval with Eq. (worm).  Written in place.
 // ===========================================================================
-__global__ void __launch_bounds__(256) k_assemble(Pools P, const int2* __restrict__ blk)
+__global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict__ blk)
 {
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
+    __shared__ double sE[32];
+    if (threadIdx.x < 32) sE[threadIdx.x] = C.E[threadIdx.x];
+    __syncthreads();
     if (u >= C.ntau * C.N || P.flags[bt.x] != 0) return;
     unsigned int* flag = &P.flags[bt.x];
+    const double lambda = C.lambda;
     const int sl = u % C.nloc;
     const int r = u / C.nloc;
     const int dsp = r % C.ndsp, k = r / C.ndsp;
@@ -237,7 +247,7 @@ __global__ void __launch_bounds__(256) k_assemble(Pools P, const int2* __restric
             above = q;
             vdir = best;
         }
-        int n = sample_worms(C, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
+        int n = sample_worms(sE, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
         if (n < 0) return;
         if (out + n + (best >= 0 ? 1 : 0) > C.cap) { atomicOr(flag, FL_OVERFLOW); return; }
         int s = p;
@@ -272,34 +282,6 @@ struct Nodes {
     Idx* wl;         // worm list
 };
 
-// Random words of one unit, 128 at a time: lane l holds block 64*b + l of
-// batch b (words 2j, 2j+1 of block j); the serial chain reads them with
-// readlane.  Same words, same order as Stream::next().
-struct RngBatch {
-    uint32_t k0, k1, c1, c2, c3, cursor;
-    uint32_t o0, o1, o2, o3;
-    PMWA_DEV void init(const ChainDev& C, uint32_t sweep, uint32_t kind, uint32_t unit)
-    {
-        k0 = C.key0; k1 = C.key1; c1 = unit; c2 = sweep; c3 = (C.chain_id << 8) | kind;
-        cursor = 0;
-    }
-    PMWA_DEV uint64_t next()
-    {
-        const uint32_t b = cursor & 127u;
-        if (b == 0) {
-            uint32_t o[4];
-            philox10(((cursor >> 7) << 6) + (uint32_t)threadIdx.x, c1, c2, c3, k0, k1, o);
-            o0 = o[0]; o1 = o[1]; o2 = o[2]; o3 = o[3];
-        }
-        const int ln = (int)(b >> 1);
-        uint32_t lo, hi;
-        if (b & 1u) { lo = __builtin_amdgcn_readlane(o2, ln); hi = __builtin_amdgcn_readlane(o3, ln); }
-        else { lo = __builtin_amdgcn_readlane(o0, ln); hi = __builtin_amdgcn_readlane(o1, ln); }
-        cursor++;
-        return ((uint64_t)hi << 32) | lo;
-    }
-};
-
 // floor(w * n / 2^64) for n < 2^32, exact
 PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 {
@@ -308,105 +290,183 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
     return (uint32_t)(hi >> 32);
 }
 
-// One attempt of one worm (Step 5).  Legs are measured with the moving worm
-// removed so that L_min is the same before and after the move (Eq. (DB)).
-// Loads come in four dependent levels; every neighbour needed for the move
-// is kept in registers.
+// Steps 5-6 over windows of up to 64 consecutive attempts of the serial
+// sequence (cycle-major, worm-list order).  Lane k evaluates attempt s0+k on
+// the state at the start of the window.  The first attempt whose read set
+// meets a node an earlier attempt of the window may write ends the window
+// (owner stamps, LDS atomicMax).  A short in-order scan gives each surviving
+// attempt its position in the domain's random-word stream; the surviving
+// moves touch disjoint nodes and are applied together.  Decisions and the
+// final state equal those of the attempts made one at a time in order.
+//
+// One attempt (Step 5): a worm facing another worm, a temporal boundary or a
+// boundary vertex reverses; facing an interior vertex it enters with
+// probability L_min/L_i (legs measured without the moving worm, so L_min is
+// the same before and after, Eq. (DB)), leaves by leg j with probability
+// w_ji/w_i, lands on a uniform free slot of leg j and faces away from the
+// vertex.
 template <typename Idx>
-PMWA_DEV void worm_step(Nodes<Idx>& A, uint32_t w, RngBatch& rb, const double* __restrict__ scat)
+PMWA_DEV void scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
+                              int NN, int nw, const ChainDev& C, uint32_t sweep, uint32_t D,
+                              const double* __restrict__ scat)
 {
-    // level 1: the worm
-    const uint32_t fw = A.fl[w];
-    const uint32_t pw = A.prv[w], nw = A.nxt[w];
-    const bool up = fw & F_DIRUP;
-    const uint32_t x = up ? nw : pw;          // object ahead
-    const uint32_t wf = up ? pw : nw;         // object behind the worm
-    // level 2: the object ahead, and the one behind
-    const uint32_t fx = A.fl[x];
-    const bool lead = threadIdx.x == 0;   // one lane stores; every lane reads
-    if (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) { if (lead) A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
-    const int32_t t = A.tick[x];
-    const uint32_t y = A.aux[x];
-    const uint32_t xf = up ? A.nxt[x] : A.prv[x];   // far neighbour of the vertex end on x
-    const int32_t t_wf = A.tick[wf];
-    const uint32_t f_wf = A.fl[wf];
-    // level 3: the partner end and the far neighbour
-    const uint32_t fy = A.fl[y];
-    const uint32_t yp = A.prv[y], yn = A.nxt[y];
-    const int32_t t_xf = A.tick[xf];
-    const uint32_t f_xf = A.fl[xf];
-    // level 4: the partner's neighbours
-    const int32_t t_yp = A.tick[yp], t_yn = A.tick[yn];
-    const uint32_t f_yp = A.fl[yp];
-
-    const bool xa = ((fx >> 1) & 3u) < 2u;
-    // legs on x (worm excluded): below delimiter, above delimiter
-    long long Lxb, Lxa;
-    if (up) {   // worm below the vertex end: lower delimiter = wf, upper = xf
-        Lxb = (long long)t - (t_wf + (long long)(f_wf & F_WORM));
-        Lxa = (long long)t_xf - t;
-    } else {    // worm above: upper delimiter = wf, lower = xf
-        Lxa = (long long)t_wf - t;
-        Lxb = (long long)t - (t_xf + (long long)(f_xf & F_WORM));
+    const int lane = (int)threadIdx.x;
+    const long long total = (long long)C.ncycle * nw;
+    const uint32_t k0 = C.key0, k1 = C.key1, c1 = D, c2 = sweep, c3 = (C.chain_id << 8) | RNG_S;
+    uint32_t cur = 0, filled = 0, wid = 0;
+    for (long long s0 = 0; s0 < total;) {
+        // words [cur, cur + 192) of the stream sit in the 512-word ring
+        while (filled < cur + 192u) {
+            uint32_t o[4];
+            philox10((filled >> 1) + (uint32_t)lane, c1, c2, c3, k0, k1, o);
+            ring[(filled + 2u * lane) & 511u] = ((uint64_t)o[1] << 32) | o[0];
+            ring[(filled + 2u * lane + 1u) & 511u] = ((uint64_t)o[3] << 32) | o[2];
+            filled += 128u;
+        }
+        if (++wid == (1u << 23)) {
+            for (int i = lane; i < NN; i += 64) own[i] = 0u;
+            wid = 1;
+        }
+        __syncthreads();
+        const long long s = s0 + lane;
+        const bool act = s < total;
+        // ---- evaluate on the window's starting state
+        uint32_t w = 0, fw = 0, pw = 0, nn_ = 0, x = 0, fx = 0, y = 0, xf = 0, wf = 0;
+        uint32_t fy = 0, yp = 0, yn = 0, f_wf = 0, f_xf = 0, f_yp = 0;
+        int32_t t = 0, t_wf = 0, t_xf = 0, t_yp = 0, t_yn = 0;
+        bool blocked = true, up = false;
+        if (act) {
+            w = A.wl[(int)(s % nw)];
+            fw = A.fl[w];
+            pw = A.prv[w];
+            nn_ = A.nxt[w];
+            up = (fw & F_DIRUP) != 0;
+            x = up ? nn_ : pw;
+            wf = up ? pw : nn_;
+            fx = A.fl[x];
+            blocked = (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) != 0;
+            if (!blocked) {
+                t = A.tick[x];
+                y = A.aux[x];
+                xf = up ? A.nxt[x] : A.prv[x];
+                t_wf = A.tick[wf];
+                f_wf = A.fl[wf];
+                fy = A.fl[y];
+                yp = A.prv[y];
+                yn = A.nxt[y];
+                t_xf = A.tick[xf];
+                f_xf = A.fl[xf];
+                t_yp = A.tick[yp];
+                f_yp = A.fl[yp];
+                t_yn = A.tick[yn];
+            }
+        }
+        const bool xa = ((fx >> 1) & 3u) < 2u;
+        int32_t Lxb, Lxa;
+        if (up) { Lxb = t - (t_wf + (int32_t)(f_wf & F_WORM)); Lxa = t_xf - t; }
+        else { Lxa = t_wf - t; Lxb = t - (t_xf + (int32_t)(f_xf & F_WORM)); }
+        const int32_t Lyb = t - (t_yp + (int32_t)(f_yp & F_WORM));
+        const int32_t Lya = t_yn - t;
+        const int32_t L0 = xa ? Lxb : Lyb, L1 = xa ? Lyb : Lxb, L2 = xa ? Lxa : Lya, L3 = xa ? Lya : Lxa;
+        int32_t Lmin = L0 < L1 ? L0 : L1;
+        Lmin = L2 < Lmin ? L2 : Lmin;
+        Lmin = L3 < Lmin ? L3 : Lmin;
+        const int32_t Li = up ? Lxb : Lxa;
+        const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
+        // ---- nodes this attempt may write; conflicts with earlier attempts
+        const uint32_t stamp = (wid << 8) | (uint32_t)(255 - lane);
+        if (act) {
+            atomicMax(&own[w], stamp);
+            if (!blocked) {
+                atomicMax(&own[pw], stamp);
+                atomicMax(&own[nn_], stamp);
+                atomicMax(&own[xf], stamp);
+                atomicMax(&own[y], stamp);
+                atomicMax(&own[yp], stamp);
+                atomicMax(&own[yn], stamp);
+            }
+        }
+        __syncthreads();
+        bool conflict = !act;
+        if (act) {
+            uint32_t v;
+            v = own[w];   conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+            v = own[pw];  conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+            v = own[nn_]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+            if (!blocked) {
+                v = own[xf]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+                v = own[y];  conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+                v = own[yp]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+                v = own[yn]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
+            }
+        }
+        const unsigned long long cmask = __ballot(conflict);
+        const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
+        // ---- stream position of each surviving attempt, in order
+        uint32_t c = cur, myc = cur;
+        for (int k = 0; k < kc; k++) {
+            if (lane == k) myc = c;
+            if (!__builtin_amdgcn_readlane((int)blocked, k)) {
+                const uint32_t li = (uint32_t)__builtin_amdgcn_readlane(Li, k);
+                const int32_t lm = __builtin_amdgcn_readlane(Lmin, k);
+                const uint32_t r = below32(ring[c & 511u], li);
+                c += (int32_t)r < lm ? 3u : 1u;
+            }
+        }
+        // ---- apply the surviving attempts (disjoint nodes)
+        if (lane < kc) {
+            bool moved = false;
+            if (!blocked) {
+                const uint32_t r = below32(ring[myc & 511u], (uint32_t)Li);
+                moved = (int32_t)r < Lmin;
+            }
+            if (!moved) {
+                A.fl[w] = (uint8_t)(fw ^ F_DIRUP);
+            } else {
+                // vertex roots with the worm in place
+                const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;
+                const uint32_t rxa = (fx >> 3) & 1u;
+                const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
+                const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
+                                 : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
+                const int S0 = S ^ (1 << i);
+                const double uu = u53(ring[(myc + 1u) & 511u]);
+                const double* row = scat + S0 * 16 + i * 4;
+                const int j = uu < row[0] ? 0 : uu < row[1] ? 1 : uu < row[2] ? 2 : 3;
+                const int32_t Lj = j == 0 ? L0 : j == 1 ? L1 : j == 2 ? L2 : L3;
+                const uint32_t r2 = below32(ring[(myc + 2u) & 511u], (uint32_t)Lj);
+                // leave leg i: above the end on x, that segment takes the worm's state
+                const uint32_t fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
+                const bool on_x = ((j & 1) != 0) != xa;
+                const bool above = j >= 2;
+                uint32_t Pn, Nn, newup, fv = 0;
+                if (above) {
+                    Pn = on_x ? x : y;
+                    Nn = on_x ? (up ? xf : wf) : yn;
+                    fv = on_x ? fx_now : fy;
+                    newup = fv & F_UP;
+                } else {
+                    Nn = on_x ? x : y;
+                    Pn = on_x ? (up ? wf : xf) : yp;
+                    const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
+                    newup = (fp & F_UP) ^ F_UP;
+                }
+                if (!up) A.fl[x] = (uint8_t)fx_now;
+                A.nxt[pw] = (Idx)nn_;
+                A.prv[nn_] = (Idx)pw;
+                if (above) A.fl[Pn] = (uint8_t)(fv ^ F_UP);
+                A.tick[w] = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
+                A.fl[w] = (uint8_t)(F_WORM | (above ? F_DIRUP : 0u) | newup);
+                A.prv[w] = (Idx)Pn;
+                A.nxt[w] = (Idx)Nn;
+                A.nxt[Pn] = (Idx)w;
+                A.prv[Nn] = (Idx)w;
+            }
+        }
+        __syncthreads();
+        cur = c;
+        s0 += kc;
     }
-    const long long Lyb = (long long)t - (t_yp + (long long)(f_yp & F_WORM));
-    const long long Lya = (long long)t_yn - t;
-    long long L[4];
-    L[0] = xa ? Lxb : Lyb;
-    L[1] = xa ? Lyb : Lxb;
-    L[2] = xa ? Lxa : Lya;
-    L[3] = xa ? Lya : Lxa;
-    const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
-    long long Lmin = L[0];
-    Lmin = L[1] < Lmin ? L[1] : Lmin;
-    Lmin = L[2] < Lmin ? L[2] : Lmin;
-    Lmin = L[3] < Lmin ? L[3] : Lmin;
-    const long long Li = up ? Lxb : Lxa;
-    const uint32_t r = below32(rb.next(), (uint32_t)Li);
-    if ((long long)r >= Lmin) { if (lead) A.fl[w] = (uint8_t)(fw ^ F_DIRUP); return; }
-    // roots with the worm in place
-    const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;    // below the end on x
-    const uint32_t rxa = (fx >> 3) & 1u;
-    const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
-    const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
-                     : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
-    const int S0 = S ^ (1 << i);
-    const double uu = u53(rb.next());
-    const double* row = scat + S0 * 16 + i * 4;
-    const double c0 = row[0], c1 = row[1], c2 = row[2];
-    const int j = uu < c0 ? 0 : uu < c1 ? 1 : uu < c2 ? 2 : 3;
-    const long long Lj = j == 0 ? L[0] : j == 1 ? L[1] : j == 2 ? L[2] : L[3];
-    const uint32_t r2 = below32(rb.next(), (uint32_t)Lj);
-    // move: leave leg i, enter leg j next to the end Vy
-    const uint32_t fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
-    const bool on_x = ((j & 1) != 0) != xa;     // leg j lies on site x
-    const bool above = j >= 2;
-    uint32_t Pn, Nn, newup, fv = 0;
-    if (above) {
-        Pn = on_x ? x : y;
-        Nn = on_x ? (up ? xf : wf) : yn;
-        fv = on_x ? fx_now : fy;
-        newup = fv & F_UP;
-    } else {
-        Nn = on_x ? x : y;
-        Pn = on_x ? (up ? wf : xf) : yp;
-        const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
-        newup = (fp & F_UP) ^ F_UP;
-    }
-    if (lead) {
-        // the worm was above the end on x: that segment takes the worm's state
-        if (!up) A.fl[x] = (uint8_t)fx_now;
-        A.nxt[pw] = (Idx)nw;
-        A.prv[nw] = (Idx)pw;
-        if (above) A.fl[Pn] = (uint8_t)(fv ^ F_UP);
-        A.tick[w] = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
-        A.fl[w] = (uint8_t)(F_WORM | (above ? F_DIRUP : 0u) | newup);
-        A.prv[w] = (Idx)Pn;
-        A.nxt[w] = (Idx)Nn;
-        A.nxt[Pn] = (Idx)w;
-        A.prv[Nn] = (Idx)w;
-    }
-    __builtin_amdgcn_wave_barrier();
 }
 
 // one-wavefront exclusive scan
@@ -422,24 +482,11 @@ PMWA_DEV int wave_excl_scan(int v, int& total)
     return x - v;
 }
 
-// expm1(lambda*ell) over the set bits of ell, ascending
-PMWA_DEV double em1_bits(const ChainDev& C, long long ell)
-{
-    double m = 0.0;
-    unsigned long long b = (unsigned long long)ell;
-    while (b) {
-        const int k = __ffsll((long long)b) - 1;
-        const double t = C.E[k];
-        m = (m + t) + m * t;
-        b &= b - 1;
-    }
-    return m;
-}
-
 template <typename Idx>
 PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D,
-                             Nodes<Idx> A, const int* __restrict__ off, const int* __restrict__ cnt,
-                             const double* __restrict__ scat, int NE)
+                             Nodes<Idx> A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
+                             const int* __restrict__ off, const int* __restrict__ cnt,
+                             const double* __restrict__ scat, const double* __restrict__ sE, int NE)
 {
     const int lane = (int)threadIdx.x;
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
@@ -522,13 +569,10 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     __syncthreads();
     if (__any(P.flags[chain] != 0)) return;
 
-    // 4. N_cycle cycles, worms in list order (every lane runs the same
-    //    serial chain of decisions)
-    RngBatch rb;
-    rb.init(C, (uint32_t)P.sweep[chain], RNG_S, (uint32_t)D);
-    for (int cyc = 0; cyc < C.ncycle; cyc++)
-        for (int iw = 0; iw < nw; iw++) worm_step(A, (uint32_t)A.wl[iw], rb, scat);
+    // 4. N_cycle cycles, worms in list order, evaluated in windows
+    for (int i = lane; i < NE + 2 * nloc; i += 64) own[i] = 0u;
     __syncthreads();
+    scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain], (uint32_t)D, scat);
 
     // 5. measurement (Step 6) and write-back, one lane per site
     long long nv = 0, nkink = 0, nwc = 0, occ = 0;
@@ -547,7 +591,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                 occ += (long long)stt * (2LL * C.T[k + 1] - last);
                 const long long ell = (long long)C.T[k + 1] - ilo;
                 if (ell > 0) {
-                    const double m = em1_bits(C, ell);
+                    const double m = em1(sE, ell);
                     const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
                     qimp += (double)ell * (par ? 1.0 / th : th);
                 }
@@ -565,7 +609,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             } else {
                 const long long ell = (long long)tk - ilo;
                 if (ell > 0) {
-                    const double m = em1_bits(C, ell);
+                    const double m = em1(sE, ell);
                     const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
                     qimp += (double)ell * (par ? 1.0 / th : th);
                 }
@@ -612,9 +656,12 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
     const int nloc = C.nloc;
     double* scat = reinterpret_cast<double*>(smem);
-    int* off = reinterpret_cast<int*>(smem + 256 * sizeof(double));
+    double* sE = scat + 256;
+    uint64_t* ring = reinterpret_cast<uint64_t*>(smem + 288 * sizeof(double));
+    int* off = reinterpret_cast<int*>(smem + 800 * sizeof(double));
     int* cnt = off + (nloc + 1);
     for (int i = lane; i < 256; i += 64) scat[i] = C.scat[i];
+    if (lane < 32) sE[lane] = C.E[lane];
     for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
     __syncthreads();
     // exclusive scan of the per-site counts
@@ -633,7 +680,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     const int NN = NE + 2 * nloc;
     if (P.flags[bt.x] != 0) return;
 
-    const size_t fixed = 256 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
+    const size_t fixed = 800 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
     const int cap_l = P.lds_nodes;
     if (NN <= cap_l && NN < 65535) {
@@ -644,8 +691,9 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
         A.prv = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
         A.aux = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
         A.wl = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
+        uint32_t* own = reinterpret_cast<uint32_t*>(p); p += (size_t)cap_l * 4;
         A.fl = reinterpret_cast<uint8_t*>(p);
-        scatter_domain(P, C, bt.x, D, A, off, cnt, scat, NE);
+        scatter_domain(P, C, bt.x, D, A, own, ring, off, cnt, scat, sE, NE);
     } else {
         if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
         const long long b = C.scr_off + (long long)D * C.scr_nodes;
@@ -656,7 +704,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
         A.aux = P.s_aux + b;
         A.fl = P.s_fl + b;
         A.wl = P.s_wl + b;
-        scatter_domain(P, C, bt.x, D, A, off, cnt, scat, NE);
+        scatter_domain(P, C, bt.x, D, A, P.s_own + b, ring, off, cnt, scat, sE, NE);
     }
 }
 
@@ -682,12 +730,12 @@ struct SiteArr {
 };
 
 // worms of one interval as events (slot base + offset), occupation starting at p
-PMWA_DEV int gen_worms(const ChainDev& C, Stream& rs, int32_t base, long long ell, int sigma,
-                       int p, uint2* out, unsigned int* flag)
+PMWA_DEV int gen_worms(const double* __restrict__ E, double lambda, Stream& rs, int32_t base,
+                       long long ell, int sigma, int p, uint2* out, unsigned int* flag)
 {
     int32_t off[NWL];
     uint8_t dirs[NWL];
-    const int n = sample_worms(C, rs, ell, sigma, off, dirs, flag);
+    const int n = sample_worms(E, lambda, rs, ell, sigma, off, dirs, flag);
     int s = p;
     for (int w = 0; w < n; w++) {
         s ^= 1;
@@ -699,13 +747,17 @@ PMWA_DEV int gen_worms(const ChainDev& C, Stream& rs, int32_t base, long long el
 // Step 1, Eq. (Para): one lane per site, temporal boundaries k = 0.. in order;
 // the upper domain's stream (site, k) makes the choice, then the worms of the
 // two legs I_1 (above) and I_2 (below) are regenerated.
-__global__ void __launch_bounds__(128) k_btemporal(Pools P, const int2* __restrict__ blk)
+__global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restrict__ blk)
 {
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
+    __shared__ double sE[32];
+    if (threadIdx.x < 32) sE[threadIdx.x] = C.E[threadIdx.x];
+    __syncthreads();
     if (u >= C.N || P.flags[bt.x] != 0) return;
     unsigned int* flag = &P.flags[bt.x];
+    const double lambda = C.lambda;
     const int dsp = u / C.nloc, sl = u % C.nloc;
     const int site = site_join(C, dsp, sl);
     const int nt = C.ntau;
@@ -724,7 +776,7 @@ __global__ void __launch_bounds__(128) k_btemporal(Pools P, const int2* __restri
                 // the circle is one interval through the boundary
                 const double W[2] = {1.0, 1.0};
                 const int sp = choose(W, u53(rs.next()));
-                const int m = gen_worms(C, rs, 0, C.M, 0, sp, b1, flag);
+                const int m = gen_worms(sE, lambda, rs, 0, C.M, 0, sp, b1, flag);
                 if (m < 0) return;
                 if (!Ak.replace(0, Ak.n, b1, m)) { atomicOr(flag, FL_OVERFLOW); return; }
                 P.cnt[cuk] = Ak.n;
@@ -752,11 +804,11 @@ __global__ void __launch_bounds__(128) k_btemporal(Pools P, const int2* __restri
         else { t2 = C.T[kp]; p = P.bs[C.bs_off + unit_su(C, kp, dsp, sl)]; }
         const long long l2 = (long long)C.T[kp + 1] - t2;
         double W[2];
-        for (int sp = 0; sp < 2; sp++) W[sp] = fleg(C, sp ^ q, l1) * fleg(C, p ^ sp, l2);
+        for (int sp = 0; sp < 2; sp++) W[sp] = fleg(sE, sp ^ q, l1) * fleg(sE, p ^ sp, l2);
         const int sp = choose(W, u53(rs.next()));
-        const int m1 = gen_worms(C, rs, C.T[k], l1, sp ^ q, sp, b1, flag);
+        const int m1 = gen_worms(sE, lambda, rs, C.T[k], l1, sp ^ q, sp, b1, flag);
         if (m1 < 0) return;
-        const int m2 = gen_worms(C, rs, t2, l2, p ^ sp, p, b2, flag);
+        const int m2 = gen_worms(sE, lambda, rs, t2, l2, p ^ sp, p, b2, flag);
         if (m2 < 0) return;
         if (nt == 1) {
             // same array: suffix first, then prefix
@@ -845,12 +897,12 @@ PMWA_DEV bool wave_replace(uint2* A, int& n, int cap, int lo, int hi, const uint
 }
 
 // worms of one interval written to LDS (all lanes write the same values)
-PMWA_DEV int gen_worms_lds(const ChainDev& C, Stream& rs, int32_t base, long long ell, int sigma,
-                           int p, uint2* out, unsigned int* flag)
+PMWA_DEV int gen_worms_lds(const double* __restrict__ E, double lambda, Stream& rs, int32_t base,
+                           long long ell, int sigma, int p, uint2* out, unsigned int* flag)
 {
     int32_t off[NWL];
     uint8_t dirs[NWL];
-    const int n = sample_worms(C, rs, ell, sigma, off, dirs, flag);
+    const int n = sample_worms(E, lambda, rs, ell, sigma, off, dirs, flag);
     int s = p;
     for (int w = 0; w < n; w++) {
         s ^= 1;
@@ -879,9 +931,17 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     site_split(C, a, dspa, sla);
     site_split(C, c, dspc, slc);
     const int nt = C.ntau, cap = C.cap;
-    uint2* A = reinterpret_cast<uint2*>(smem);
+    double* sE = reinterpret_cast<double*>(smem);
+    uint2* A = reinterpret_cast<uint2*>(smem + 32 * sizeof(double));
     uint2* B = A + cap;
     uint2* Wk = B + cap;       // 4 legs x NWL new worms
+    if (lane < 32) sE[lane] = C.E[lane];
+    const double lambda = C.lambda;
+    double vwa[6];
+    {
+        const int AL[6] = {0, 5, 6, 9, 10, 15};
+        for (int m = 0; m < 6; m++) vwa[m] = C.vw[AL[m]];
+    }
     Stream rs;
     rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)(2LL * a + d));
     for (int k = 0; k < nt; k++) {
@@ -926,7 +986,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
             {
                 const long long ls[4] = {l0, l1, l2, l3};
                 for (int g = 0; g < 4; g++) {
-                    const double m = em1(C, ls[g]);
+                    const double m = em1(sE, ls[g]);
                     const double dd = 2.0 * (1.0 + m);
                     f[g][0] = 1.0 + (m * m) / dd;
                     f[g][1] = (m * (2.0 + m)) / dd;
@@ -937,15 +997,15 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
             for (int m = 0; m < 6; m++) {
                 const int S = ALLOWED[m];
                 const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-                W[m] = (((f[0][p1 ^ s1] * f[1][p2 ^ s2]) * f[2][s1p ^ q1]) * f[3][s2p ^ q2]) * C.vw[S];
+                W[m] = (((f[0][p1 ^ s1] * f[1][p2 ^ s2]) * f[2][s1p ^ q1]) * f[3][s2p ^ q2]) * vwa[m];
             }
             const int m = choose(W, u53(rs.next()));
             const int S = ALLOWED[m];
             const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-            const int n0 = gen_worms_lds(C, rs, lo_a, l0, p1 ^ s1, p1, Wk, flag);
-            const int n1 = n0 < 0 ? -1 : gen_worms_lds(C, rs, lo_c, l1, p2 ^ s2, p2, Wk + NWL, flag);
-            const int n2 = n1 < 0 ? -1 : gen_worms_lds(C, rs, t, l2, s1p ^ q1, s1p, Wk + 2 * NWL, flag);
-            const int n3 = n2 < 0 ? -1 : gen_worms_lds(C, rs, t, l3, s2p ^ q2, s2p, Wk + 3 * NWL, flag);
+            const int n0 = gen_worms_lds(sE, lambda, rs, lo_a, l0, p1 ^ s1, p1, Wk, flag);
+            const int n1 = n0 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, lo_c, l1, p2 ^ s2, p2, Wk + NWL, flag);
+            const int n2 = n1 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l2, s1p ^ q1, s1p, Wk + 2 * NWL, flag);
+            const int n3 = n2 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l3, s2p ^ q2, s2p, Wk + 3 * NWL, flag);
             if (n3 < 0) { fail = true; break; }
             __syncthreads();
             if (lane == 0) {
