@@ -153,6 +153,12 @@ int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out);
 int pmwa_set_timing(pmwa_t* h, int enable);
 int pmwa_phase_times(pmwa_t* h, double* ms, int64_t* launches);
 
+/* Scattering-phase diagnostics of the last sweep of `chain` (synchronises):
+   out[0] evaluation windows summed over domains, out[1] the most windows in
+   one domain, out[2] worm attempts summed over domains, out[3] the most
+   attempts in one domain.  n >= 4. */
+int pmwa_diag(pmwa_t* h, int chain, int64_t* out, int n);
+
 /* Events per (site, slab) a chain would be given by default. */
 int pmwa_default_event_cap(const pmwa_params* p);
 

@@ -70,7 +70,7 @@ struct orc_chain {
     int Lx, Ly, N, ntau, ex, ey, M;
     int32_t T[65];
     double delta, lambda, C, rho_max, wd[4], acc[4];
-    double E[32];              /* expm1(lambda * 2^k) */
+    double F[4][256];          /* expm1(lambda * v * 2^(8g)), digit v of ell */
     double* cdf;               /* [ntau][KMAX] Poisson CDF of candidate counts */
     int*    cdf_len;
     double scat[16][4][4];     /* cumulative exit table, row S0, entry leg i */
@@ -185,14 +185,15 @@ static int slab_of(const orc_chain* c, int32_t tick)
 /* ------------------------------------------------------------------ */
 /* element functions of the worm law, from the expm1 bit table          */
 /* ------------------------------------------------------------------ */
-/* m = exp(lambda*ell) - 1, accumulated over the set bits of ell in
+/* m = exp(lambda*ell) - 1, accumulated over the base-256 digits of ell in
    ascending order: (1+m)(1+t) - 1 = (m + t) + m t. */
 static double em1(const orc_chain* c, int64_t ell)
 {
     double m = 0.0;
-    for (int k = 0; k < 32; k++) {
-        if ((ell >> k) & 1) {
-            double t = c->E[k];
+    for (int g = 0; g < 4; g++) {
+        int v = (int)((ell >> (8 * g)) & 255);
+        if (v) {
+            double t = c->F[g][v];
             m = (m + t) + m * t;
         }
     }
@@ -285,7 +286,9 @@ static void build_tables(orc_chain* c)
     c->M = 1 << p->ticks_log2;
     c->delta = p->beta / (double)c->M;
     c->lambda = p->eta * c->delta;
-    for (int k = 0; k < 32; k++) c->E[k] = expm1(c->lambda * ldexp(1.0, k));
+    for (int g = 0; g < 4; g++)
+        for (int v = 0; v < 256; v++)
+            c->F[g][v] = expm1(c->lambda * (double)((uint64_t)v << (8 * g)));
 
     /* E_b(sa,sc) = V sa sc - (mu/4)(sa+sc): the site term split over the
        four bonds of a site (hard-core Bose-Hubbard model, Eq. (BH)) */

@@ -48,7 +48,7 @@ struct ChainDev {
     int64_t scr_off;   // node scratch of the HBM scattering path (nodes)
     int32_t T[NT_MAX + 1];
     int32_t pad_;
-    double E[32];      // expm1(lambda * 2^k)
+    double F[1024];    // expm1(lambda * v * 2^(8g)) at [g*256 + v]
     double acc[4];     // w_d / rho_max, index s_a | s_c << 1
     double vw[16];     // vertex weight by root pattern
     double scat[256];  // cumulative exit table [S0][entry][exit]
@@ -57,7 +57,7 @@ struct ChainDev {
 struct DomPart {
     long long nv, nkink, nw, occ2;
     double qimp;
-    long long pad_;
+    long long windows;   // evaluation windows of the scattering phase (diagnostic)
 };
 
 struct Pools {
@@ -122,6 +122,33 @@ struct Stream {
     }
 };
 
+// The same word stream drawn by a whole wavefront in lock step: lane l
+// computes block 64*b + l of batch b; words are read back with readlane.
+struct WaveStream {
+    uint32_t k0, k1, c1, c2, c3, w;
+    uint32_t o0, o1, o2, o3;
+    PMWA_DEV void init(const ChainDev& C, uint32_t sweep, uint32_t kind, uint32_t unit)
+    {
+        k0 = C.key0; k1 = C.key1; c1 = unit; c2 = sweep; c3 = (C.chain_id << 8) | kind;
+        w = 0;
+    }
+    PMWA_DEV uint64_t next()
+    {
+        const uint32_t b = w & 127u;
+        if (b == 0) {
+            uint32_t o[4];
+            philox10(((w >> 7) << 6) + (uint32_t)threadIdx.x, c1, c2, c3, k0, k1, o);
+            o0 = o[0]; o1 = o[1]; o2 = o[2]; o3 = o[3];
+        }
+        const int ln = (int)(b >> 1);
+        uint32_t lo, hi;
+        if (b & 1u) { lo = __builtin_amdgcn_readlane(o2, ln); hi = __builtin_amdgcn_readlane(o3, ln); }
+        else { lo = __builtin_amdgcn_readlane(o0, ln); hi = __builtin_amdgcn_readlane(o1, ln); }
+        w++;
+        return ((uint64_t)hi << 32) | lo;
+    }
+};
+
 PMWA_DEV double u53(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
 PMWA_DEV uint64_t below(uint64_t w, uint64_t n) { return __umul64hi(w, n); }
 
@@ -166,16 +193,18 @@ PMWA_DEV long long ev_base(const ChainDev& C, int k, int dsp, int sl)
 // ---------------------------------------------------------------------------
 // element functions of the worm law (hard-core f_qp), from the expm1 table
 // ---------------------------------------------------------------------------
-// E[k] = expm1(lambda * 2^k) (a copy in LDS); bits of ell in ascending order
-PMWA_DEV double em1(const double* __restrict__ E, long long ell)
+// F[g*256 + v] = expm1(lambda * v * 2^(8g)) (a copy in LDS); the base-256
+// digits of ell in ascending order, (1+m)(1+t) - 1 = (m + t) + m t
+PMWA_DEV double em1(const double* __restrict__ F, long long ell)
 {
     double m = 0.0;
-    unsigned long long b = (unsigned long long)ell;
-    while (b) {
-        const int k = __ffsll((long long)b) - 1;
-        const double t = E[k];
-        m = (m + t) + m * t;
-        b &= b - 1;
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        const int v = (int)((ell >> (8 * g)) & 255);
+        if (v) {
+            const double t = F[g * 256 + v];
+            m = (m + t) + m * t;
+        }
     }
     return m;
 }
@@ -216,7 +245,8 @@ PMWA_DEV int choose(const double (&W)[N], double u)
 // count by inversion of x^n/n!/f_sigma(x), x = lambda*ell, n <= ell (redraw
 // otherwise); distinct uniform offsets in [0, ell), sorted; one direction
 // bit per worm in ascending order.  Returns n, or -1 on failure (flagged).
-PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, Stream& s, long long ell,
+template <class RS>
+PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, long long ell,
                           int sigma, int32_t* off, uint8_t* dirs, unsigned int* flag)
 {
     if (ell == 0) {

@@ -3,7 +3,7 @@
 // Host tables follow the paper's definitions with a fixed floating-point
 // operation order (no contraction), so that every Monte Carlo decision is
 // reproducible bit for bit by any implementation that uses the same order:
-//   Delta = beta / M, lambda = eta * Delta, E[k] = expm1(lambda * 2^k);
+//   Delta = beta / M, lambda = eta * Delta, F[g][v] = expm1(lambda * v * 2^(8g));
 //   E_b(sa,sc) = V*(sa&sc) - (mu*0.25)*(sa+sc); C = max E_b + t/2 (t > 0) or
 //   + 1/2; w_d = C - E_b; acc = w_d / rho_max;
 //   Poisson candidate counts per slab (inversion table, tail folded into a
@@ -174,7 +174,9 @@ static int build_chain(const pmwa_params& p, uint32_t cap_override, HostChain& h
     hc.delta = p.beta / (double)d.M;
     d.lambda = p.eta * hc.delta;
     d.t = p.t;
-    for (int k = 0; k < 32; k++) d.E[k] = std::expm1(d.lambda * std::ldexp(1.0, k));
+    for (int g = 0; g < 4; g++)
+        for (int v = 0; v < 256; v++)
+            d.F[g * 256 + v] = std::expm1(d.lambda * (double)((uint64_t)v << (8 * g)));
 
     double Eb[4], Emax = 0.0;
     for (int s = 0; s < 4; s++) {
@@ -448,7 +450,7 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     size_t lds_max = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds_max) lds_max = prop.maxSharedMemoryPerMultiProcessor;
     if (lds_max > 160 * 1024) lds_max = 160 * 1024;
-    const size_t fixed = 800 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
+    const size_t fixed = 1792 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
     const size_t per_node = 4 + 4 * 2 + 4 + 1;   // tick, nxt, prv, aux, wl (16-bit), owner stamp, flags
     // nodes wanted: the largest expected domain with margin
@@ -526,7 +528,7 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
     {
         int maxcap = 0;
         for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
-        h->bs_lds = 32 * sizeof(double) + (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2);
+        h->bs_lds = 1024 * sizeof(double) + (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2);
         if (h->bs_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->bs_lds);
@@ -656,6 +658,24 @@ int pmwa_phase_times(pmwa_t* h, double* ms, int64_t* launches)
         launches[ph - 1] += 1;
     }
     h->ev_used = 0;
+    return PMWA_OK;
+}
+
+int pmwa_diag(pmwa_t* h, int chain, int64_t* out, int n)
+{
+    if (!h || !out || n < 4 || chain < 0 || chain >= (int)h->ch.size()) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const HostChain& hc = h->ch[chain];
+    std::vector<DomPart> dp(hc.n_dom);
+    HIPCHK(hipMemcpy(dp.data(), h->P.dpart + hc.d.dom_off, dp.size() * sizeof(DomPart), hipMemcpyDeviceToHost));
+    int64_t wsum = 0, wmax = 0, att = 0, amax = 0;
+    for (const DomPart& x : dp) {
+        wsum += x.windows;
+        wmax = std::max<int64_t>(wmax, x.windows);
+        att += x.nw * (int64_t)hc.d.ncycle;
+        amax = std::max<int64_t>(amax, x.nw * (int64_t)hc.d.ncycle);
+    }
+    out[0] = wsum; out[1] = wmax; out[2] = att; out[3] = amax;
     return PMWA_OK;
 }
 

@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    __shared__ double sE[32];
-    if (threadIdx.x < 32) sE[threadIdx.x] = C.E[threadIdx.x];
+    __shared__ double sE[1024];
+    for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
     __syncthreads();
     if (u >= C.ntau * C.N || P.flags[bt.x] != 0) return;
     unsigned int* flag = &P.flags[bt.x];
@@ -306,10 +306,11 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 // w_ji/w_i, lands on a uniform free slot of leg j and faces away from the
 // vertex.
 template <typename Idx>
-PMWA_DEV void scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
-                              int NN, int nw, const ChainDev& C, uint32_t sweep, uint32_t D,
-                              const double* __restrict__ scat)
+PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
+                                   int NN, int nw, const ChainDev& C, uint32_t sweep, uint32_t D,
+                                   const double* __restrict__ scat)
 {
+    long long windows = 0;
     const int lane = (int)threadIdx.x;
     const long long total = (long long)C.ncycle * nw;
     const uint32_t k0 = C.key0, k1 = C.key1, c1 = D, c2 = sweep, c3 = (C.chain_id << 8) | RNG_S;
@@ -402,14 +403,23 @@ PMWA_DEV void scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_
         }
         const unsigned long long cmask = __ballot(conflict);
         const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
-        // ---- stream position of each surviving attempt, in order
+        // ---- stream position of each surviving attempt, in order; lane l
+        //      holds words cur+l, cur+64+l, cur+128+l of the stream
+        const uint64_t wv0 = ring[(cur + (uint32_t)lane) & 511u];
+        const uint64_t wv1 = ring[(cur + 64u + (uint32_t)lane) & 511u];
+        const uint64_t wv2 = ring[(cur + 128u + (uint32_t)lane) & 511u];
         uint32_t c = cur, myc = cur;
         for (int k = 0; k < kc; k++) {
             if (lane == k) myc = c;
-            if (!__builtin_amdgcn_readlane((int)blocked, k)) {
-                const uint32_t li = (uint32_t)__builtin_amdgcn_readlane(Li, k);
+            const int32_t li = __builtin_amdgcn_readlane(blocked ? 0 : Li, k);
+            if (li != 0) {
                 const int32_t lm = __builtin_amdgcn_readlane(Lmin, k);
-                const uint32_t r = below32(ring[c & 511u], li);
+                const uint32_t q = c - cur;
+                const uint64_t wq = q < 64u ? wv0 : q < 128u ? wv1 : wv2;
+                const int ln = (int)(q & 63u);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wq, ln);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(wq >> 32), ln);
+                const uint32_t r = below32(((uint64_t)hi << 32) | lo, (uint32_t)li);
                 c += (int32_t)r < lm ? 3u : 1u;
             }
         }
@@ -466,7 +476,9 @@ PMWA_DEV void scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_
         __syncthreads();
         cur = c;
         s0 += kc;
+        windows++;
     }
+    return windows;
 }
 
 // one-wavefront exclusive scan
@@ -572,7 +584,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     // 4. N_cycle cycles, worms in list order, evaluated in windows
     for (int i = lane; i < NE + 2 * nloc; i += 64) own[i] = 0u;
     __syncthreads();
-    scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain], (uint32_t)D, scat);
+    const long long windows =
+        scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain], (uint32_t)D, scat);
 
     // 5. measurement (Step 6) and write-back, one lane per site
     long long nv = 0, nkink = 0, nwc = 0, occ = 0;
@@ -638,7 +651,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     }
     if (lane == 0) {
         DomPart dp;
-        dp.nv = nv; dp.nkink = nkink; dp.nw = nwc; dp.occ2 = occ; dp.qimp = qimp; dp.pad_ = 0;
+        dp.nv = nv; dp.nkink = nkink; dp.nw = nwc; dp.occ2 = occ; dp.qimp = qimp; dp.windows = windows;
         P.dpart[C.dom_off + D] = dp;
     }
 }
@@ -657,11 +670,11 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     const int nloc = C.nloc;
     double* scat = reinterpret_cast<double*>(smem);
     double* sE = scat + 256;
-    uint64_t* ring = reinterpret_cast<uint64_t*>(smem + 288 * sizeof(double));
-    int* off = reinterpret_cast<int*>(smem + 800 * sizeof(double));
+    uint64_t* ring = reinterpret_cast<uint64_t*>(smem + 1280 * sizeof(double));
+    int* off = reinterpret_cast<int*>(smem + 1792 * sizeof(double));
     int* cnt = off + (nloc + 1);
     for (int i = lane; i < 256; i += 64) scat[i] = C.scat[i];
-    if (lane < 32) sE[lane] = C.E[lane];
+    for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
     for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
     __syncthreads();
     // exclusive scan of the per-site counts
@@ -680,7 +693,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     const int NN = NE + 2 * nloc;
     if (P.flags[bt.x] != 0) return;
 
-    const size_t fixed = 800 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
+    const size_t fixed = 1792 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
     const int cap_l = P.lds_nodes;
     if (NN <= cap_l && NN < 65535) {
@@ -752,8 +765,8 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    __shared__ double sE[32];
-    if (threadIdx.x < 32) sE[threadIdx.x] = C.E[threadIdx.x];
+    __shared__ double sE[1024];
+    for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
     __syncthreads();
     if (u >= C.N || P.flags[bt.x] != 0) return;
     unsigned int* flag = &P.flags[bt.x];
@@ -897,7 +910,7 @@ PMWA_DEV bool wave_replace(uint2* A, int& n, int cap, int lo, int hi, const uint
 }
 
 // worms of one interval written to LDS (all lanes write the same values)
-PMWA_DEV int gen_worms_lds(const double* __restrict__ E, double lambda, Stream& rs, int32_t base,
+PMWA_DEV int gen_worms_lds(const double* __restrict__ E, double lambda, WaveStream& rs, int32_t base,
                            long long ell, int sigma, int p, uint2* out, unsigned int* flag)
 {
     int32_t off[NWL];
@@ -932,17 +945,17 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     site_split(C, c, dspc, slc);
     const int nt = C.ntau, cap = C.cap;
     double* sE = reinterpret_cast<double*>(smem);
-    uint2* A = reinterpret_cast<uint2*>(smem + 32 * sizeof(double));
+    uint2* A = reinterpret_cast<uint2*>(smem + 1024 * sizeof(double));
     uint2* B = A + cap;
     uint2* Wk = B + cap;       // 4 legs x NWL new worms
-    if (lane < 32) sE[lane] = C.E[lane];
+    for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
     const double lambda = C.lambda;
     double vwa[6];
     {
         const int AL[6] = {0, 5, 6, 9, 10, 15};
         for (int m = 0; m < 6; m++) vwa[m] = C.vw[AL[m]];
     }
-    Stream rs;
+    WaveStream rs;
     rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)(2LL * a + d));
     for (int k = 0; k < nt; k++) {
         const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);

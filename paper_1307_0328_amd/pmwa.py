@@ -19,7 +19,7 @@ PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
 
 EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
-           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times"]
+           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times", "pmwa_diag"]
 
 
 class pmwa_params(C.Structure):
@@ -76,6 +76,7 @@ def lib():
         L.pmwa_destroy.restype = None
         L.pmwa_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.pmwa_phase_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.pmwa_diag.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -181,6 +182,13 @@ def pmwa_phase_times(h):
     return ms, n
 
 
+def pmwa_diag(h, chain):
+    out = np.zeros(4, np.int64)
+    _check(lib().pmwa_diag(h, chain, out.ctypes.data, 4), "pmwa_diag")
+    return dict(windows=int(out[0]), windows_max=int(out[1]), attempts=int(out[2]),
+                attempts_max=int(out[3]))
+
+
 def pmwa_destroy(h):
     if h:
         lib().pmwa_destroy(h)
@@ -246,3 +254,6 @@ class Sim:
 
     def phase_times(self):
         return pmwa_phase_times(self.h)
+
+    def diag(self, chain=0):
+        return pmwa_diag(self.h, chain)
