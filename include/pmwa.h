@@ -153,6 +153,24 @@ int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out);
 int pmwa_set_timing(pmwa_t* h, int enable);
 int pmwa_phase_times(pmwa_t* h, double* ms, int64_t* launches);
 
+/* Continuous batching.  pmwa_create_slots allocates n_slots chain slots;
+   shapes[i] gives slot i's largest chain: a chain fits slot i when none of
+   its sizes (sites x slabs, bonds x slabs, domains, sites per domain,
+   crossing bonds, Poisson-table length) exceeds those of shapes[i].  Slots
+   start idle.  pmwa_slot_load installs a chain in slot `slot` (stream
+   ordered: its empty configuration is set up before the next sweep) that
+   stops after target_sweeps sweeps; pmwa_slot_release makes the slot idle.
+   pmwa_sweep advances every installed chain below its target.
+   pmwa_slot_progress synchronises and returns the sweeps done.  Records
+   and states are read with pmwa_measure / pmwa_get_state using the slot
+   index.  A chain's trajectory does not depend on its slot or on the other
+   chains.  PMWA_EINVAL if the chain does not fit the slot. */
+int pmwa_create_slots(const pmwa_params* shapes, int n_slots, const pmwa_opts* opts,
+                      pmwa_t** out);
+int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_sweeps);
+int pmwa_slot_release(pmwa_t* h, int slot);
+int pmwa_slot_progress(pmwa_t* h, int slot, int64_t* sweeps_done);
+
 /* Scattering-phase diagnostics of the last sweep of `chain` (synchronises):
    out[0] evaluation windows summed over domains, out[1] the most windows in
    one domain, out[2] worm attempts summed over domains, out[3] the most

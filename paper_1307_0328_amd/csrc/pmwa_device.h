@@ -46,6 +46,9 @@ struct ChainDev {
     double lambda, t;
     int64_t ev_off, cnt_off, bs_off, bv_off, bvc_off, dom_off, ser_off, cdf_off;
     int64_t scr_off;   // node scratch of the HBM scattering path (nodes)
+    int64_t target;    // sweeps after which the chain stops
+    int32_t active;    // 0: idle slot, every kernel skips the chain
+    int32_t pad1_;
     int32_t T[NT_MAX + 1];
     int32_t pad_;
     double F[1024];    // expm1(lambda * v * 2^(8g)) at [g*256 + v]
@@ -291,6 +294,12 @@ PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, lo
     }
     for (int i = 0; i < n; i++) dirs[i] = (uint8_t)(s.next() >> 63);
     return n;
+}
+
+// the chain takes part in this sweep
+PMWA_DEV bool live(const Pools& P, const ChainDev& C, int c)
+{
+    return C.active != 0 && P.flags[c] == 0 && P.sweep[c] < (unsigned long long)C.target;
 }
 
 // event encoding

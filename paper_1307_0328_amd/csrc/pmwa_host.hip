@@ -43,6 +43,15 @@ struct HostChain {
     int64_t n_units_v, n_units_r, n_dom, n_bt, n_bsx, n_bsy;
     uint64_t enq_sweeps = 0, read_sweeps = 0;
     std::vector<pmwa_obs> host_rows;   // drained, not yet returned
+    // what the chain's regions hold (a slot keeps these for every chain it takes)
+    int64_t cap_ev = 0, cap_su = 0, cap_bv = 0, cap_dom = 0, cap_cdf = 0, cap_scr = 0;
+    int64_t cap_units_v = 0, cap_units_r = 0, cap_bt = 0, cap_bsx = 0, cap_bsy = 0;
+    int cap_event = 0;
+    bool active = true;
+    uint64_t target = ~0ULL;
+    // slot installs: pinned staging and the event of its last copy
+    unsigned char* staging = nullptr;
+    hipEvent_t staged = nullptr;
 };
 
 template <typename T>
@@ -69,6 +78,8 @@ struct pmwa_handle {
     size_t lds_bytes = 0;
     size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
     int64_t ev_total = 0, site_slabs = 0;
+    bool slots = false;
+    int max_nloc = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool own_stream = false;
@@ -394,6 +405,10 @@ void pmwa_destroy(pmwa_t* h)
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (auto& hc : h->ch) {
+        if (hc.staging) (void)hipHostFree(hc.staging);
+        if (hc.staged) (void)hipEventDestroy(hc.staged);
+    }
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
@@ -404,7 +419,8 @@ void pmwa_destroy(pmwa_t* h)
     delete h;
 }
 
-int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, pmwa_t** out)
+static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, bool slots,
+                       pmwa_t** out)
 {
     if (!out) return PMWA_EINVAL;
     *out = nullptr;
@@ -437,8 +453,22 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
         d.ser_off = (int64_t)c * h->opts.series_cap;
         d.cdf_off = cdf; cdf += (int64_t)hc.cdf.size();
         max_nloc = std::max(max_nloc, d.nloc);
+        hc.cap_ev = (int64_t)d.ntau * d.N * d.cap;
+        hc.cap_su = (int64_t)d.ntau * d.N;
+        hc.cap_bv = 2LL * d.ntau * d.N * d.capb;
+        hc.cap_dom = hc.n_dom;
+        hc.cap_cdf = (int64_t)hc.cdf.size();
+        hc.cap_units_v = hc.n_units_v; hc.cap_units_r = hc.n_units_r;
+        hc.cap_bt = hc.n_bt; hc.cap_bsx = hc.n_bsx; hc.cap_bsy = hc.n_bsy;
+        hc.cap_event = d.cap;
+        hc.active = !slots;
+        hc.target = slots ? 0ULL : ~0ULL;
+        d.active = slots ? 0 : 1;
+        d.target = slots ? 0 : INT64_MAX;
     }
     if (rc) { pmwa_destroy(h); return rc; }
+    h->slots = slots;
+    h->max_nloc = max_nloc;
 
     // LDS budget of the scattering kernel
     int dev = 0;
@@ -480,6 +510,7 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
         d.scr_nodes = (int32_t)nodes;
         d.scr_off = scr;
         scr += nodes * hc.n_dom;
+        hc.cap_scr = nodes * hc.n_dom;
     }
 
     h->ev_total = ev;
@@ -546,7 +577,111 @@ int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, 
         pmwa_destroy(h);
         return PMWA_EDEVICE;
     }
+    if (slots) {
+        for (auto& hc : h->ch) {
+            if (hipHostMalloc((void**)&hc.staging, sizeof(ChainDev) + hc.cap_cdf * sizeof(double)) != hipSuccess ||
+                hipEventCreateWithFlags(&hc.staged, hipEventDisableTiming) != hipSuccess) {
+                pmwa_destroy(h);
+                return PMWA_ENOMEM;
+            }
+        }
+    }
     *out = h;
+    return PMWA_OK;
+}
+
+int pmwa_create(const pmwa_params* chains, int n_chains, const pmwa_opts* opts, pmwa_t** out)
+{
+    return create_impl(chains, n_chains, opts, false, out);
+}
+
+int pmwa_create_slots(const pmwa_params* shapes, int n_slots, const pmwa_opts* opts, pmwa_t** out)
+{
+    return create_impl(shapes, n_slots, opts, true, out);
+}
+
+static void advance_enq(pmwa_t* h)
+{
+    for (auto& hc : h->ch)
+        if (hc.active && hc.enq_sweeps < hc.target) hc.enq_sweeps++;
+}
+
+int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_sweeps)
+{
+    if (!h || !p || !h->slots || slot < 0 || slot >= (int)h->ch.size() || target_sweeps < 0) return PMWA_EINVAL;
+    HostChain& hc = h->ch[slot];
+    HostChain job;
+    int rc = build_chain(*p, (uint32_t)hc.cap_event, job);
+    if (rc) return rc;
+    ChainDev& d = job.d;
+    // the job must fit the slot's regions and launch tables
+    const int64_t ev = (int64_t)d.ntau * d.N * d.cap, su = (int64_t)d.ntau * d.N;
+    const int64_t bv = 2LL * d.ntau * d.N * d.capb;
+    if (ev > hc.cap_ev || su > hc.cap_su || bv > hc.cap_bv || job.n_dom > hc.cap_dom ||
+        (int64_t)job.cdf.size() > hc.cap_cdf || job.n_units_v > hc.cap_units_v ||
+        job.n_units_r > hc.cap_units_r || job.n_bt > hc.cap_bt || job.n_bsx > hc.cap_bsx ||
+        job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc)
+        return PMWA_EINVAL;
+    const ChainDev& s = hc.d;
+    d.ev_off = s.ev_off; d.cnt_off = s.cnt_off; d.bs_off = s.bs_off; d.bv_off = s.bv_off;
+    d.bvc_off = s.bvc_off; d.dom_off = s.dom_off; d.ser_off = s.ser_off; d.cdf_off = s.cdf_off;
+    d.scr_off = s.scr_off;
+    d.scr_nodes = (int32_t)std::min<int64_t>(hc.cap_scr / std::max<int64_t>(job.n_dom, 1), 0x7FFFFFFF);
+    d.active = 1;
+    d.target = target_sweeps;
+    // the staging buffer of the slot's previous install must have been consumed
+    HIPCHK(hipEventSynchronize(hc.staged));
+    std::memcpy(hc.staging, &d, sizeof(ChainDev));
+    std::memcpy(hc.staging + sizeof(ChainDev), job.cdf.data(), job.cdf.size() * sizeof(double));
+    hipStream_t st = h->stream;
+    HIPCHK(hipMemcpyAsync(h->d_cd + slot, hc.staging, sizeof(ChainDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(h->d_cdf + d.cdf_off, hc.staging + sizeof(ChainDev), job.cdf.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(hc.staged, st));
+    // the empty configuration
+    HIPCHK(hipMemsetAsync(h->P.cnt + d.cnt_off, 0, su * sizeof(int32_t), st));
+    HIPCHK(hipMemsetAsync(h->P.bs + d.bs_off, 0, su, st));
+    HIPCHK(hipMemsetAsync(h->P.bvc + d.bvc_off, 0, 2 * su * sizeof(int32_t), st));
+    HIPCHK(hipMemsetAsync(h->P.dpart + d.dom_off, 0, job.n_dom * sizeof(DomPart), st));
+    HIPCHK(hipMemsetAsync(h->P.sweep + slot, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(h->P.flags + slot, 0, sizeof(unsigned int), st));
+    HIPCHK(hipMemsetAsync(h->P.nnacc + slot, 0, sizeof(unsigned long long), st));
+    // host view: keep the slot's capacities, take the job's parameters
+    hc.p = job.p;
+    hc.d = d;
+    hc.cdf = job.cdf;
+    hc.C = job.C; hc.rho_max = job.rho_max; hc.delta = job.delta;
+    hc.n_units_v = job.n_units_v; hc.n_units_r = job.n_units_r; hc.n_dom = job.n_dom;
+    hc.n_bt = job.n_bt; hc.n_bsx = job.n_bsx; hc.n_bsy = job.n_bsy;
+    hc.enq_sweeps = hc.read_sweeps = 0;
+    hc.host_rows.clear();
+    hc.active = true;
+    hc.target = (uint64_t)target_sweeps;
+    return PMWA_OK;
+}
+
+int pmwa_slot_release(pmwa_t* h, int slot)
+{
+    if (!h || !h->slots || slot < 0 || slot >= (int)h->ch.size()) return PMWA_EINVAL;
+    HostChain& hc = h->ch[slot];
+    HIPCHK(hipEventSynchronize(hc.staged));
+    hc.d.active = 0;
+    std::memcpy(hc.staging, &hc.d, sizeof(ChainDev));
+    HIPCHK(hipMemcpyAsync(h->d_cd + slot, hc.staging, sizeof(ChainDev), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipEventRecord(hc.staged, h->stream));
+    hc.active = false;
+    hc.host_rows.clear();
+    hc.read_sweeps = hc.enq_sweeps;
+    return PMWA_OK;
+}
+
+int pmwa_slot_progress(pmwa_t* h, int slot, int64_t* sweeps_done)
+{
+    if (!h || !sweeps_done || slot < 0 || slot >= (int)h->ch.size()) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    unsigned long long sw = 0;
+    HIPCHK(hipMemcpy(&sw, h->P.sweep + slot, sizeof(sw), hipMemcpyDeviceToHost));
+    *sweeps_done = (int64_t)sw;
     return PMWA_OK;
 }
 
@@ -562,8 +697,7 @@ int pmwa_phase(pmwa_t* h, int phase)
             }
     }
     int rc = launch_phase(h, phase);
-    if (rc == PMWA_OK && phase == 7)
-        for (auto& hc : h->ch) hc.enq_sweeps++;
+    if (rc == PMWA_OK && phase == 7) advance_enq(h);
     return rc;
 }
 
@@ -606,7 +740,7 @@ int pmwa_sweep(pmwa_t* h, int64_t n)
                 if (rc) return rc;
             }
         }
-        for (auto& hc : h->ch) hc.enq_sweeps++;
+        advance_enq(h);
     }
     return PMWA_OK;
 }

@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
     }
     __syncthreads();
     long long nn = 0;
-    if (u < 2 * C.ntau * C.N && P.flags[bt.x] == 0) {
+    if (u < 2 * C.ntau * C.N && live(P, C, bt.x)) {
         const int sl = u % C.nloc;
         int r = u / C.nloc;
         const int dsp = r % C.ndsp;
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     __shared__ double sE[1024];
     for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
     __syncthreads();
-    if (u >= C.ntau * C.N || P.flags[bt.x] != 0) return;
+    if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
     const double lambda = C.lambda;
     const int sl = u % C.nloc;
@@ -691,7 +691,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     __syncthreads();
     const int NE = carry;
     const int NN = NE + 2 * nloc;
-    if (P.flags[bt.x] != 0) return;
+    if (!live(P, C, bt.x)) return;
 
     const size_t fixed = 1792 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
@@ -768,7 +768,7 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
     __shared__ double sE[1024];
     for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
     __syncthreads();
-    if (u >= C.N || P.flags[bt.x] != 0) return;
+    if (u >= C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
     const double lambda = C.lambda;
     const int dsp = u / C.nloc, sl = u % C.nloc;
@@ -934,7 +934,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     const int u = bt.y;
     const int lane = (int)threadIdx.x;
     const int nb_units = d == 0 ? (C.dom_x > 1 ? C.Ly * C.dom_x : 0) : (C.dom_y > 1 ? C.Lx * C.dom_y : 0);
-    if (u >= nb_units || P.flags[bt.x] != 0) return;
+    if (u >= nb_units || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
     int a;
     if (d == 0) { const int y = u / C.dom_x, dx = u % C.dom_x; a = y * C.Lx + dx * C.ex + C.ex - 1; }
@@ -1057,6 +1057,7 @@ __global__ void __launch_bounds__(256) k_finish(Pools P)
 {
     const int chain = blockIdx.x;
     const ChainDev& C = P.cd[chain];
+    if (!live(P, C, chain)) return;
     const int nd = (int)C.n_dom;
     const int tid = (int)threadIdx.x;
     const int per = (nd + 255) / 256;

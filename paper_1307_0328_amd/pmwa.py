@@ -19,7 +19,8 @@ PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
 
 EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
-           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times", "pmwa_diag"]
+           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times", "pmwa_diag",
+           "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
 
 
 class pmwa_params(C.Structure):
@@ -77,6 +78,10 @@ def lib():
         L.pmwa_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.pmwa_phase_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.pmwa_diag.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
+        L.pmwa_create_slots.argtypes = [P(pmwa_params), C.c_int, P(pmwa_opts), P(C.c_void_p)]
+        L.pmwa_slot_load.argtypes = [C.c_void_p, C.c_int, P(pmwa_params), C.c_int64]
+        L.pmwa_slot_release.argtypes = [C.c_void_p, C.c_int]
+        L.pmwa_slot_progress.argtypes = [C.c_void_p, C.c_int, P(C.c_int64)]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -114,6 +119,28 @@ def pmwa_create(chains, opts=None):
     h = C.c_void_p()
     _check(lib().pmwa_create(arr, len(chains), C.byref(o), C.byref(h)), "pmwa_create")
     return h
+
+
+def pmwa_create_slots(shapes, opts=None):
+    arr = (pmwa_params * len(shapes))(*shapes)
+    o = opts if opts is not None else pmwa_opts()
+    h = C.c_void_p()
+    _check(lib().pmwa_create_slots(arr, len(shapes), C.byref(o), C.byref(h)), "pmwa_create_slots")
+    return h
+
+
+def pmwa_slot_load(h, slot, p, target_sweeps):
+    _check(lib().pmwa_slot_load(h, slot, C.byref(p), int(target_sweeps)), "pmwa_slot_load")
+
+
+def pmwa_slot_release(h, slot):
+    _check(lib().pmwa_slot_release(h, slot), "pmwa_slot_release")
+
+
+def pmwa_slot_progress(h, slot):
+    n = C.c_int64()
+    _check(lib().pmwa_slot_progress(h, slot, C.byref(n)), "pmwa_slot_progress")
+    return int(n.value)
 
 
 def pmwa_sweep(h, n):

@@ -49,27 +49,38 @@ def large_2048(L: int = 2048) -> list[dict]:
                  dom_x=L // 32, dom_y=L // 32, dom_tau=4, ticks_log2=24, seed=4, chain_id=0)]
 
 
-def serving_jobs(n_jobs: int, rate: float = 50.0, seed: int = 4, max_L: int = 256,
-                 sweeps_lo: float = 1e3, sweeps_hi: float = 1e5) -> list[dict]:
-    """Poisson arrivals (mean `rate` per second); each job a chain with L
-    uniform in [16, max_L] (a multiple of 8, domain edge 8 or 16), beta*t
-    uniform in [2, 32], mu uniform in [-2, 2], V in {0, 1}, eta=0.05, sweeps
-    log-uniform in [sweeps_lo, sweeps_hi].  The domain grid is a function of
-    the job's own parameters only."""
+def serving_jobs(n_jobs: int, rate: float = 50.0, seed: int = 4, L_lo: int = 16, L_hi: int = 256,
+                 beta_lo: float = 2.0, beta_hi: float = 32.0, sweeps_lo: float = 1e3,
+                 sweeps_hi: float = 1e5, edge: int = 8, slab_beta: float = 8.0) -> list[dict]:
+    """Poisson arrivals (mean `rate` per second).  Each job is a chain with L
+    uniform over the multiples of `edge` in [L_lo, L_hi], beta*t uniform in
+    [beta_lo, beta_hi], mu uniform in [-2, 2], V in {0, 1}, eta = 0.05, and a
+    sweep count log-uniform in [sweeps_lo, sweeps_hi].  Its domain grid is a
+    function of its own parameters only: `edge` sites per domain edge, and
+    temporal slabs of at most `slab_beta`.  chain_id = job index."""
     rng = np.random.default_rng(seed)
     t = 0.0
     jobs = []
     for j in range(n_jobs):
         t += rng.exponential(1.0 / rate)
-        L = int(rng.integers(2, max_L // 8 + 1)) * 8
-        beta = float(rng.uniform(2.0, 32.0))
+        L = int(rng.integers(L_lo // edge, L_hi // edge + 1)) * edge
+        beta = float(rng.uniform(beta_lo, beta_hi))
         mu = float(rng.uniform(-2.0, 2.0))
         V = float(rng.integers(0, 2))
         sweeps = int(round(np.exp(rng.uniform(np.log(sweeps_lo), np.log(sweeps_hi)))))
-        edge = 16 if L % 16 == 0 and L >= 32 else 8
-        ntau = max(1, int(np.ceil(beta / 8.0)))
+        ntau = max(1, int(np.ceil(beta / slab_beta)))
         jobs.append(dict(arrival=t, sweeps=sweeps,
                          params=dict(Lx=L, Ly=L, beta=beta, t=1.0, V=V, mu=mu, eta=0.05,
                                      dom_x=L // edge, dom_y=L // edge, dom_tau=ntau,
                                      ticks_log2=24, seed=5, chain_id=j)))
     return jobs
+
+
+def serving_slot_shape(L_max: int, beta_max: float, edge: int = 8, slab_beta: float = 8.0) -> dict:
+    """The largest job of `serving_jobs` with these bounds: the most sites,
+    slabs and domains, and the longest Poisson table (V = 1, mu = -2, full
+    slabs)."""
+    ntau = max(1, int(np.ceil(beta_max / slab_beta)))
+    return dict(Lx=L_max, Ly=L_max, beta=slab_beta * ntau, t=1.0, V=1.0, mu=-2.0, eta=0.05,
+                dom_x=L_max // edge, dom_y=L_max // edge, dom_tau=ntau, ticks_log2=24,
+                seed=0, chain_id=0)
