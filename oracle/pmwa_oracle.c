@@ -782,17 +782,20 @@ static void worm_step(orc_chain* c, int k, wref* w, rstream* s)
     int i = up ? (x == a ? 0 : 1) : (x == a ? 2 : 3);
     int64_t Lmin = L[0];
     for (int j = 1; j < 4; j++) if (L[j] < Lmin) Lmin = L[j];
+    /* an attempt that faces an interior vertex draws three words: the enter
+       test, the exit leg, the landing slot (the last two unused if it turns) */
+    uint64_t w_enter = rs_next(s), w_exit = rs_next(s), w_slot = rs_next(s);
     /* enter with probability L_min / L_i */
-    uint64_t r = below(rs_next(s), (uint64_t)L[i]);
+    uint64_t r = below(w_enter, (uint64_t)L[i]);
     if ((int64_t)r >= Lmin) { lx->e[iw].dir ^= 1; return; }
 
     int S = state_below(c, a, k, va) | (state_below(c, cc, k, vc) << 1)
           | (c->site[a].e[va].up << 2) | (c->site[cc].e[vc].up << 3);
     int S0 = S ^ (1 << i);
-    double u = u53(rs_next(s));
+    double u = u53(w_exit);
     int j = 0;
     while (!(u < c->scat[S0][i][j])) j++;
-    uint64_t r2 = below(rs_next(s), (uint64_t)L[j]);
+    uint64_t r2 = below(w_slot, (uint64_t)L[j]);
 
     /* move: remove the worm from leg i */
     int wup = lx->e[iw].up;

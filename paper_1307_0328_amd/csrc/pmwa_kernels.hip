@@ -290,14 +290,15 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
     return (uint32_t)(hi >> 32);
 }
 
-// Steps 5-6 over windows of up to 64 consecutive attempts of the serial
-// sequence (cycle-major, worm-list order).  Lane k evaluates attempt s0+k on
-// the state at the start of the window.  The first attempt whose read set
-// meets a node an earlier attempt of the window may write ends the window
-// (owner stamps, LDS atomicMax).  A short in-order scan gives each surviving
-// attempt its position in the domain's random-word stream; the surviving
-// moves touch disjoint nodes and are applied together.  Decisions and the
-// final state equal those of the attempts made one at a time in order.
+// Steps 5-6 over windows of consecutive attempts of the serial sequence
+// (cycle-major, worm-list order), at most one attempt per worm in a window.
+// Lane k evaluates attempt s0+k on the state at the start of the window.
+// The first attempt whose read set meets a node an earlier attempt of the
+// window may write ends the window (owner stamps, LDS atomicMax).  An attempt
+// facing an interior vertex draws three words, so the stream position of
+// each attempt is a prefix count.  The surviving moves touch disjoint nodes
+// and are applied together; decisions and the final state equal those of the
+// attempts made one at a time in order.
 //
 // One attempt (Step 5): a worm facing another worm, a temporal boundary or a
 // boundary vertex reverses; facing an interior vertex it enters with
@@ -313,8 +314,10 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
     long long windows = 0;
     const int lane = (int)threadIdx.x;
     const long long total = (long long)C.ncycle * nw;
+    const int wmax = nw < 64 ? nw : 64;
     const uint32_t k0 = C.key0, k1 = C.key1, c1 = D, c2 = sweep, c3 = (C.chain_id << 8) | RNG_S;
     uint32_t cur = 0, filled = 0, wid = 0;
+    int iw0 = 0;                       // worm-list position of attempt s0
     for (long long s0 = 0; s0 < total;) {
         // words [cur, cur + 192) of the stream sit in the 512-word ring
         while (filled < cur + 192u) {
@@ -329,15 +332,16 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             wid = 1;
         }
         __syncthreads();
-        const long long s = s0 + lane;
-        const bool act = s < total;
+        const bool act = lane < wmax && s0 + lane < total;
         // ---- evaluate on the window's starting state
         uint32_t w = 0, fw = 0, pw = 0, nn_ = 0, x = 0, fx = 0, y = 0, xf = 0, wf = 0;
         uint32_t fy = 0, yp = 0, yn = 0, f_wf = 0, f_xf = 0, f_yp = 0;
         int32_t t = 0, t_wf = 0, t_xf = 0, t_yp = 0, t_yn = 0;
         bool blocked = true, up = false;
         if (act) {
-            w = A.wl[(int)(s % nw)];
+            int iw = iw0 + lane;
+            if (iw >= nw) iw -= nw;
+            w = A.wl[iw];
             fw = A.fl[w];
             pw = A.prv[w];
             nn_ = A.nxt[w];
@@ -374,19 +378,22 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         Lmin = L3 < Lmin ? L3 : Lmin;
         const int32_t Li = up ? Lxb : Lxa;
         const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
-        // ---- nodes this attempt may write; conflicts with earlier attempts
+        // ---- nodes a moving attempt may write; conflicts with earlier attempts.
+        //      (A turning attempt only flips its own worm's direction, which no
+        //      other attempt of the window reads.)
+        const bool mover = act && !blocked;
         const uint32_t stamp = (wid << 8) | (uint32_t)(255 - lane);
-        if (act) {
-            atomicMax(&own[w], stamp);
-            if (!blocked) {
-                atomicMax(&own[pw], stamp);
-                atomicMax(&own[nn_], stamp);
-                atomicMax(&own[xf], stamp);
-                atomicMax(&own[y], stamp);
-                atomicMax(&own[yp], stamp);
-                atomicMax(&own[yn], stamp);
-            }
+        if (mover) {
+            atomicMax(&own[pw], stamp);
+            atomicMax(&own[nn_], stamp);
+            atomicMax(&own[xf], stamp);
+            atomicMax(&own[y], stamp);
+            atomicMax(&own[yp], stamp);
+            atomicMax(&own[yn], stamp);
         }
+        // stream position: three words per attempt facing an interior vertex
+        const unsigned long long mmask = __ballot(mover);
+        const uint32_t myc = cur + 3u * (uint32_t)__popcll(mmask & ((1ULL << lane) - 1ULL));
         __syncthreads();
         bool conflict = !act;
         if (act) {
@@ -403,26 +410,6 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         }
         const unsigned long long cmask = __ballot(conflict);
         const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
-        // ---- stream position of each surviving attempt, in order; lane l
-        //      holds words cur+l, cur+64+l, cur+128+l of the stream
-        const uint64_t wv0 = ring[(cur + (uint32_t)lane) & 511u];
-        const uint64_t wv1 = ring[(cur + 64u + (uint32_t)lane) & 511u];
-        const uint64_t wv2 = ring[(cur + 128u + (uint32_t)lane) & 511u];
-        uint32_t c = cur, myc = cur;
-        for (int k = 0; k < kc; k++) {
-            if (lane == k) myc = c;
-            const int32_t li = __builtin_amdgcn_readlane(blocked ? 0 : Li, k);
-            if (li != 0) {
-                const int32_t lm = __builtin_amdgcn_readlane(Lmin, k);
-                const uint32_t q = c - cur;
-                const uint64_t wq = q < 64u ? wv0 : q < 128u ? wv1 : wv2;
-                const int ln = (int)(q & 63u);
-                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wq, ln);
-                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(wq >> 32), ln);
-                const uint32_t r = below32(((uint64_t)hi << 32) | lo, (uint32_t)li);
-                c += (int32_t)r < lm ? 3u : 1u;
-            }
-        }
         // ---- apply the surviving attempts (disjoint nodes)
         if (lane < kc) {
             bool moved = false;
@@ -474,8 +461,10 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             }
         }
         __syncthreads();
-        cur = c;
+        cur += 3u * (uint32_t)__popcll(mmask & (kc >= 64 ? ~0ULL : ((1ULL << kc) - 1ULL)));
         s0 += kc;
+        iw0 += kc;
+        if (iw0 >= nw) iw0 -= nw;
         windows++;
     }
     return windows;
