@@ -61,7 +61,7 @@ typedef struct pmwa_params {
     double   t, V, mu, eta;   /* hopping >= 0, repulsion, chem. potential, eta > 0 */
     int32_t  dom_x, dom_y;    /* spatial domain grid; Lx % dom_x == 0, extent >= 2 */
     int32_t  dom_tau;         /* temporal domains N_beta, 1..64                    */
-    int32_t  ticks_log2;      /* M = 2^ticks_log2 ticks per beta, 8..30            */
+    int32_t  ticks_log2;      /* M = 2^ticks_log2 ticks per beta, 8..29            */
     int32_t  n_cycle;         /* scattering cycles per sweep; <= 0: ceil(4 C/eta)  */
     double   C;               /* diagonal shift; NaN: max_s E_b(s) + t/2          */
     uint64_t seed;            /* Philox key                                        */

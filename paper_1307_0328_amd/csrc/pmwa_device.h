@@ -11,8 +11,9 @@
 //   counts          cnt[cnt_off + u]
 //   boundary state  bs[bs_off + u]       occupation just above T_k
 //   bond buffer     bv[bv_off + (((k*2 + d)*ndsp + dsp) * capb + j) * nloc + sl]
-//                   new diagonal vertices of bond (site, +d) in slab k:
-//                   tick | s_a << 30 | s_c << 31
+//                   vertices of bond (site, +d) in slab k after the vertex
+//                   phase, in tick order: tick | kink << 29 | s_a << 30 |
+//                   s_c << 31 (occupations just below the vertex)
 //   event info      bit0 worm; bit3 occupation just above; vertex bits1-2 =
 //                   bond direction seen from this site (0 +x, 1 +y, 2 -x,
 //                   3 -y); worm bit1 = moving up.
@@ -29,8 +30,9 @@ namespace pmwa {
 constexpr int NT_MAX = 64;      // temporal domains
 constexpr int KMAXC = 256;      // Poisson table entries = max candidates per bond-slab
 constexpr int NWL = 48;         // worms drawn on one interval
-constexpr int KINKMAX = 128;    // kinks kept per (site, slab)
 constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr uint32_t BV_TICK = (1u << 29) - 1u;   // bond-buffer entry: tick bits
+constexpr uint32_t BV_KINK = 1u << 29;          //   kink (occupations flip)
 
 // stream kinds in Philox counter word 3 (low byte)
 enum : uint32_t { RNG_V = 1, RNG_R = 2, RNG_S = 3, RNG_BT = 4, RNG_BS = 5 };
@@ -244,14 +246,37 @@ PMWA_DEV int choose(const double (&W)[N], double u)
     return pick >= 0 ? pick : last;
 }
 
+// Sorts v[0], v[64], ..., v[64(n-1)] (one lane's column of an LDS array)
+// ascending; returns true when two entries are equal.
+PMWA_DEV bool sort_col(int32_t* v, int n)
+{
+    bool rep = false;
+    for (int x = 1; x < n; x++) {
+        const int32_t t = v[x * 64];
+        int y = x - 1;
+        int32_t w = v[y * 64];
+        while (w > t) {
+            v[(y + 1) * 64] = w;
+            if (--y < 0) break;
+            w = v[y * 64];
+        }
+        rep |= (y >= 0 && w == t);
+        v[(y + 1) * 64] = t;
+    }
+    return rep;
+}
+
 // Worms of one interval with `ell` free slots and end-state parity sigma:
 // count by inversion of x^n/n!/f_sigma(x), x = lambda*ell, n <= ell (redraw
 // otherwise); distinct uniform offsets in [0, ell), sorted; one direction
-// bit per worm in ascending order.  Returns n, or -1 on failure (flagged).
+// bit per worm in ascending order.  Offsets go to off[0], off[64], ... (the
+// lane's column of an LDS array), direction bit i to bit i of `dirs`.
+// Returns n, or -1 on failure (flagged).
 template <class RS>
 PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, long long ell,
-                          int sigma, int32_t* off, uint8_t* dirs, unsigned int* flag)
+                          int sigma, int32_t* off, uint64_t& dirs, unsigned int* flag)
 {
+    dirs = 0;
     if (ell == 0) {
         if (sigma) atomicOr(flag, FL_SAMPLER);
         return 0;
@@ -281,18 +306,13 @@ PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, lo
         do {
             r = (int32_t)below(s.next(), (uint64_t)ell);
             again = false;
-            for (int j = 0; j < i; j++) again |= (off[j] == r);
+            for (int j = 0; j < i; j++) again |= (off[j * 64] == r);
         } while (again && ++guard < 100000);
         if (again) { atomicOr(flag, FL_SAMPLER); return -1; }
-        off[i] = r;
+        off[i * 64] = r;
     }
-    for (int a = 1; a < n; a++) {
-        int32_t v = off[a];
-        int b = a - 1;
-        while (b >= 0 && off[b] > v) { off[b + 1] = off[b]; b--; }
-        off[b + 1] = v;
-    }
-    for (int i = 0; i < n; i++) dirs[i] = (uint8_t)(s.next() >> 63);
+    sort_col(off, n);
+    for (int i = 0; i < n; i++) dirs |= (s.next() >> 63) << i;
     return n;
 }
 

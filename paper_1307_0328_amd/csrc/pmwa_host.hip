@@ -21,7 +21,7 @@
 #include "pmwa_device.h"
 
 namespace pmwa {
-__global__ void k_vertex(Pools P, const int2* __restrict__ blk);
+__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
 __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
@@ -77,6 +77,8 @@ struct pmwa_handle {
     int nblk_v = 0, nblk_r = 0, nblk_s = 0, nblk_bt = 0, nblk_bsx = 0, nblk_bsy = 0;
     size_t lds_bytes = 0;
     size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
+    int vs = 1;              // candidate column length of the vertex kernel
+    size_t v_lds = 0;
     int64_t ev_total = 0, site_slabs = 0;
     bool slots = false;
     int max_nloc = 1;
@@ -137,7 +139,7 @@ static int validate(const pmwa_params& p)
     if (p.dom_x < 1 || p.dom_y < 1 || p.dom_tau < 1 || p.dom_tau > NT_MAX) return 0;
     if (p.Lx % p.dom_x || p.Ly % p.dom_y) return 0;
     if (p.Lx / p.dom_x < 2 || p.Ly / p.dom_y < 2) return 0;
-    if (p.ticks_log2 < 8 || p.ticks_log2 > 30) return 0;
+    if (p.ticks_log2 < 8 || p.ticks_log2 > 29) return 0;
     if ((int64_t(1) << p.ticks_log2) / p.dom_tau < 2) return 0;
     if (p.chain_id >= (1u << 24)) return 0;
     if ((int64_t)p.Lx * p.Ly >= (int64_t(1) << 28)) return 0;
@@ -230,7 +232,12 @@ static int build_chain(const pmwa_params& p, uint32_t cap_override, HostChain& h
         stride = std::max(stride, (int)t.size());
     }
     d.cdf_stride = stride;
-    d.capb = stride;
+    // bond buffer: candidates plus the kinks kept; the mean number of kinks of
+    // a bond in a slab is at most t times the slab's beta
+    {
+        const double tb = p.t * p.beta / (double)d.ntau;
+        d.capb = stride + 16 + (int)std::ceil(2.0 * tb + 6.0 * std::sqrt(tb + 1.0));
+    }
     hc.cdf.assign((size_t)d.ntau * stride, 2.0);
     for (int k = 0; k < d.ntau; k++)
         std::copy(tabs[k].begin(), tabs[k].end(), hc.cdf.begin() + (size_t)k * stride);
@@ -323,7 +330,7 @@ static int launch_kernel(pmwa_t* h, int phase)
     hipStream_t s = h->stream;
     switch (phase) {
     case 1:
-        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), 0, s, h->P, h->d_blk_v);
+        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), h->v_lds, s, h->P, h->d_blk_v, h->vs);
         break;
     case 2:
         if (h->nblk_r) hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(64), 0, s, h->P, h->d_blk_r);
@@ -559,10 +566,18 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     {
         int maxcap = 0;
         for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
-        h->bs_lds = 1024 * sizeof(double) + (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2);
+        h->bs_lds = 1024 * sizeof(double) + (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2) +
+                    (size_t)NWL * 64 * sizeof(int32_t);
         if (h->bs_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->bs_lds);
+        int vs = 1;
+        for (auto& hc : h->ch) vs = std::max(vs, hc.d.cdf_stride);
+        h->vs = vs;
+        h->v_lds = (size_t)vs * (2 * sizeof(double) + 64 * sizeof(int32_t));
+        if (h->v_lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)k_vertex, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)h->v_lds);
     }
     if (r2) { pmwa_destroy(h); return r2; }
     // the empty configuration
@@ -620,7 +635,7 @@ int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_swe
     if (ev > hc.cap_ev || su > hc.cap_su || bv > hc.cap_bv || job.n_dom > hc.cap_dom ||
         (int64_t)job.cdf.size() > hc.cap_cdf || job.n_units_v > hc.cap_units_v ||
         job.n_units_r > hc.cap_units_r || job.n_bt > hc.cap_bt || job.n_bsx > hc.cap_bsx ||
-        job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc)
+        job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc || d.cdf_stride > h->vs)
         return PMWA_EINVAL;
     const ChainDev& s = hc.d;
     d.ev_off = s.ev_off; d.cnt_off = s.cnt_off; d.bs_off = s.bs_off; d.bv_off = s.bv_off;

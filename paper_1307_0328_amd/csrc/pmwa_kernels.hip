@@ -13,7 +13,8 @@ namespace pmwa {
 // Step 3: vertex phase.  One lane per (bond, slab): keep the kinks, draw a
 // Poisson(rho_max * Delta * dT_k) number of candidate ticks, and accept each
 // with w_d(state)/rho_max (thinning gives the density of the diagonal matrix
-// element).  Also integrates n_a n_c over the slab (before the update).
+// element).  Also integrates n_a n_c over the slab (before the update).  The
+// bond's kinks and accepted vertices go to its bond buffer in tick order.
 // ===========================================================================
 PMWA_DEV bool key_before(const ChainDev& C, int site, uint2 e, int32_t tick, long long bid)
 {
@@ -23,13 +24,99 @@ PMWA_DEV bool key_before(const ChainDev& C, int site, uint2 e, int32_t tick, lon
     return bond_id(C, site, (int)ev_dir(e.y)) < bid;
 }
 
-__global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__ blk)
+struct BondEnds {
+    const uint2* Ea;     // events of site a (the bond's lower end), stride st
+    const uint2* Ec;     // events of site c = a + e_d
+    int na, nc, st, sa0, sc0, a, c, d;
+    long long bid;
+};
+
+// One ordered pass over the events of both ends, with the sorted candidate
+// ticks cand[0..np) (a lane column of LDS) taken at their place in the site
+// order.  Kinks of the bond and accepted candidates are written to `out` in
+// tick order.  With INTEG, also integrates n_a n_c in half ticks over
+// [2 T_k, 2 T_k+1).  A candidate on the tick of a kink of the bond stops the
+// candidates (returns -1; the integral is still completed); otherwise
+// returns the number of entries.
+template <bool INTEG>
+PMWA_DEV int bond_walk(const ChainDev& C, const BondEnds& B, int32_t Tk, int32_t Tk1,
+                       const int32_t* cand, int np, Stream& rs, uint32_t* out, int capb,
+                       long long& nn)
 {
+    const double acc0 = C.acc[0], acc1 = C.acc[1], acc2 = C.acc[2], acc3 = C.acc[3];
+    int ia = 0, ic = 0, s_a = B.sa0, s_c = B.sc0, i = 0, nout = 0;
+    bool clash = false;
+    long long last = 2LL * Tk;
+    uint2 ea = B.na > 0 ? B.Ea[0] : make_uint2(0, 0);
+    uint2 ec = B.nc > 0 ? B.Ec[0] : make_uint2(0, 0);
+    int32_t tau = np > 0 ? cand[0] : 0;
+    for (;;) {
+        const bool ha = ia < B.na, hc = ic < B.nc;
+        const bool pend = i < np;
+        const bool ka = pend && ha && key_before(C, B.a, ea, tau, B.bid);
+        const bool kc = pend && hc && key_before(C, B.c, ec, tau, B.bid);
+        if (pend && !ka && !kc) {
+            // every object ordered before the candidate has been passed
+            if (ha && (int32_t)ea.x == tau && !ev_worm(ea.y) && (int)ev_dir(ea.y) == B.d &&
+                (int)ev_up(ea.y) != s_a) {
+                clash = true;
+                np = i;
+                if (!INTEG) break;
+                continue;
+            }
+            const double uu = u53(rs.next());
+            const int sidx = s_a | (s_c << 1);
+            const double accv = sidx == 0 ? acc0 : sidx == 1 ? acc1 : sidx == 2 ? acc2 : acc3;
+            if (uu < accv) {
+                if (nout < capb) out[(long long)nout * B.st] = (uint32_t)tau | ((uint32_t)s_a << 30) | ((uint32_t)s_c << 31);
+                nout++;
+            }
+            i++;
+            if (i < np) tau = cand[i * 64];
+            continue;
+        }
+        if (!ha && !hc) break;
+        if (!INTEG && !pend) {
+            // only kinks of the bond are left to copy
+            if (!ha) break;
+        }
+        const bool takea = pend ? (ka && (!kc || pos2(ea) <= pos2(ec)))
+                                : (!hc || (ha && pos2(ea) <= pos2(ec)));
+        if (INTEG) {
+            const long long p = pos2(takea ? ea : ec);
+            nn += (long long)(s_a & s_c) * (p - last);
+            last = p;
+        }
+        if (takea) {
+            const int up = (int)ev_up(ea.y);
+            if (!clash && !ev_worm(ea.y) && (int)ev_dir(ea.y) == B.d && up != s_a) {
+                if (nout < capb)
+                    out[(long long)nout * B.st] = ea.x | BV_KINK | ((uint32_t)s_a << 30) | ((uint32_t)(s_a ^ 1) << 31);
+                nout++;
+            }
+            s_a = up;
+            ia++;
+            if (ia < B.na) ea = B.Ea[(long long)ia * B.st];
+        } else {
+            s_c = (int)ev_up(ec.y);
+            ic++;
+            if (ic < B.nc) ec = B.Ec[(long long)ic * B.st];
+        }
+    }
+    if (INTEG) nn += (long long)(s_a & s_c) * (2LL * Tk1 - last);
+    return clash ? -1 : nout;
+}
+
+// dynamic LDS: Poisson tables of the first two slabs of the block (2 * vs
+// doubles), then the candidate ticks, one column of vs entries per lane
+__global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__ blk, int vs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    // Poisson tables of the (at most two) first slabs this block touches
-    __shared__ double s_cdf[2 * KMAXC];
+    double* s_cdf = reinterpret_cast<double*>(smem);
+    int32_t* cand = reinterpret_cast<int32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + threadIdx.x;
     const int k_first = bt.y / (2 * C.N);
     for (int i = (int)threadIdx.x; i < 2 * C.cdf_stride; i += 64) {
         const int kk = k_first + i / C.cdf_stride;
@@ -38,117 +125,84 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
     __syncthreads();
     long long nn = 0;
     if (u < 2 * C.ntau * C.N && live(P, C, bt.x)) {
+        unsigned int* flag = &P.flags[bt.x];
         const int sl = u % C.nloc;
         int r = u / C.nloc;
         const int dsp = r % C.ndsp;
         r /= C.ndsp;
         const int d = r & 1, k = r >> 1;
-        const int a = site_join(C, dsp, sl);
-        const int c = nbr(C, a, d);
+        BondEnds B;
+        B.a = site_join(C, dsp, sl);
+        B.c = nbr(C, B.a, d);
+        B.d = d;
         int dspc, slc;
-        site_split(C, c, dspc, slc);
-        const long long bid = 2LL * a + d;
-        const uint32_t sweep = (uint32_t)P.sweep[bt.x];
-        const int na = P.cnt[C.cnt_off + unit_su(C, k, dsp, sl)];
-        const int nc = P.cnt[C.cnt_off + unit_su(C, k, dspc, slc)];
-        const int sa0 = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
-        const int sc0 = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
-        const uint2* Ea = P.ev + ev_base(C, k, dsp, sl);
-        const uint2* Ec = P.ev + ev_base(C, k, dspc, slc);
-        const int st = C.nloc;
+        site_split(C, B.c, dspc, slc);
+        B.bid = 2LL * B.a + d;
+        B.na = P.cnt[C.cnt_off + unit_su(C, k, dsp, sl)];
+        B.nc = P.cnt[C.cnt_off + unit_su(C, k, dspc, slc)];
+        B.sa0 = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
+        B.sc0 = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
+        B.Ea = P.ev + ev_base(C, k, dsp, sl);
+        B.Ec = P.ev + ev_base(C, k, dspc, slc);
+        B.st = C.nloc;
         const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
-
-        // integral of n_a n_c over the slab, half-tick units
-        {
-            int ia = 0, ic = 0, s_a = sa0, s_c = sc0;
-            long long last = 2LL * Tk;
-            uint2 ea = ia < na ? Ea[0] : make_uint2(0, 0);
-            uint2 ec = ic < nc ? Ec[0] : make_uint2(0, 0);
-            while (ia < na || ic < nc) {
-                bool takea = (ic >= nc) || (ia < na && pos2(ea) <= pos2(ec));
-                uint2 e = takea ? ea : ec;
-                long long p = pos2(e);
-                nn += (long long)(s_a & s_c) * (p - last);
-                last = p;
-                if (takea) { s_a = (int)ev_up(e.y); ia++; if (ia < na) ea = Ea[(long long)ia * st]; }
-                else { s_c = (int)ev_up(e.y); ic++; if (ic < nc) ec = Ec[(long long)ic * st]; }
-            }
-            nn += (long long)(s_a & s_c) * (2LL * Tk1 - last);
-        }
-
-        // kinks of this bond survive
-        int32_t kinks[KINKMAX];
-        int nk = 0;
-        {
-            int s = sa0;
-            for (int j = 0; j < na; j++) {
-                uint2 e = Ea[(long long)j * st];
-                int up = (int)ev_up(e.y);
-                if (!ev_worm(e.y) && (int)ev_dir(e.y) == d && up != s) {
-                    if (nk < KINKMAX) kinks[nk++] = (int32_t)e.x;
-                    else atomicOr(&P.flags[bt.x], FL_OVERFLOW);
-                }
-                s = up;
-            }
-        }
+        const uint32_t sweep = (uint32_t)P.sweep[bt.x];
+        const int capb = C.capb;
+        uint32_t* out = P.bv + C.bv_off + (long long)((k * 2 + d) * C.ndsp + dsp) * capb * C.nloc + sl;
 
         Stream rs;
-        rs.init(C, sweep, RNG_V, (uint32_t)(bid * C.ntau + k));
+        rs.init(C, sweep, RNG_V, (uint32_t)(B.bid * C.ntau + k));
         const double* cdf = (k - k_first < 2) ? s_cdf + (k - k_first) * C.cdf_stride
                                               : P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
-        const double acc0 = C.acc[0], acc1 = C.acc[1], acc2 = C.acc[2], acc3 = C.acc[3];
         const double u0 = u53(rs.next());
         int n = 0;
         while (!(u0 < cdf[n])) n++;
-        int32_t cand[KMAXC];
         const uint64_t dT = (uint64_t)(Tk1 - Tk);
-        for (int i = 0; i < n; i++) {
-            int32_t tau;
-            bool again;
-            int guard = 0;
-            do {
-                tau = Tk + (int32_t)below(rs.next(), dT);
-                again = false;
-                for (int j = 0; j < nk; j++) again |= (kinks[j] == tau);
-                for (int j = 0; j < i; j++) again |= (cand[j] == tau);
-            } while (again && ++guard < 100000);
-            if (again) { atomicOr(&P.flags[bt.x], FL_SAMPLER); n = i; break; }
-            cand[i] = tau;
-        }
-        for (int x = 1; x < n; x++) {
-            int32_t v = cand[x];
-            int y = x - 1;
-            while (y >= 0 && cand[y] > v) { cand[y + 1] = cand[y]; y--; }
-            cand[y + 1] = v;
-        }
-        // occupations seen at each candidate (sorted), then acceptance
-        uint32_t* out = P.bv + C.bv_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.capb * C.nloc + sl;
-        int ia = 0, ic = 0, s_a = sa0, s_c = sc0, nacc = 0;
-        for (int i = 0; i < n; i++) {
-            const int32_t tau = cand[i];
-            while (ia < na) {
-                uint2 e = Ea[(long long)ia * st];
-                if (!key_before(C, a, e, tau, bid)) break;
-                s_a = (int)ev_up(e.y);
-                ia++;
+        // ticks as first drawn; they are the ticks kept unless one repeats
+        // a kink of the bond or another candidate
+        for (int i = 0; i < n; i++) cand[i * 64] = Tk + (int32_t)below(rs.next(), dT);
+        const bool rep = sort_col(cand, n);
+        int nout = bond_walk<true>(C, B, Tk, Tk1, cand, rep ? 0 : n, rs, out, capb, nn);
+        if (rep || nout < 0) {
+            // exact sequential draws: a tick on a kink of the bond or on an
+            // earlier candidate is drawn again.  The kinks are listed in the
+            // bond buffer first (it is rewritten below).
+            int nk = 0;
+            {
+                int s = B.sa0;
+                for (int j = 0; j < B.na; j++) {
+                    const uint2 e = B.Ea[(long long)j * B.st];
+                    const int up = (int)ev_up(e.y);
+                    if (!ev_worm(e.y) && (int)ev_dir(e.y) == d && up != s) {
+                        if (nk < capb) out[(long long)nk * B.st] = e.x;
+                        nk++;
+                    }
+                    s = up;
+                }
             }
-            while (ic < nc) {
-                uint2 e = Ec[(long long)ic * st];
-                if (!key_before(C, c, e, tau, bid)) break;
-                s_c = (int)ev_up(e.y);
-                ic++;
+            if (nk > capb) { atomicOr(flag, FL_OVERFLOW); nk = capb; }
+            rs.init(C, sweep, RNG_V, (uint32_t)(B.bid * C.ntau + k));
+            (void)rs.next();
+            for (int i = 0; i < n; i++) {
+                int32_t tau;
+                bool again;
+                int guard = 0;
+                do {
+                    tau = Tk + (int32_t)below(rs.next(), dT);
+                    again = false;
+                    for (int j = 0; j < nk; j++) again |= ((int32_t)out[(long long)j * B.st] == tau);
+                    for (int j = 0; j < i; j++) again |= (cand[j * 64] == tau);
+                } while (again && ++guard < 100000);
+                if (again) { atomicOr(flag, FL_SAMPLER); n = i; break; }
+                cand[i * 64] = tau;
             }
-            const double uu = u53(rs.next());
-            const int sidx = s_a | (s_c << 1);
-            const double accv = sidx == 0 ? acc0 : sidx == 1 ? acc1 : sidx == 2 ? acc2 : acc3;
-            if (uu < accv) {
-                if (nacc < C.capb)
-                    out[(long long)nacc * st] = (uint32_t)tau | ((uint32_t)s_a << 30) | ((uint32_t)s_c << 31);
-                nacc++;
-            }
+            sort_col(cand, n);
+            long long unused = 0;
+            nout = bond_walk<false>(C, B, Tk, Tk1, cand, n, rs, out, capb, unused);
+            if (nout < 0) { atomicOr(flag, FL_STATE); nout = 0; }
         }
-        if (nacc > C.capb) { atomicOr(&P.flags[bt.x], FL_OVERFLOW); nacc = C.capb; }
-        P.bvc[C.bvc_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.nloc + sl] = nacc;
+        if (nout > capb) { atomicOr(flag, FL_OVERFLOW); nout = capb; }
+        P.bvc[C.bvc_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.nloc + sl] = nout;
     }
     // wave sum of the bond occupation integral -> one atomic per block
     for (int o = 32; o > 0; o >>= 1) nn += __shfl_down(nn, o, 64);
@@ -156,9 +210,10 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
 }
 
 // ===========================================================================
-// Step 4: per (site, slab) merge the surviving kinks with the new diagonal
-// vertices of the four bonds of the site, erase all worms, and regenerate
-// them on every interval with Eq. (worm).  Written in place.
+// Step 4: per (site, slab) merge the vertex lists of the four bonds of the
+// site (kinks and new diagonal vertices, from the bond buffers) in (tick,
+// bond id) order, and generate the worms of every interval with Eq. (worm).
+// The site's old list (old vertices and worms) is overwritten.
 // ===========================================================================
 __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict__ blk)
 {
@@ -166,10 +221,12 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
     __shared__ double sE[1024];
+    __shared__ int32_t s_off[NWL * 64];
     for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
     __syncthreads();
     if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
+    int32_t* off = s_off + threadIdx.x;
     const double lambda = C.lambda;
     const int sl = u % C.nloc;
     const int r = u / C.nloc;
@@ -178,86 +235,74 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     const int st = C.nloc;
     uint2* E = P.ev + ev_base(C, k, dsp, sl);
     const long long cu = C.cnt_off + unit_su(C, k, dsp, sl);
-    const int n_old = P.cnt[cu];
     const int s_lo = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
     const int s_hi = P.bs[C.bs_off + unit_su(C, (k + 1) % C.ntau, dsp, sl)];
 
-    // surviving kinks: tick, dir | below << 2 | above << 3
-    int32_t kt[KINKMAX];
-    uint8_t kf[KINKMAX];
-    int nk = 0;
-    {
-        int s = s_lo;
-        for (int j = 0; j < n_old; j++) {
-            uint2 e = E[(long long)j * st];
-            int up = (int)ev_up(e.y);
-            if (!ev_worm(e.y) && up != s) {
-                if (nk < KINKMAX) { kt[nk] = (int32_t)e.x; kf[nk] = (uint8_t)(ev_dir(e.y) | (s << 2) | (up << 3)); nk++; }
-                else { atomicOr(flag, FL_OVERFLOW); return; }
-            }
-            s = up;
-        }
-    }
     // the four bond buffers of this site: (i,+x), (i,+y), (i-x,+x), (i-y,+y)
     const uint32_t* src[4];
     int ns[4], ps[4];
     long long bids[4];
+    uint32_t hv[4];
+#pragma unroll
     for (int d = 0; d < 4; d++) {
-        int a = (d < 2) ? i : nbr(C, i, d);
+        const int a = (d < 2) ? i : nbr(C, i, d);
         int dspa, sla;
         site_split(C, a, dspa, sla);
-        int bd = d & 1;
-        long long row = (long long)((k * 2 + bd) * C.ndsp + dspa);
+        const int bd = d & 1;
+        const long long row = (long long)((k * 2 + bd) * C.ndsp + dspa);
         src[d] = P.bv + C.bv_off + row * C.capb * C.nloc + sla;
         ns[d] = P.bvc[C.bvc_off + row * C.nloc + sla];
         ps[d] = 0;
         bids[d] = 2LL * a + bd;
+        hv[d] = ns[d] > 0 ? src[d][0] : 0u;
     }
-    int pk = 0;
     Stream rs;
     rs.init(C, (uint32_t)P.sweep[bt.x], RNG_R, (uint32_t)((long long)i * C.ntau + k));
     int32_t lo = C.T[k];
     int p = s_lo;
     int out = 0;
-    int32_t off[NWL];
-    uint8_t dirs[NWL];
     for (;;) {
         // next vertex in (tick, bond id) order
         int best = -1;
-        int32_t bt_tick = 0;
-        long long bt_bid = 0;
-        if (pk < nk) { best = 4; bt_tick = kt[pk]; bt_bid = bond_id(C, i, kf[pk] & 3); }
+        int32_t btk = 0;
+        long long bb = 0;
+#pragma unroll
         for (int d = 0; d < 4; d++) {
-            if (ps[d] >= ns[d]) continue;
-            int32_t tk = (int32_t)(src[d][(long long)ps[d] * st] & 0x3FFFFFFFu);
-            if (best < 0 || tk < bt_tick || (tk == bt_tick && bids[d] < bt_bid)) {
-                best = d; bt_tick = tk; bt_bid = bids[d];
+            const int32_t tk = (int32_t)(hv[d] & BV_TICK);
+            if (ps[d] < ns[d] && (best < 0 || tk < btk || (tk == btk && bids[d] < bb))) {
+                best = d; btk = tk; bb = bids[d];
+            }
+        }
+        uint32_t v = 0;
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            if (d == best) {
+                v = hv[d];
+                ps[d]++;
+                if (ps[d] < ns[d]) hv[d] = src[d][(long long)ps[d] * st];
             }
         }
         int32_t hi;
-        int q, above = 0, vdir = 0;
+        int q, above = 0;
         if (best < 0) { hi = C.T[k + 1]; q = s_hi; }
-        else if (best == 4) {
-            hi = bt_tick; q = (kf[pk] >> 2) & 1; above = (kf[pk] >> 3) & 1; vdir = kf[pk] & 3; pk++;
-        } else {
-            uint32_t v = src[best][(long long)ps[best] * st];
-            ps[best]++;
-            hi = bt_tick;
-            q = (int)((best < 2) ? (v >> 30) & 1u : (v >> 31) & 1u);
-            above = q;
-            vdir = best;
+        else {
+            hi = btk;
+            q = (int)((best < 2 ? v >> 30 : v >> 31) & 1u);
+            above = q ^ (int)((v >> 29) & 1u);
         }
-        int n = sample_worms(sE, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
+        uint64_t dirs;
+        const int n = sample_worms(sE, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
         if (n < 0) return;
         if (out + n + (best >= 0 ? 1 : 0) > C.cap) { atomicOr(flag, FL_OVERFLOW); return; }
         int s = p;
         for (int w = 0; w < n; w++) {
             s ^= 1;
-            E[(long long)out * st] = make_uint2((uint32_t)(lo + off[w]), 1u | ((uint32_t)dirs[w] << 1) | ((uint32_t)s << 3));
+            E[(long long)out * st] = make_uint2((uint32_t)(lo + off[w * 64]),
+                                                1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3));
             out++;
         }
         if (best < 0) break;
-        E[(long long)out * st] = make_uint2((uint32_t)hi, ((uint32_t)vdir << 1) | ((uint32_t)above << 3));
+        E[(long long)out * st] = make_uint2((uint32_t)hi, ((uint32_t)best << 1) | ((uint32_t)above << 3));
         out++;
         lo = hi;
         p = above;
@@ -718,32 +763,28 @@ struct SiteArr {
     int st, n, cap;
     PMWA_DEV uint2 get(int j) const { return e[(long long)j * st]; }
     PMWA_DEV void put(int j, uint2 v) { e[(long long)j * st] = v; }
-    // replace events [lo, hi) by nw[0..m)
-    PMWA_DEV bool replace(int lo, int hi, const uint2* nw, int m)
+    // resize the range [lo, hi) to m entries (contents of the new range
+    // undefined), moving the events above it
+    PMWA_DEV bool resize(int lo, int hi, int m)
     {
         const int delta = m - (hi - lo);
         if (n + delta > cap) return false;
         if (delta > 0) for (int j = n - 1; j >= hi; j--) put(j + delta, get(j));
         else if (delta < 0) for (int j = hi; j < n; j++) put(j + delta, get(j));
-        for (int j = 0; j < m; j++) put(lo + j, nw[j]);
         n += delta;
         return true;
     }
 };
 
-// worms of one interval as events (slot base + offset), occupation starting at p
-PMWA_DEV int gen_worms(const double* __restrict__ E, double lambda, Stream& rs, int32_t base,
-                       long long ell, int sigma, int p, uint2* out, unsigned int* flag)
+// writes the n worms of an interval (slot base + off[64 w], direction bit w
+// of dirs) as events from position j0, occupation starting at p
+PMWA_DEV void put_worms(SiteArr& A, int j0, int32_t base, const int32_t* off, uint64_t dirs, int n, int p)
 {
-    int32_t off[NWL];
-    uint8_t dirs[NWL];
-    const int n = sample_worms(E, lambda, rs, ell, sigma, off, dirs, flag);
     int s = p;
     for (int w = 0; w < n; w++) {
         s ^= 1;
-        out[w] = make_uint2((uint32_t)(base + off[w]), 1u | ((uint32_t)dirs[w] << 1) | ((uint32_t)s << 3));
+        A.put(j0 + w, make_uint2((uint32_t)(base + off[w * 64]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3)));
     }
-    return n;
 }
 
 // Step 1, Eq. (Para): one lane per site, temporal boundaries k = 0.. in order;
@@ -755,6 +796,7 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
     __shared__ double sE[1024];
+    __shared__ int32_t s_off[2 * NWL * 64];
     for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
     __syncthreads();
     if (u >= C.N || !live(P, C, bt.x)) return;
@@ -764,7 +806,8 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
     const int site = site_join(C, dsp, sl);
     const int nt = C.ntau;
     const uint32_t sweep = (uint32_t)P.sweep[bt.x];
-    uint2 b1[NWL], b2[NWL];
+    int32_t* o1 = s_off + threadIdx.x;
+    int32_t* o2 = s_off + NWL * 64 + threadIdx.x;
     for (int k = 0; k < nt; k++) {
         Stream rs;
         rs.init(C, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
@@ -778,9 +821,11 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
                 // the circle is one interval through the boundary
                 const double W[2] = {1.0, 1.0};
                 const int sp = choose(W, u53(rs.next()));
-                const int m = gen_worms(sE, lambda, rs, 0, C.M, 0, sp, b1, flag);
+                uint64_t d1;
+                const int m = sample_worms(sE, lambda, rs, C.M, 0, o1, d1, flag);
                 if (m < 0) return;
-                if (!Ak.replace(0, Ak.n, b1, m)) { atomicOr(flag, FL_OVERFLOW); return; }
+                if (!Ak.resize(0, Ak.n, m)) { atomicOr(flag, FL_OVERFLOW); return; }
+                put_worms(Ak, 0, 0, o1, d1, m, sp);
                 P.cnt[cuk] = Ak.n;
                 *sk = (uint8_t)sp;
                 continue;
@@ -808,16 +853,22 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
         double W[2];
         for (int sp = 0; sp < 2; sp++) W[sp] = fleg(sE, sp ^ q, l1) * fleg(sE, p ^ sp, l2);
         const int sp = choose(W, u53(rs.next()));
-        const int m1 = gen_worms(sE, lambda, rs, C.T[k], l1, sp ^ q, sp, b1, flag);
+        uint64_t d1, d2;
+        const int m1 = sample_worms(sE, lambda, rs, l1, sp ^ q, o1, d1, flag);
         if (m1 < 0) return;
-        const int m2 = gen_worms(sE, lambda, rs, t2, l2, p ^ sp, p, b2, flag);
+        const int m2 = sample_worms(sE, lambda, rs, l2, p ^ sp, o2, d2, flag);
         if (m2 < 0) return;
         if (nt == 1) {
             // same array: suffix first, then prefix
-            if (!Ak.replace(jl + 1, Ak.n, b2, m2) || !Ak.replace(0, jv, b1, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
+            if (!Ak.resize(jl + 1, Ak.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
+            put_worms(Ak, jl + 1, t2, o2, d2, m2, p);
+            if (!Ak.resize(0, jv, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
+            put_worms(Ak, 0, C.T[k], o1, d1, m1, sp);
             P.cnt[cuk] = Ak.n;
         } else {
-            if (!Ak.replace(0, jv, b1, m1) || !Bk.replace(jl + 1, Bk.n, b2, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
+            if (!Ak.resize(0, jv, m1) || !Bk.resize(jl + 1, Bk.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
+            put_worms(Ak, 0, C.T[k], o1, d1, m1, sp);
+            put_worms(Bk, jl + 1, t2, o2, d2, m2, p);
             P.cnt[cuk] = Ak.n;
             P.cnt[cukp] = Bk.n;
         }
@@ -898,23 +949,24 @@ PMWA_DEV bool wave_replace(uint2* A, int& n, int cap, int lo, int hi, const uint
     return true;
 }
 
-// worms of one interval written to LDS (all lanes write the same values)
+// worms of one interval written to LDS out[0..n).  Every lane draws the
+// same words (a wave stream) into its own column `off`; lane w writes worm w.
 PMWA_DEV int gen_worms_lds(const double* __restrict__ E, double lambda, WaveStream& rs, int32_t base,
-                           long long ell, int sigma, int p, uint2* out, unsigned int* flag)
+                           long long ell, int sigma, int p, int32_t* off, uint2* out, unsigned int* flag)
 {
-    int32_t off[NWL];
-    uint8_t dirs[NWL];
+    uint64_t dirs;
     const int n = sample_worms(E, lambda, rs, ell, sigma, off, dirs, flag);
-    int s = p;
-    for (int w = 0; w < n; w++) {
-        s ^= 1;
-        if (threadIdx.x == 0)
-            out[w] = make_uint2((uint32_t)(base + off[w]), 1u | ((uint32_t)dirs[w] << 1) | ((uint32_t)s << 3));
+    const int w = (int)threadIdx.x;
+    if (w < n) {
+        const uint32_t s = (uint32_t)((p + w + 1) & 1);
+        out[w] = make_uint2((uint32_t)(base + off[w * 64]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (s << 3));
     }
+    __builtin_amdgcn_wave_barrier();
     return n;
 }
 
-// dynamic LDS: A[cap] B[cap] W[4][NWL]
+// dynamic LDS: F table (1024 doubles), A[cap] B[cap] W[4][NWL], then one
+// NWL-entry column of worm offsets per lane
 __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict__ blk, int d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -937,6 +989,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     uint2* A = reinterpret_cast<uint2*>(smem + 1024 * sizeof(double));
     uint2* B = A + cap;
     uint2* Wk = B + cap;       // 4 legs x NWL new worms
+    int32_t* off = reinterpret_cast<int32_t*>(Wk + 4 * NWL) + lane;
     for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
     const double lambda = C.lambda;
     double vwa[6];
@@ -984,30 +1037,35 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
             const long long l0 = (long long)t - lo_a, l1 = (long long)t - lo_c;
             const long long l2 = (long long)hi_a - t, l3 = (long long)hi_c - t;
             // f_0 = cosh, f_1 = sinh of eta*Delta*l for the four legs
-            double f[4][2];
+            double f0[4], f1[4];
             {
                 const long long ls[4] = {l0, l1, l2, l3};
+#pragma unroll
                 for (int g = 0; g < 4; g++) {
                     const double m = em1(sE, ls[g]);
                     const double dd = 2.0 * (1.0 + m);
-                    f[g][0] = 1.0 + (m * m) / dd;
-                    f[g][1] = (m * (2.0 + m)) / dd;
+                    f0[g] = 1.0 + (m * m) / dd;
+                    f1[g] = (m * (2.0 + m)) / dd;
                 }
             }
             double W[6];
-            const int ALLOWED[6] = {0, 5, 6, 9, 10, 15};
+#pragma unroll
             for (int m = 0; m < 6; m++) {
-                const int S = ALLOWED[m];
+                const int S = m == 0 ? 0 : m == 1 ? 5 : m == 2 ? 6 : m == 3 ? 9 : m == 4 ? 10 : 15;
                 const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-                W[m] = (((f[0][p1 ^ s1] * f[1][p2 ^ s2]) * f[2][s1p ^ q1]) * f[3][s2p ^ q2]) * vwa[m];
+                const double g0 = (p1 ^ s1) ? f1[0] : f0[0];
+                const double g1 = (p2 ^ s2) ? f1[1] : f0[1];
+                const double g2 = (s1p ^ q1) ? f1[2] : f0[2];
+                const double g3 = (s2p ^ q2) ? f1[3] : f0[3];
+                W[m] = (((g0 * g1) * g2) * g3) * vwa[m];
             }
             const int m = choose(W, u53(rs.next()));
-            const int S = ALLOWED[m];
+            const int S = m == 0 ? 0 : m == 1 ? 5 : m == 2 ? 6 : m == 3 ? 9 : m == 4 ? 10 : 15;
             const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-            const int n0 = gen_worms_lds(sE, lambda, rs, lo_a, l0, p1 ^ s1, p1, Wk, flag);
-            const int n1 = n0 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, lo_c, l1, p2 ^ s2, p2, Wk + NWL, flag);
-            const int n2 = n1 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l2, s1p ^ q1, s1p, Wk + 2 * NWL, flag);
-            const int n3 = n2 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l3, s2p ^ q2, s2p, Wk + 3 * NWL, flag);
+            const int n0 = gen_worms_lds(sE, lambda, rs, lo_a, l0, p1 ^ s1, p1, off, Wk, flag);
+            const int n1 = n0 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, lo_c, l1, p2 ^ s2, p2, off, Wk + NWL, flag);
+            const int n2 = n1 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l2, s1p ^ q1, s1p, off, Wk + 2 * NWL, flag);
+            const int n3 = n2 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l3, s2p ^ q2, s2p, off, Wk + 3 * NWL, flag);
             if (n3 < 0) { fail = true; break; }
             __syncthreads();
             if (lane == 0) {
