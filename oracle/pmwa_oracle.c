@@ -1010,7 +1010,7 @@ static void spatial_phase(orc_chain* c, int d)
         int cc = nb(c, a, d);
         int64_t b = 2 * (int64_t)a + d;
         rstream s;
-        rs_init(&s, c, RNG_BS, (uint32_t)b);
+        int kcur = -1;
         int32_t tcur = -1;
         for (;;) {
             /* next vertex of this bond in tick order */
@@ -1021,6 +1021,9 @@ static void spatial_phase(orc_chain* c, int d)
             if (t < 0) break;
             tcur = t;
             int k = slab_of(c, t);
+            /* legs end at the temporal boundaries, so the slabs of a bond are
+               independent updates; each draws from its own (bond, slab) stream */
+            if (k != kcur) { rs_init(&s, c, RNG_BS, (uint32_t)(b * c->ntau + k)); kcur = k; }
             int va = find_vertex(c, a, t, d), vc = find_vertex(c, cc, t, d + 2);
             if (va < 0 || vc < 0) { c->flags |= FLAG_STATE; return; }
             int32_t lo_a, lo_c, hi_a, hi_c;

@@ -21,7 +21,7 @@
 #include "pmwa_device.h"
 
 namespace pmwa {
-__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs);
+__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
 __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
@@ -78,6 +78,7 @@ struct pmwa_handle {
     size_t lds_bytes = 0;
     size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
     int vs = 1;              // candidate column length of the vertex kernel
+    int v_rows = 1;          // flips per site staged in LDS by the vertex kernel
     size_t v_lds = 0;
     int64_t ev_total = 0, site_slabs = 0;
     bool slots = false;
@@ -271,8 +272,9 @@ static int build_chain(const pmwa_params& p, uint32_t cap_override, HostChain& h
     hc.n_dom = (int64_t)d.ntau * d.ndsp;
     d.n_dom = (uint32_t)hc.n_dom;
     hc.n_bt = d.N;
-    hc.n_bsx = p.dom_x > 1 ? (int64_t)p.Ly * p.dom_x : 0;
-    hc.n_bsy = p.dom_y > 1 ? (int64_t)p.Lx * p.dom_y : 0;
+    // spatial boundary units: (cross bond, slab)
+    hc.n_bsx = p.dom_x > 1 ? (int64_t)p.Ly * p.dom_x * p.dom_tau : 0;
+    hc.n_bsy = p.dom_y > 1 ? (int64_t)p.Lx * p.dom_y * p.dom_tau : 0;
     return PMWA_OK;
 }
 
@@ -330,7 +332,7 @@ static int launch_kernel(pmwa_t* h, int phase)
     hipStream_t s = h->stream;
     switch (phase) {
     case 1:
-        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), h->v_lds, s, h->P, h->d_blk_v, h->vs);
+        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows);
         break;
     case 2:
         if (h->nblk_r) hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(64), 0, s, h->P, h->d_blk_r);
@@ -574,7 +576,11 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         int vs = 1;
         for (auto& hc : h->ch) vs = std::max(vs, hc.d.cdf_stride);
         h->vs = vs;
-        h->v_lds = (size_t)vs * (2 * sizeof(double) + 64 * sizeof(int32_t));
+        // occupation-changing objects (kinks and worms) of a site in a slab
+        // staged in LDS; a lane with more reads its lists from HBM
+        const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + 64 * sizeof(int32_t));
+        h->v_rows = std::max(8, std::min(std::max(maxcap, 8), 64));
+        h->v_lds = v_fixed + (size_t)h->v_rows * 128 * sizeof(uint32_t);
         if (h->v_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_vertex, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->v_lds);

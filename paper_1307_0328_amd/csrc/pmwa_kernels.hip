@@ -24,101 +24,259 @@ PMWA_DEV bool key_before(const ChainDev& C, int site, uint2 e, int32_t tick, lon
     return bond_id(C, site, (int)ev_dir(e.y)) < bid;
 }
 
-struct BondEnds {
-    const uint2* Ea;     // events of site a (the bond's lower end), stride st
-    const uint2* Ec;     // events of site c = a + e_d
-    int na, nc, st, sa0, sc0, a, c, d;
+// Object lists of the two ends of a bond, as seen by the vertex phase.  A
+// record packs tick | worm << 29 | up << 30 | m << 31, with up the occupation
+// just above the object and m = it is a vertex of the bond's direction d.
+// Only objects that change the occupation (kinks and worms) matter for the
+// states seen by candidates, for the n_a n_c integral and for the kinks kept,
+// so FlipList holds just those (in LDS); FullList reads all events from HBM.
+struct FlipList {
+    const uint32_t* r;   // LDS column: tick | worm << 29 | dir << 30
+    int n, s0, d;
+    PMWA_DEV uint32_t get(int j) const
+    {
+        const uint32_t x = r[j * 64];
+        const uint32_t w = (x >> 29) & 1u;
+        const uint32_t up = (uint32_t)(s0 ^ ((j + 1) & 1));
+        const uint32_t m = (!w && (int)(x >> 30) == d) ? 1u : 0u;
+        return (x & (BV_TICK | (1u << 29))) | (up << 30) | (m << 31);
+    }
+    PMWA_DEV int dir(int j) const { return (int)(r[j * 64] >> 30); }
+};
+struct FullList {
+    const uint2* E;
+    int n, st, d;
+    PMWA_DEV uint32_t get(int j) const
+    {
+        const uint2 e = E[(long long)j * st];
+        const uint32_t w = e.y & 1u;
+        const uint32_t m = (!w && (int)((e.y >> 1) & 3u) == d) ? 1u : 0u;
+        return e.x | (w << 29) | (((e.y >> 3) & 1u) << 30) | (m << 31);
+    }
+    PMWA_DEV int dir(int j) const { return (int)ev_dir(E[(long long)j * st].y); }
+};
+
+PMWA_DEV long long pk_pos2(uint32_t pe) { return 2LL * (long long)(pe & BV_TICK) + (long long)((pe >> 29) & 1u); }
+PMWA_DEV int pk_up(uint32_t pe) { return (int)((pe >> 30) & 1u); }
+
+// the object ordered before the candidate (tau, bid) on `site`?  Equal ticks
+// between vertices are decided by bond id.
+template <class Lst>
+PMWA_DEV bool pk_before(const ChainDev& C, int site, uint32_t pe, const Lst& L, int j, int32_t tau, long long bid)
+{
+    const int32_t t = (int32_t)(pe & BV_TICK);
+    if (t != tau) return t < tau;
+    if (pe & (1u << 29)) return false;
+    return bond_id(C, site, L.dir(j)) < bid;
+}
+
+struct BondCtx {
+    int a, c, sa0, sc0, st;
     long long bid;
 };
 
-// One ordered pass over the events of both ends, with the sorted candidate
-// ticks cand[0..np) (a lane column of LDS) taken at their place in the site
-// order.  Kinks of the bond and accepted candidates are written to `out` in
+// One ordered pass over the objects of both ends, with the sorted candidates
+// cand[0..np) (a lane column of LDS: tick | rank << 29, the rank being the
+// number of acceptance thresholds at or below the candidate's word) taken at
+// their place in the site order.  Kinks of the bond and accepted candidates are written to `out` in
 // tick order.  With INTEG, also integrates n_a n_c in half ticks over
 // [2 T_k, 2 T_k+1).  A candidate on the tick of a kink of the bond stops the
 // candidates (returns -1; the integral is still completed); otherwise
 // returns the number of entries.
-template <bool INTEG>
-PMWA_DEV int bond_walk(const ChainDev& C, const BondEnds& B, int32_t Tk, int32_t Tk1,
-                       const int32_t* cand, int np, Stream& rs, uint32_t* out, int capb,
-                       long long& nn)
+template <bool INTEG, class Lst>
+PMWA_DEV int bond_walk(const ChainDev& C, const BondCtx& B, const Lst& LA, const Lst& LC,
+                       int32_t Tk, int32_t Tk1, const int32_t* cand, int np, uint32_t acc_cnt,
+                       uint32_t* out, int capb, long long& nn)
 {
-    const double acc0 = C.acc[0], acc1 = C.acc[1], acc2 = C.acc[2], acc3 = C.acc[3];
     int ia = 0, ic = 0, s_a = B.sa0, s_c = B.sc0, i = 0, nout = 0;
     bool clash = false;
     long long last = 2LL * Tk;
-    uint2 ea = B.na > 0 ? B.Ea[0] : make_uint2(0, 0);
-    uint2 ec = B.nc > 0 ? B.Ec[0] : make_uint2(0, 0);
-    int32_t tau = np > 0 ? cand[0] : 0;
+    uint32_t ea = LA.n > 0 ? LA.get(0) : 0u;
+    uint32_t ec = LC.n > 0 ? LC.get(0) : 0u;
+    const uint32_t cw0 = np > 0 ? (uint32_t)cand[0] : 0u;
+    int32_t tau = (int32_t)(cw0 & BV_TICK);
+    uint32_t rank = cw0 >> 29;
     for (;;) {
-        const bool ha = ia < B.na, hc = ic < B.nc;
+        const bool ha = ia < LA.n, hc = ic < LC.n;
         const bool pend = i < np;
-        const bool ka = pend && ha && key_before(C, B.a, ea, tau, B.bid);
-        const bool kc = pend && hc && key_before(C, B.c, ec, tau, B.bid);
+        const bool ka = pend && ha && pk_before(C, B.a, ea, LA, ia, tau, B.bid);
+        const bool kc = pend && hc && pk_before(C, B.c, ec, LC, ic, tau, B.bid);
         if (pend && !ka && !kc) {
             // every object ordered before the candidate has been passed
-            if (ha && (int32_t)ea.x == tau && !ev_worm(ea.y) && (int)ev_dir(ea.y) == B.d &&
-                (int)ev_up(ea.y) != s_a) {
+            if (ha && (int32_t)(ea & BV_TICK) == tau && (ea >> 31) && pk_up(ea) != s_a) {
                 clash = true;
                 np = i;
                 if (!INTEG) break;
                 continue;
             }
-            const double uu = u53(rs.next());
+            // accepted iff its word is below the threshold of the state
             const int sidx = s_a | (s_c << 1);
-            const double accv = sidx == 0 ? acc0 : sidx == 1 ? acc1 : sidx == 2 ? acc2 : acc3;
-            if (uu < accv) {
+            const uint32_t need = (acc_cnt >> (3 * sidx)) & 7u;
+            if (rank < need) {
                 if (nout < capb) out[(long long)nout * B.st] = (uint32_t)tau | ((uint32_t)s_a << 30) | ((uint32_t)s_c << 31);
                 nout++;
             }
             i++;
-            if (i < np) tau = cand[i * 64];
+            if (i < np) { const uint32_t cw = (uint32_t)cand[i * 64]; tau = (int32_t)(cw & BV_TICK); rank = cw >> 29; }
             continue;
         }
         if (!ha && !hc) break;
-        if (!INTEG && !pend) {
-            // only kinks of the bond are left to copy
-            if (!ha) break;
-        }
-        const bool takea = pend ? (ka && (!kc || pos2(ea) <= pos2(ec)))
-                                : (!hc || (ha && pos2(ea) <= pos2(ec)));
+        if (!INTEG && !pend && !ha) break;   // only kinks of the bond are left to copy
+        const bool takea = pend ? (ka && (!kc || pk_pos2(ea) <= pk_pos2(ec)))
+                                : (!hc || (ha && pk_pos2(ea) <= pk_pos2(ec)));
         if (INTEG) {
-            const long long p = pos2(takea ? ea : ec);
+            const long long p = pk_pos2(takea ? ea : ec);
             nn += (long long)(s_a & s_c) * (p - last);
             last = p;
         }
         if (takea) {
-            const int up = (int)ev_up(ea.y);
-            if (!clash && !ev_worm(ea.y) && (int)ev_dir(ea.y) == B.d && up != s_a) {
+            const int up = pk_up(ea);
+            if (!clash && (ea >> 31) && up != s_a) {
                 if (nout < capb)
-                    out[(long long)nout * B.st] = ea.x | BV_KINK | ((uint32_t)s_a << 30) | ((uint32_t)(s_a ^ 1) << 31);
+                    out[(long long)nout * B.st] = (ea & BV_TICK) | BV_KINK | ((uint32_t)s_a << 30) | ((uint32_t)(s_a ^ 1) << 31);
                 nout++;
             }
             s_a = up;
             ia++;
-            if (ia < B.na) ea = B.Ea[(long long)ia * B.st];
+            if (ia < LA.n) ea = LA.get(ia);
         } else {
-            s_c = (int)ev_up(ec.y);
+            s_c = pk_up(ec);
             ic++;
-            if (ic < B.nc) ec = B.Ec[(long long)ic * B.st];
+            if (ic < LC.n) ec = LC.get(ic);
         }
     }
     if (INTEG) nn += (long long)(s_a & s_c) * (2LL * Tk1 - last);
     return clash ? -1 : nout;
 }
 
+// Acceptance with probability w_d(state)/rho_max by the word w: u53(w) <
+// acc[s] is the same as (w >> 11) < ceil(acc[s] * 2^53) (exact integers), so
+// a word is summarised by its rank r = number of the four thresholds at or
+// below w >> 11, and the candidate is accepted in state s iff r < cnt[s],
+// cnt[s] = number of thresholds at or below the threshold of s.
+struct AccRank {
+    uint64_t thr[4];
+    uint32_t cnt;        // cnt[s] in bits 3s..3s+2
+    PMWA_DEV void init(const ChainDev& C)
+    {
+#pragma unroll
+        for (int q = 0; q < 4; q++) thr[q] = (uint64_t)ceil(C.acc[q] * 0x1.0p53);
+        cnt = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int r = 0; r < 4; r++) c += thr[r] <= thr[q] ? 1u : 0u;
+            cnt |= c << (3 * q);
+        }
+    }
+    PMWA_DEV uint32_t rank(uint64_t w) const
+    {
+        const uint64_t m = w >> 11;
+        return (thr[0] <= m ? 1u : 0u) + (thr[1] <= m ? 1u : 0u) + (thr[2] <= m ? 1u : 0u) + (thr[3] <= m ? 1u : 0u);
+    }
+};
+
+// the acceptance words of the sorted candidates follow the tick words
+PMWA_DEV void tag_ranks(int32_t* cand, int n, Stream& rs, const AccRank& AR)
+{
+    for (int i = 0; i < n; i++) cand[i * 64] = (int32_t)((uint32_t)cand[i * 64] | (AR.rank(rs.next()) << 29));
+}
+
+// kinks of the bond, exact sequential candidate draws (a tick on a kink of
+// the bond or on an earlier candidate is drawn again), then the pass
+template <class Lst>
+PMWA_DEV int vertex_exact(const ChainDev& C, const BondCtx& B, const Lst& LA, const Lst& LC,
+                          int32_t Tk, int32_t Tk1, int32_t* cand, int n, uint32_t sweep, uint32_t unit,
+                          const AccRank& AR, uint32_t* out, int capb, unsigned int* flag)
+{
+    // the kinks are listed in the bond buffer first (it is rewritten below)
+    int nk = 0;
+    {
+        int s = B.sa0;
+        for (int j = 0; j < LA.n; j++) {
+            const uint32_t pe = LA.get(j);
+            const int up = pk_up(pe);
+            if ((pe >> 31) && up != s) {
+                if (nk < capb) out[(long long)nk * B.st] = pe & BV_TICK;
+                nk++;
+            }
+            s = up;
+        }
+    }
+    if (nk > capb) { atomicOr(flag, FL_OVERFLOW); nk = capb; }
+    Stream rs;
+    rs.init(C, sweep, RNG_V, unit);
+    (void)rs.next();
+    const uint64_t dT = (uint64_t)(Tk1 - Tk);
+    for (int i = 0; i < n; i++) {
+        int32_t tau;
+        bool again;
+        int guard = 0;
+        do {
+            tau = Tk + (int32_t)below(rs.next(), dT);
+            again = false;
+            for (int j = 0; j < nk; j++) again |= ((int32_t)out[(long long)j * B.st] == tau);
+            for (int j = 0; j < i; j++) again |= (cand[j * 64] == tau);
+        } while (again && ++guard < 100000);
+        if (again) { atomicOr(flag, FL_SAMPLER); n = i; break; }
+        cand[i * 64] = tau;
+    }
+    sort_col(cand, n);
+    tag_ranks(cand, n, rs, AR);
+    long long unused = 0;
+    const int nout = bond_walk<false>(C, B, LA, LC, Tk, Tk1, cand, n, AR.cnt, out, capb, unused);
+    if (nout < 0) { atomicOr(flag, FL_STATE); return 0; }
+    return nout;
+}
+
+// occupation-changing objects of a site list -> LDS column (at most `rows`);
+// returns their number (which may exceed rows)
+PMWA_DEV int stage_flips(const uint2* E, int n, int st, int s0, uint32_t* F, int rows)
+{
+    // branch-free body: every event is written at the next free row and
+    // kept only if it changes the occupation, so the loads can be batched
+    int nf = 0, s = s0;
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        uint2 e[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) e[q] = E[(long long)(j + q) * st];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int up = (int)ev_up(e[q].y);
+            F[(nf < rows ? nf : rows - 1) * 64] = e[q].x | ((e[q].y & 1u) << 29) | (((e[q].y >> 1) & 3u) << 30);
+            nf += up != s ? 1 : 0;
+            s = up;
+        }
+    }
+    for (; j < n; j++) {
+        const uint2 e = E[(long long)j * st];
+        const int up = (int)ev_up(e.y);
+        F[(nf < rows ? nf : rows - 1) * 64] = e.x | ((e.y & 1u) << 29) | (((e.y >> 1) & 3u) << 30);
+        nf += up != s ? 1 : 0;
+        s = up;
+    }
+    return nf;
+}
+
 // dynamic LDS: Poisson tables of the first two slabs of the block (2 * vs
-// doubles), then the candidate ticks, one column of vs entries per lane
-__global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__ blk, int vs)
+// doubles), the candidate ticks (one column of vs entries per lane), and the
+// occupation-changing objects of both ends of each lane's bond (two columns
+// of `rows` entries per lane)
+__global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
-    const int u = bt.y + (int)threadIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int u = bt.y + lane;
     double* s_cdf = reinterpret_cast<double*>(smem);
-    int32_t* cand = reinterpret_cast<int32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + threadIdx.x;
+    int32_t* cand = reinterpret_cast<int32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + lane;
+    uint32_t* FA = reinterpret_cast<uint32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + (size_t)vs * 64 + lane;
+    uint32_t* FC = FA + (size_t)rows * 64;
     const int k_first = bt.y / (2 * C.N);
-    for (int i = (int)threadIdx.x; i < 2 * C.cdf_stride; i += 64) {
+    for (int i = lane; i < 2 * C.cdf_stride; i += 64) {
         const int kk = k_first + i / C.cdf_stride;
         s_cdf[i] = kk < C.ntau ? P.cdf[C.cdf_off + (long long)kk * C.cdf_stride + i % C.cdf_stride] : 2.0;
     }
@@ -131,76 +289,55 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
         const int dsp = r % C.ndsp;
         r /= C.ndsp;
         const int d = r & 1, k = r >> 1;
-        BondEnds B;
+        BondCtx B;
         B.a = site_join(C, dsp, sl);
         B.c = nbr(C, B.a, d);
-        B.d = d;
         int dspc, slc;
         site_split(C, B.c, dspc, slc);
         B.bid = 2LL * B.a + d;
-        B.na = P.cnt[C.cnt_off + unit_su(C, k, dsp, sl)];
-        B.nc = P.cnt[C.cnt_off + unit_su(C, k, dspc, slc)];
+        B.st = C.nloc;
+        const int na = P.cnt[C.cnt_off + unit_su(C, k, dsp, sl)];
+        const int nc = P.cnt[C.cnt_off + unit_su(C, k, dspc, slc)];
         B.sa0 = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
         B.sc0 = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
-        B.Ea = P.ev + ev_base(C, k, dsp, sl);
-        B.Ec = P.ev + ev_base(C, k, dspc, slc);
-        B.st = C.nloc;
+        const uint2* Ea = P.ev + ev_base(C, k, dsp, sl);
+        const uint2* Ec = P.ev + ev_base(C, k, dspc, slc);
+        const int nfa = stage_flips(Ea, na, B.st, B.sa0, FA, rows);
+        const int nfc = stage_flips(Ec, nc, B.st, B.sc0, FC, rows);
+        const bool staged = nfa <= rows && nfc <= rows;
+        const FlipList fla{FA, nfa, B.sa0, d}, flc{FC, nfc, B.sc0, -1};
+        const FullList gla{Ea, na, B.st, d}, glc{Ec, nc, B.st, -1};
+
         const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
         const uint32_t sweep = (uint32_t)P.sweep[bt.x];
+        const uint32_t unit = (uint32_t)(B.bid * C.ntau + k);
         const int capb = C.capb;
         uint32_t* out = P.bv + C.bv_off + (long long)((k * 2 + d) * C.ndsp + dsp) * capb * C.nloc + sl;
 
         Stream rs;
-        rs.init(C, sweep, RNG_V, (uint32_t)(B.bid * C.ntau + k));
-        const double* cdf = (k - k_first < 2) ? s_cdf + (k - k_first) * C.cdf_stride
-                                              : P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
+        rs.init(C, sweep, RNG_V, unit);
         const double u0 = u53(rs.next());
         int n = 0;
-        while (!(u0 < cdf[n])) n++;
+        if (k - k_first < 2) {
+            const double* cdf = s_cdf + (k - k_first) * C.cdf_stride;
+            while (!(u0 < cdf[n])) n++;
+        } else {
+            const double* cdf = P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
+            while (!(u0 < cdf[n])) n++;
+        }
         const uint64_t dT = (uint64_t)(Tk1 - Tk);
         // ticks as first drawn; they are the ticks kept unless one repeats
         // a kink of the bond or another candidate
         for (int i = 0; i < n; i++) cand[i * 64] = Tk + (int32_t)below(rs.next(), dT);
         const bool rep = sort_col(cand, n);
-        int nout = bond_walk<true>(C, B, Tk, Tk1, cand, rep ? 0 : n, rs, out, capb, nn);
-        if (rep || nout < 0) {
-            // exact sequential draws: a tick on a kink of the bond or on an
-            // earlier candidate is drawn again.  The kinks are listed in the
-            // bond buffer first (it is rewritten below).
-            int nk = 0;
-            {
-                int s = B.sa0;
-                for (int j = 0; j < B.na; j++) {
-                    const uint2 e = B.Ea[(long long)j * B.st];
-                    const int up = (int)ev_up(e.y);
-                    if (!ev_worm(e.y) && (int)ev_dir(e.y) == d && up != s) {
-                        if (nk < capb) out[(long long)nk * B.st] = e.x;
-                        nk++;
-                    }
-                    s = up;
-                }
-            }
-            if (nk > capb) { atomicOr(flag, FL_OVERFLOW); nk = capb; }
-            rs.init(C, sweep, RNG_V, (uint32_t)(B.bid * C.ntau + k));
-            (void)rs.next();
-            for (int i = 0; i < n; i++) {
-                int32_t tau;
-                bool again;
-                int guard = 0;
-                do {
-                    tau = Tk + (int32_t)below(rs.next(), dT);
-                    again = false;
-                    for (int j = 0; j < nk; j++) again |= ((int32_t)out[(long long)j * B.st] == tau);
-                    for (int j = 0; j < i; j++) again |= (cand[j * 64] == tau);
-                } while (again && ++guard < 100000);
-                if (again) { atomicOr(flag, FL_SAMPLER); n = i; break; }
-                cand[i * 64] = tau;
-            }
-            sort_col(cand, n);
-            long long unused = 0;
-            nout = bond_walk<false>(C, B, Tk, Tk1, cand, n, rs, out, capb, unused);
-            if (nout < 0) { atomicOr(flag, FL_STATE); nout = 0; }
-        }
+        AccRank AR;
+        AR.init(C);
+        if (!rep) tag_ranks(cand, n, rs, AR);
+        int nout = staged ? bond_walk<true>(C, B, fla, flc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn)
+                          : bond_walk<true>(C, B, gla, glc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn);
+        if (rep || nout < 0)
+            nout = staged ? vertex_exact(C, B, fla, flc, Tk, Tk1, cand, n, sweep, unit, AR, out, capb, flag)
+                          : vertex_exact(C, B, gla, glc, Tk, Tk1, cand, n, sweep, unit, AR, out, capb, flag);
         if (nout > capb) { atomicOr(flag, FL_OVERFLOW); nout = capb; }
         P.bvc[C.bvc_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.nloc + sl] = nout;
     }
@@ -876,13 +1013,13 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
     }
 }
 
-// Step 2, Eq. (ParaSpace): one wavefront per bond crossing a spatial domain
-// boundary in direction d (owned by the left/lower domain).  The two site
-// arrays of the bond, slab by slab, sit in LDS; its vertices are visited in
-// tick order; a heat bath over the six allowed root states with the leg
-// weights f picks the new roots, then the worms of the four legs are
-// regenerated.  Searches are wave ballots, edits are wave-parallel shifts;
-// the chain of decisions is the same on every lane.
+// Step 2, Eq. (ParaSpace): one wavefront per (bond crossing a spatial domain
+// boundary in direction d, slab); the bond is owned by the left/lower
+// domain.  The two site arrays of the bond in the slab sit in LDS; its
+// vertices are visited in tick order; a heat bath over the six allowed root
+// states with the leg weights f picks the new roots, then the worms of the
+// four legs are regenerated.  Searches are wave ballots, edits are
+// wave-parallel shifts; the chain of decisions is the same on every lane.
 PMWA_DEV int wave_first(const uint2* A, int from, int n, int mode, uint32_t arg0, int32_t arg1)
 {
     // mode 0: vertex with bond direction arg0;  mode 1: vertex with tick arg1 and direction arg0
@@ -972,7 +1109,8 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
-    const int u = bt.y;
+    const int nt = C.ntau;
+    const int u = bt.y / nt, k = bt.y % nt;   // cross bond, slab
     const int lane = (int)threadIdx.x;
     const int nb_units = d == 0 ? (C.dom_x > 1 ? C.Ly * C.dom_x : 0) : (C.dom_y > 1 ? C.Lx * C.dom_y : 0);
     if (u >= nb_units || !live(P, C, bt.x)) return;
@@ -984,7 +1122,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     int dspa, sla, dspc, slc;
     site_split(C, a, dspa, sla);
     site_split(C, c, dspc, slc);
-    const int nt = C.ntau, cap = C.cap;
+    const int cap = C.cap;
     double* sE = reinterpret_cast<double*>(smem);
     uint2* A = reinterpret_cast<uint2*>(smem + 1024 * sizeof(double));
     uint2* B = A + cap;
@@ -997,9 +1135,11 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
         const int AL[6] = {0, 5, 6, 9, 10, 15};
         for (int m = 0; m < 6; m++) vwa[m] = C.vw[AL[m]];
     }
+    // legs end at the temporal boundaries: the slabs of a bond are
+    // independent updates, each with its own (bond, slab) stream
     WaveStream rs;
-    rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)(2LL * a + d));
-    for (int k = 0; k < nt; k++) {
+    rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)((2LL * a + d) * nt + k));
+    {
         const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
         const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
         const uint2* GA = P.ev + ev_base(C, k, dspa, sla);
