@@ -90,7 +90,7 @@ struct orc_chain {
 #define KMAX 1024
 
 /* Philox counter word 3 carries (chain_id << 8) | stream kind */
-enum { RNG_V = 1, RNG_R = 2, RNG_S = 3, RNG_BT = 4, RNG_BS = 5 };
+enum { RNG_V = 1, RNG_R = 2, RNG_S = 3, RNG_BT = 4, RNG_BS = 5, RNG_BSL = 6 /* .. 9: the four legs */ };
 
 /* ------------------------------------------------------------------ */
 /* random stream of one unit                                           */
@@ -1009,8 +1009,7 @@ static void spatial_phase(orc_chain* c, int d)
         if (!is_cross(c, a, d)) continue;
         int cc = nb(c, a, d);
         int64_t b = 2 * (int64_t)a + d;
-        rstream s;
-        int kcur = -1;
+        int kcur = -1, v = 0;
         int32_t tcur = -1;
         for (;;) {
             /* next vertex of this bond in tick order */
@@ -1022,8 +1021,15 @@ static void spatial_phase(orc_chain* c, int d)
             tcur = t;
             int k = slab_of(c, t);
             /* legs end at the temporal boundaries, so the slabs of a bond are
-               independent updates; each draws from its own (bond, slab) stream */
-            if (k != kcur) { rs_init(&s, c, RNG_BS, (uint32_t)(b * c->ntau + k)); kcur = k; }
+               independent updates.  Streams: unit (bond, slab); vertex v of
+               the bond in the slab (tick order) draws its choice from kind
+               RNG_BS and the worms of leg g from kind RNG_BSL + g, each from
+               word 2^17 v on (word-pair index v << 16) */
+            if (k != kcur) { kcur = k; v = 0; }
+            const uint32_t unit = (uint32_t)(b * c->ntau + k);
+            rstream s;
+            rs_init(&s, c, RNG_BS, unit);
+            s.w = (uint64_t)v << 17;
             int va = find_vertex(c, a, t, d), vc = find_vertex(c, cc, t, d + 2);
             if (va < 0 || vc < 0) { c->flags |= FLAG_STATE; return; }
             int32_t lo_a, lo_c, hi_a, hi_c;
@@ -1051,10 +1057,16 @@ static void spatial_phase(orc_chain* c, int d)
             erase_worms(c, cc, lo_c, t);
             erase_worms(c, a, t, hi_a);
             erase_worms(c, cc, t, hi_c);
-            place_worms(c, &s, a, lo_a, l0, p1 ^ s1, p1);
-            place_worms(c, &s, cc, lo_c, l1, p2 ^ s2, p2);
-            place_worms(c, &s, a, t, l2, s1p ^ q1, s1p);
-            place_worms(c, &s, cc, t, l3, s2p ^ q2, s2p);
+            rstream sl[4];
+            for (int g = 0; g < 4; g++) {
+                rs_init(&sl[g], c, RNG_BSL + g, unit);
+                sl[g].w = (uint64_t)v << 17;
+            }
+            place_worms(c, &sl[0], a, lo_a, l0, p1 ^ s1, p1);
+            place_worms(c, &sl[1], cc, lo_c, l1, p2 ^ s2, p2);
+            place_worms(c, &sl[2], a, t, l2, s1p ^ q1, s1p);
+            place_worms(c, &sl[3], cc, t, l3, s2p ^ q2, s2p);
+            v++;
         }
     }
 }

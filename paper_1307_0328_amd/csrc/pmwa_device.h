@@ -35,7 +35,9 @@ constexpr uint32_t BV_TICK = (1u << 29) - 1u;   // bond-buffer entry: tick bits
 constexpr uint32_t BV_KINK = 1u << 29;          //   kink (occupations flip)
 
 // stream kinds in Philox counter word 3 (low byte)
-enum : uint32_t { RNG_V = 1, RNG_R = 2, RNG_S = 3, RNG_BT = 4, RNG_BS = 5 };
+// (the spatial update draws a vertex's choice from RNG_BS and the worms of
+// its leg g from RNG_BSL + g)
+enum : uint32_t { RNG_V = 1, RNG_R = 2, RNG_S = 3, RNG_BT = 4, RNG_BS = 5, RNG_BSL = 6 };
 // sticky per-chain error flags
 enum : uint32_t { FL_OVERFLOW = 1, FL_SAMPLER = 2, FL_STATE = 4 };
 // node flags of the scattering phase (bits 0-3 equal the event info bits)
@@ -88,6 +90,18 @@ struct Pools {
     uint32_t* s_own;
     int32_t series_cap;
     int32_t lds_nodes;           // node capacity of the LDS path (0 = off)
+};
+
+// per vertex of a cross bond in the spatial boundary update (in LDS)
+struct BsVert {
+    int32_t t, lo_a, lo_c;
+    int32_t l[4];            // leg lengths: lower a, lower c, upper a, upper c
+    uint32_t fl;             // bit0 p1 fixed, bit1 p2 fixed, bit2 q1, bit3 q2,
+                             // bit4 previous vertex on a is the bond's, bit5 on c,
+                             // bit6 next vertex on a is the bond's, bit7 on c
+    uint32_t m4;             // choice index for (p1, p2) = (x & 1, x >> 1) at bits 4x
+    uint32_t S, p12;         // chosen root pattern; actual lower-end occupations
+    int32_t cnt[4];          // worms drawn on each leg (0 for legs redrawn later)
 };
 
 // ---------------------------------------------------------------------------
@@ -199,18 +213,19 @@ PMWA_DEV long long ev_base(const ChainDev& C, int k, int dsp, int sl)
 // element functions of the worm law (hard-core f_qp), from the expm1 table
 // ---------------------------------------------------------------------------
 // F[g*256 + v] = expm1(lambda * v * 2^(8g)) (a copy in LDS); the base-256
-// digits of ell in ascending order, (1+m)(1+t) - 1 = (m + t) + m t
+// digits of ell in ascending order, (1+m)(1+t) - 1 = (m + t) + m t.  A zero
+// digit has t = +0 and leaves m (finite, >= 0) unchanged exactly, so every
+// digit is combined without a branch and the four loads issue together.
 PMWA_DEV double em1(const double* __restrict__ F, long long ell)
 {
-    double m = 0.0;
-#pragma unroll
-    for (int g = 0; g < 4; g++) {
-        const int v = (int)((ell >> (8 * g)) & 255);
-        if (v) {
-            const double t = F[g * 256 + v];
-            m = (m + t) + m * t;
-        }
-    }
+    const double t0 = F[(int)(ell & 255)];
+    const double t1 = F[256 + (int)((ell >> 8) & 255)];
+    const double t2 = F[512 + (int)((ell >> 16) & 255)];
+    const double t3 = F[768 + (int)((ell >> 24) & 255)];
+    double m = t0;
+    m = (m + t1) + m * t1;
+    m = (m + t2) + m * t2;
+    m = (m + t3) + m * t3;
     return m;
 }
 PMWA_DEV double fleg(const double* __restrict__ E, int sigma, long long ell)

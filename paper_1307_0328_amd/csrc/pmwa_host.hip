@@ -568,7 +568,9 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     {
         int maxcap = 0;
         for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
-        h->bs_lds = 1024 * sizeof(double) + (size_t)(2 * maxcap + 4 * NWL) * sizeof(uint2) +
+        // F table; A, B, A2, B2; 10 int arrays; the per-vertex records; one
+        // worm-offset column per lane
+        h->bs_lds = 1024 * sizeof(double) + (size_t)maxcap * (4 * sizeof(uint2) + 10 * sizeof(int) + sizeof(BsVert)) +
                     (size_t)NWL * 64 * sizeof(int32_t);
         if (h->bs_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -1015,95 +1015,150 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
 
 // Step 2, Eq. (ParaSpace): one wavefront per (bond crossing a spatial domain
 // boundary in direction d, slab); the bond is owned by the left/lower
-// domain.  The two site arrays of the bond in the slab sit in LDS; its
-// vertices are visited in tick order; a heat bath over the six allowed root
-// states with the leg weights f picks the new roots, then the worms of the
-// four legs are regenerated.  Searches are wave ballots, edits are
-// wave-parallel shifts; the chain of decisions is the same on every lane.
-PMWA_DEV int wave_first(const uint2* A, int from, int n, int mode, uint32_t arg0, int32_t arg1)
+// domain.  The bond's vertices in the slab are updated in tick order: a heat
+// bath over the six allowed root states with the leg weights f, then the
+// worms of the four legs are regenerated.
+//
+// Leg lengths and the occupations at the upper leg ends are fixed before the
+// update starts (ticks never move; a vertex above is updated later), and the
+// occupation at the lower end of a leg is either fixed or, when the previous
+// vertex on that site is the bond's previous vertex, its new root.  So the
+// wave computes, for every vertex in parallel, the choice for each of the
+// four possible lower-end occupations, then follows the short chain of
+// choices; worms are drawn per (vertex, leg) from their own streams, only
+// for the legs that no later vertex regenerates, and both site arrays are
+// rebuilt by prefix sums.  The result equals the vertices updated one by one.
+
+// index of the previous / next vertex (worms skipped) for every position of
+// a site array, by wave ballots (chunks of 64 with a carry)
+PMWA_DEV void vertex_links(const uint2* A, int n, int* pv, int* nv)
 {
-    // mode 0: vertex with bond direction arg0;  mode 1: vertex with tick arg1 and direction arg0
-    // mode 2: any vertex
     const int lane = (int)threadIdx.x;
-    for (int base = from; base < n; base += 64) {
+    int carry = -1;
+    for (int base = 0; base < n; base += 64) {
         const int j = base + lane;
-        bool hit = false;
+        const bool v = j < n && !ev_worm(A[j].y);
+        const unsigned long long m = __ballot(v);
+        const unsigned long long below_m = m & ((1ULL << lane) - 1ULL);
+        if (j < n) pv[j] = below_m ? base + 63 - __clzll((long long)below_m) : carry;
+        if (m) carry = base + 63 - __clzll((long long)m);
+    }
+    carry = n;
+    for (int top = ((n + 63) / 64) * 64 - 64; top >= 0; top -= 64) {
+        const int j = top + lane;
+        const bool v = j < n && !ev_worm(A[j].y);
+        const unsigned long long m = __ballot(v);
+        const unsigned long long above_m = lane == 63 ? 0ULL : (m & ~((2ULL << lane) - 1ULL));
+        if (j < n) nv[j] = above_m ? top + __ffsll((long long)above_m) - 1 : carry;
+        if (m) carry = top + __ffsll((long long)m) - 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// positions of the vertices of direction `dir` in order: V[ord] = j and
+// ord_of[j] = ord; returns their number
+PMWA_DEV int bond_vertices(const uint2* A, int n, uint32_t dir, int* V, int* ord_of)
+{
+    const int lane = (int)threadIdx.x;
+    int cnt = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + lane;
+        bool bv = false;
         if (j < n) {
             const uint2 e = A[j];
-            const bool v = !ev_worm(e.y);
-            if (mode == 0) hit = v && ev_dir(e.y) == arg0;
-            else if (mode == 1) hit = v && ev_dir(e.y) == arg0 && (int32_t)e.x == arg1;
-            else hit = v;
+            bv = !ev_worm(e.y) && ev_dir(e.y) == dir;
         }
-        const unsigned long long m = __ballot(hit);
-        if (m) return base + __ffsll((long long)m) - 1;
-    }
-    return n;
-}
-
-PMWA_DEV int wave_last_vertex(const uint2* A, int upto)
-{
-    const int lane = (int)threadIdx.x;
-    for (int top = upto; top > 0; top -= 64) {
-        const int j = top - 64 + lane;
-        const bool hit = j >= 0 && !ev_worm(A[j].y);
-        const unsigned long long m = __ballot(hit);
-        if (m) return top - 64 + (63 - __clzll((long long)m));
-    }
-    return -1;
-}
-
-// replace A[lo, hi) by nw[0..m) in LDS, one wavefront
-PMWA_DEV bool wave_replace(uint2* A, int& n, int cap, int lo, int hi, const uint2* nw, int m)
-{
-    const int lane = (int)threadIdx.x;
-    const int delta = m - (hi - lo);
-    if (n + delta > cap) return false;
-    if (delta > 0) {
-        for (int top = n; top > hi; top -= 64) {
-            const int j = top - 64 + lane;
-            uint2 v = make_uint2(0, 0);
-            const bool ok = j >= hi;
-            if (ok) v = A[j];
-            __builtin_amdgcn_wave_barrier();
-            if (ok) A[j + delta] = v;
-            __builtin_amdgcn_wave_barrier();
+        const unsigned long long m = __ballot(bv);
+        if (bv) {
+            const int o = cnt + __popcll(m & ((1ULL << lane) - 1ULL));
+            V[o] = j;
+            ord_of[j] = o;
         }
-    } else if (delta < 0) {
-        for (int base = hi; base < n; base += 64) {
-            const int j = base + lane;
-            uint2 v = make_uint2(0, 0);
-            const bool ok = j < n;
-            if (ok) v = A[j];
-            __builtin_amdgcn_wave_barrier();
-            if (ok) A[j + delta] = v;
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-    for (int j = lane; j < m; j += 64) A[lo + j] = nw[j];
-    __builtin_amdgcn_wave_barrier();
-    n += delta;
-    return true;
-}
-
-// worms of one interval written to LDS out[0..n).  Every lane draws the
-// same words (a wave stream) into its own column `off`; lane w writes worm w.
-PMWA_DEV int gen_worms_lds(const double* __restrict__ E, double lambda, WaveStream& rs, int32_t base,
-                           long long ell, int sigma, int p, int32_t* off, uint2* out, unsigned int* flag)
-{
-    uint64_t dirs;
-    const int n = sample_worms(E, lambda, rs, ell, sigma, off, dirs, flag);
-    const int w = (int)threadIdx.x;
-    if (w < n) {
-        const uint32_t s = (uint32_t)((p + w + 1) & 1);
-        out[w] = make_uint2((uint32_t)(base + off[w * 64]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (s << 3));
+        cnt += __popcll(m);
     }
     __builtin_amdgcn_wave_barrier();
-    return n;
+    return cnt;
 }
 
-// dynamic LDS: F table (1024 doubles), A[cap] B[cap] W[4][NWL], then one
-// NWL-entry column of worm offsets per lane
+// wave-inclusive prefix sum of one int per lane
+PMWA_DEV int wave_incl_sum(int x)
+{
+    const int lane = (int)threadIdx.x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// new array of one site: old vertices (bond vertices with new roots) and the
+// worms of the intervals no bond vertex touches, plus the new worms; the new
+// worms of interval (j, next vertex) start at pos[j] + 1 (or 0 for the
+// interval below the first vertex).  Returns the new length.
+PMWA_DEV int rebuild_positions(const uint2* A, int n, const int* pv, const int* nv, const int* ord_of,
+                               const BsVert* VV, uint32_t dir, int lower_leg, int upper_leg, int* pos)
+{
+    const int lane = (int)threadIdx.x;
+    auto is_bv = [&](int j) { return j >= 0 && j < n && !ev_worm(A[j].y) && ev_dir(A[j].y) == dir; };
+    // worms inserted below the first vertex
+    int first = n;
+    if (n > 0) first = ev_worm(A[0].y) ? nv[0] : 0;
+    int ins0 = 0;
+    if (first < n && is_bv(first)) ins0 = VV[ord_of[first]].cnt[lower_leg];
+    int carry = ins0;
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + lane;
+        int x = 0;
+        if (j < n) {
+            const uint2 e = A[j];
+            if (!ev_worm(e.y)) {
+                x = 1;
+                const int u = nv[j];
+                if (u < n && is_bv(u)) x += VV[ord_of[u]].cnt[lower_leg];
+                else if (ev_dir(e.y) == dir) x += VV[ord_of[j]].cnt[upper_leg];
+            } else {
+                const int lo = pv[j], u = nv[j];
+                const bool touched = is_bv(lo) || is_bv(u);
+                x = touched ? 0 : 1;
+            }
+        }
+        const int incl = wave_incl_sum(x);
+        if (j < n) pos[j] = carry + incl - x;
+        carry += __shfl(incl, 63, 64);
+    }
+    __builtin_amdgcn_wave_barrier();
+    return carry;
+}
+
+// copies the kept objects of A to their positions in A2 (bond vertices get
+// their new occupation above)
+PMWA_DEV void rebuild_copy(const uint2* A, int n, const int* pv, const int* nv, const int* ord_of,
+                           const BsVert* VV, uint32_t dir, int side, const int* pos, uint2* A2)
+{
+    const int lane = (int)threadIdx.x;
+    auto is_bv = [&](int j) { return j >= 0 && j < n && !ev_worm(A[j].y) && ev_dir(A[j].y) == dir; };
+    for (int j = lane; j < n; j += 64) {
+        uint2 e = A[j];
+        if (!ev_worm(e.y)) {
+            if (ev_dir(e.y) == dir) {
+                const uint32_t S = VV[ord_of[j]].S;
+                const uint32_t up = side == 0 ? (S >> 2) & 1u : S >> 3;
+                e.y = (e.y & ~8u) | (up << 3);
+            }
+            A2[pos[j]] = e;
+        } else if (!is_bv(pv[j]) && !is_bv(nv[j])) {
+            A2[pos[j]] = e;
+        }
+    }
+}
+
+// dynamic LDS: the F table (1024 doubles), then (cap = event capacity)
+//   A, B, A2, B2           4 x cap uint2
+//   pvA nvA ordA posA, the same for B      8 x cap int
+//   VA, VB                  2 x cap int
+//   VV                      cap BsVert
+//   one NWL-entry column of worm offsets per lane
 __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict__ blk, int d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1126,68 +1181,95 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     double* sE = reinterpret_cast<double*>(smem);
     uint2* A = reinterpret_cast<uint2*>(smem + 1024 * sizeof(double));
     uint2* B = A + cap;
-    uint2* Wk = B + cap;       // 4 legs x NWL new worms
-    int32_t* off = reinterpret_cast<int32_t*>(Wk + 4 * NWL) + lane;
-    for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
-    const double lambda = C.lambda;
+    uint2* A2 = B + cap;
+    uint2* B2 = A2 + cap;
+    int* pvA = reinterpret_cast<int*>(B2 + cap);
+    int* nvA = pvA + cap;
+    int* ordA = nvA + cap;
+    int* posA = ordA + cap;
+    int* pvB = posA + cap;
+    int* nvB = pvB + cap;
+    int* ordB = nvB + cap;
+    int* posB = ordB + cap;
+    int* VA = posB + cap;
+    int* VB = VA + cap;
+    BsVert* VV = reinterpret_cast<BsVert*>(VB + cap);
+    int32_t* off = reinterpret_cast<int32_t*>(VV + cap) + lane;
+
+    const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
+    const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
+    const int na = P.cnt[cua], nb = P.cnt[cuc];
+    {
+        const uint2* GA = P.ev + ev_base(C, k, dspa, sla);
+        const uint2* GB = P.ev + ev_base(C, k, dspc, slc);
+        for (int j = lane; j < na; j += 64) A[j] = GA[(long long)j * C.nloc];
+        for (int j = lane; j < nb; j += 64) B[j] = GB[(long long)j * C.nloc];
+        for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
+    }
+    __syncthreads();
+    const int nva = bond_vertices(A, na, (uint32_t)d, VA, ordA);
+    const int nvb = bond_vertices(B, nb, (uint32_t)(d + 2), VB, ordB);
+    if (nva != nvb) { if (lane == 0) atomicOr(flag, FL_STATE); return; }
+    const int nbv = nva;
+    if (nbv == 0) return;
+    vertex_links(A, na, pvA, nvA);
+    vertex_links(B, nb, pvB, nvB);
+    __syncthreads();
+
+    const int bsa = P.bs[C.bs_off + unit_su(C, k, dspa, sla)];
+    const int bsc = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
+    const int bsa1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspa, sla)];
+    const int bsc1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspc, slc)];
+    const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
+    const uint32_t sweep = (uint32_t)P.sweep[bt.x];
+    const uint32_t unit = (uint32_t)((2LL * a + d) * nt + k);
     double vwa[6];
     {
         const int AL[6] = {0, 5, 6, 9, 10, 15};
+#pragma unroll
         for (int m = 0; m < 6; m++) vwa[m] = C.vw[AL[m]];
     }
-    // legs end at the temporal boundaries: the slabs of a bond are
-    // independent updates, each with its own (bond, slab) stream
-    WaveStream rs;
-    rs.init(C, (uint32_t)P.sweep[bt.x], RNG_BS, (uint32_t)((2LL * a + d) * nt + k));
-    {
-        const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
-        const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
-        const uint2* GA = P.ev + ev_base(C, k, dspa, sla);
-        const uint2* GB = P.ev + ev_base(C, k, dspc, slc);
-        int na = P.cnt[cua], nb = P.cnt[cuc];
-        for (int j = lane; j < na; j += 64) A[j] = GA[(long long)j * C.nloc];
-        for (int j = lane; j < nb; j += 64) B[j] = GB[(long long)j * C.nloc];
-        __syncthreads();
-        const int bsa = P.bs[C.bs_off + unit_su(C, k, dspa, sla)];
-        const int bsc = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
-        const int bsa1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspa, sla)];
-        const int bsc1 = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dspc, slc)];
-        bool dirty = false, fail = false;
-        int ja = 0;
-        for (;;) {
-            ja = wave_first(A, ja, na, 0, (uint32_t)d, 0);
-            if (ja >= na) break;
-            dirty = true;
-            const int32_t t = (int32_t)A[ja].x;
-            const int jc = wave_first(B, 0, nb, 1, (uint32_t)(d + 2), t);
-            if (jc >= nb) { if (lane == 0) atomicOr(flag, FL_STATE); fail = true; break; }
-            // legs, worms ignored
-            const int la = wave_last_vertex(A, ja);
-            const int lc = wave_last_vertex(B, jc);
-            const int ha = wave_first(A, ja + 1, na, 2, 0, 0);
-            const int hc = wave_first(B, jc + 1, nb, 2, 0, 0);
-            const int32_t lo_a = la >= 0 ? (int32_t)A[la].x : C.T[k];
-            const int p1 = la >= 0 ? (int)ev_up(A[la].y) : bsa;
-            const int32_t lo_c = lc >= 0 ? (int32_t)B[lc].x : C.T[k];
-            const int p2 = lc >= 0 ? (int)ev_up(B[lc].y) : bsc;
-            const int32_t hi_a = ha < na ? (int32_t)A[ha].x : C.T[k + 1];
-            const int q1 = ha < na ? (int)ev_up(A[ha - 1].y) : bsa1;
-            const int32_t hi_c = hc < nb ? (int32_t)B[hc].x : C.T[k + 1];
-            const int q2 = hc < nb ? (int)ev_up(B[hc - 1].y) : bsc1;
-            const long long l0 = (long long)t - lo_a, l1 = (long long)t - lo_c;
-            const long long l2 = (long long)hi_a - t, l3 = (long long)hi_c - t;
-            // f_0 = cosh, f_1 = sinh of eta*Delta*l for the four legs
-            double f0[4], f1[4];
-            {
-                const long long ls[4] = {l0, l1, l2, l3};
+
+    // ---- every vertex: legs, fixed occupations, the choice per (p1, p2)
+    bool bad = false;
+    for (int v = lane; v < nbv; v += 64) {
+        const int ja = VA[v], jc = VB[v];
+        const int32_t t = (int32_t)A[ja].x;
+        bad |= (int32_t)B[jc].x != t;
+        const int la = pvA[ja], ha = nvA[ja], lc = pvB[jc], hc = nvB[jc];
+        BsVert Vv;
+        Vv.t = t;
+        Vv.lo_a = la >= 0 ? (int32_t)A[la].x : Tk;
+        Vv.lo_c = lc >= 0 ? (int32_t)B[lc].x : Tk;
+        const int32_t hi_a = ha < na ? (int32_t)A[ha].x : Tk1;
+        const int32_t hi_c = hc < nb ? (int32_t)B[hc].x : Tk1;
+        Vv.l[0] = t - Vv.lo_a; Vv.l[1] = t - Vv.lo_c; Vv.l[2] = hi_a - t; Vv.l[3] = hi_c - t;
+        const int p1f = la >= 0 ? (int)ev_up(A[la].y) : bsa;
+        const int p2f = lc >= 0 ? (int)ev_up(B[lc].y) : bsc;
+        const int q1 = ha < na ? (int)ev_up(A[ha - 1].y) : bsa1;
+        const int q2 = hc < nb ? (int)ev_up(B[hc - 1].y) : bsc1;
+        const bool prev_a = la >= 0 && !ev_worm(A[la].y) && ev_dir(A[la].y) == (uint32_t)d;
+        const bool prev_c = lc >= 0 && !ev_worm(B[lc].y) && ev_dir(B[lc].y) == (uint32_t)(d + 2);
+        const bool next_a = ha < na && ev_dir(A[ha].y) == (uint32_t)d;
+        const bool next_c = hc < nb && ev_dir(B[hc].y) == (uint32_t)(d + 2);
+        Vv.fl = (uint32_t)p1f | ((uint32_t)p2f << 1) | ((uint32_t)q1 << 2) | ((uint32_t)q2 << 3) |
+                ((uint32_t)prev_a << 4) | ((uint32_t)prev_c << 5) | ((uint32_t)next_a << 6) | ((uint32_t)next_c << 7);
+        double f0[4], f1[4];
 #pragma unroll
-                for (int g = 0; g < 4; g++) {
-                    const double m = em1(sE, ls[g]);
-                    const double dd = 2.0 * (1.0 + m);
-                    f0[g] = 1.0 + (m * m) / dd;
-                    f1[g] = (m * (2.0 + m)) / dd;
-                }
-            }
+        for (int g = 0; g < 4; g++) {
+            const double m = em1(sE, (long long)Vv.l[g]);
+            const double dd = 2.0 * (1.0 + m);
+            f0[g] = 1.0 + (m * m) / dd;
+            f1[g] = (m * (2.0 + m)) / dd;
+        }
+        Stream rs;
+        rs.init(C, sweep, RNG_BS, unit);
+        rs.w = (uint32_t)v << 17;
+        const double uu = u53(rs.next());
+        uint32_t m4 = 0;
+#pragma unroll
+        for (int x = 0; x < 4; x++) {
+            const int p1 = x & 1, p2 = x >> 1;
             double W[6];
 #pragma unroll
             for (int m = 0; m < 6; m++) {
@@ -1199,40 +1281,101 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
                 const double g3 = (s2p ^ q2) ? f1[3] : f0[3];
                 W[m] = (((g0 * g1) * g2) * g3) * vwa[m];
             }
-            const int m = choose(W, u53(rs.next()));
+            m4 |= (uint32_t)choose(W, uu) << (4 * x);
+        }
+        Vv.m4 = m4;
+        VV[v] = Vv;
+    }
+    if (__ballot(bad)) { if (lane == 0) atomicOr(flag, FL_STATE); return; }
+    __syncthreads();
+
+    // ---- the chain of choices (uniform on every lane)
+    {
+        int s1p_prev = 0, s2p_prev = 0;
+        for (int v = 0; v < nbv; v++) {
+            const uint32_t fl = VV[v].fl, m4 = VV[v].m4;
+            const int p1 = (fl & 16u) ? s1p_prev : (int)(fl & 1u);
+            const int p2 = (fl & 32u) ? s2p_prev : (int)((fl >> 1) & 1u);
+            const int m = (int)((m4 >> (4 * (p1 | (p2 << 1)))) & 15u);
             const int S = m == 0 ? 0 : m == 1 ? 5 : m == 2 ? 6 : m == 3 ? 9 : m == 4 ? 10 : 15;
-            const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
-            const int n0 = gen_worms_lds(sE, lambda, rs, lo_a, l0, p1 ^ s1, p1, off, Wk, flag);
-            const int n1 = n0 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, lo_c, l1, p2 ^ s2, p2, off, Wk + NWL, flag);
-            const int n2 = n1 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l2, s1p ^ q1, s1p, off, Wk + 2 * NWL, flag);
-            const int n3 = n2 < 0 ? -1 : gen_worms_lds(sE, lambda, rs, t, l3, s2p ^ q2, s2p, off, Wk + 3 * NWL, flag);
-            if (n3 < 0) { fail = true; break; }
-            __syncthreads();
-            if (lane == 0) {
-                A[ja].y = (A[ja].y & ~8u) | ((uint32_t)s1p << 3);
-                B[jc].y = (B[jc].y & ~8u) | ((uint32_t)s2p << 3);
-            }
-            __syncthreads();
-            if (!wave_replace(A, na, cap, ja + 1, ha, Wk + 2 * NWL, n2) ||
-                !wave_replace(A, na, cap, la + 1, ja, Wk, n0) ||
-                !wave_replace(B, nb, cap, jc + 1, hc, Wk + 3 * NWL, n3) ||
-                !wave_replace(B, nb, cap, lc + 1, jc, Wk + NWL, n1)) {
-                if (lane == 0) atomicOr(flag, FL_OVERFLOW);
-                fail = true;
-                break;
-            }
-            __syncthreads();
-            ja = la + 1 + n0 + 1;   // just past the vertex
+            if (lane == 0) { VV[v].S = (uint32_t)S; VV[v].p12 = (uint32_t)(p1 | (p2 << 1)); }
+            s1p_prev = (S >> 2) & 1;
+            s2p_prev = S >> 3;
         }
-        if (fail) return;
-        if (dirty) {
-            uint2* OA = P.ev + ev_base(C, k, dspa, sla);
-            uint2* OB = P.ev + ev_base(C, k, dspc, slc);
-            for (int j = lane; j < na; j += 64) OA[(long long)j * C.nloc] = A[j];
-            for (int j = lane; j < nb; j += 64) OB[(long long)j * C.nloc] = B[j];
-            if (lane == 0) { P.cnt[cua] = na; P.cnt[cuc] = nb; }
+    }
+    __syncthreads();
+
+    // ---- worm counts of the legs that stay (lane per (vertex, leg))
+    const double lambda = C.lambda;
+    for (int w0 = 0; w0 < 4 * nbv; w0 += 64) {
+        const int uvg = w0 + lane;
+        if (uvg < 4 * nbv) {
+            const int v = uvg >> 2, g = uvg & 3;
+            const BsVert& Vv = VV[v];
+            const bool dead = (g == 2 && (Vv.fl & 64u)) || (g == 3 && (Vv.fl & 128u));
+            int n = 0;
+            if (!dead) {
+                const int S = (int)Vv.S, p1 = (int)(Vv.p12 & 1u), p2 = (int)(Vv.p12 >> 1);
+                const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
+                const int q1 = (int)((Vv.fl >> 2) & 1u), q2 = (int)((Vv.fl >> 3) & 1u);
+                const int sig = g == 0 ? p1 ^ s1 : g == 1 ? p2 ^ s2 : g == 2 ? s1p ^ q1 : s2p ^ q2;
+                Stream rs;
+                rs.init(C, sweep, RNG_BSL + (uint32_t)g, unit);
+                rs.w = (uint32_t)v << 17;
+                uint64_t dirs;
+                n = sample_worms(sE, lambda, rs, (long long)Vv.l[g], sig, off, dirs, flag);
+                if (n < 0) n = 0;
+            }
+            VV[v].cnt[g] = n;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+
+    // ---- new arrays: positions, kept objects, then the new worms
+    const int na2 = rebuild_positions(A, na, pvA, nvA, ordA, VV, (uint32_t)d, 0, 2, posA);
+    const int nb2 = rebuild_positions(B, nb, pvB, nvB, ordB, VV, (uint32_t)(d + 2), 1, 3, posB);
+    if (na2 > cap || nb2 > cap) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
+    __syncthreads();
+    rebuild_copy(A, na, pvA, nvA, ordA, VV, (uint32_t)d, 0, posA, A2);
+    rebuild_copy(B, nb, pvB, nvB, ordB, VV, (uint32_t)(d + 2), 1, posB, B2);
+    for (int w0 = 0; w0 < 4 * nbv; w0 += 64) {
+        const int uvg = w0 + lane;
+        if (uvg < 4 * nbv) {
+            const int v = uvg >> 2, g = uvg & 3;
+            const BsVert& Vv = VV[v];
+            if (Vv.cnt[g] > 0) {
+                const int S = (int)Vv.S, p1 = (int)(Vv.p12 & 1u), p2 = (int)(Vv.p12 >> 1);
+                const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
+                const int q1 = (int)((Vv.fl >> 2) & 1u), q2 = (int)((Vv.fl >> 3) & 1u);
+                const int sig = g == 0 ? p1 ^ s1 : g == 1 ? p2 ^ s2 : g == 2 ? s1p ^ q1 : s2p ^ q2;
+                const int start_occ = g == 0 ? p1 : g == 1 ? p2 : g == 2 ? s1p : s2p;
+                const int32_t base = g == 0 ? Vv.lo_a : g == 1 ? Vv.lo_c : Vv.t;
+                // first output slot: just above the leg's lower delimiter
+                int at;
+                if (g == 0) { const int lo = pvA[VA[v]]; at = lo >= 0 ? posA[lo] + 1 : 0; }
+                else if (g == 1) { const int lo = pvB[VB[v]]; at = lo >= 0 ? posB[lo] + 1 : 0; }
+                else if (g == 2) at = posA[VA[v]] + 1;
+                else at = posB[VB[v]] + 1;
+                uint2* O = (g == 0 || g == 2) ? A2 : B2;
+                Stream rs;
+                rs.init(C, sweep, RNG_BSL + (uint32_t)g, unit);
+                rs.w = (uint32_t)v << 17;
+                uint64_t dirs;
+                const int n = sample_worms(sE, lambda, rs, (long long)Vv.l[g], sig, off, dirs, flag);
+                for (int w = 0; w < n; w++) {
+                    const uint32_t occ = (uint32_t)((start_occ + w + 1) & 1);
+                    O[at + w] = make_uint2((uint32_t)(base + off[w * 64]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (occ << 3));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    {
+        uint2* OA = P.ev + ev_base(C, k, dspa, sla);
+        uint2* OB = P.ev + ev_base(C, k, dspc, slc);
+        for (int j = lane; j < na2; j += 64) OA[(long long)j * C.nloc] = A2[j];
+        for (int j = lane; j < nb2; j += 64) OB[(long long)j * C.nloc] = B2[j];
+        if (lane == 0) { P.cnt[cua] = na2; P.cnt[cuc] = nb2; }
     }
 }
 
