@@ -746,6 +746,9 @@ static int32_t hiexcl(const orc_chain* c, int site, int k, int j)
 /* one attempt of one worm (Step 5); returns 0 */
 static void worm_step(orc_chain* c, int k, wref* w, rstream* s)
 {
+    /* every attempt draws three words, used or not: the enter test, the
+       exit leg and the landing slot */
+    uint64_t w_enter = rs_next(s), w_exit = rs_next(s), w_slot = rs_next(s);
     int x = w->site;
     int iw = find_worm(c, x, w->slot);
     if (iw < 0) { c->flags |= FLAG_STATE; return; }
@@ -782,9 +785,6 @@ static void worm_step(orc_chain* c, int k, wref* w, rstream* s)
     int i = up ? (x == a ? 0 : 1) : (x == a ? 2 : 3);
     int64_t Lmin = L[0];
     for (int j = 1; j < 4; j++) if (L[j] < Lmin) Lmin = L[j];
-    /* an attempt that faces an interior vertex draws three words: the enter
-       test, the exit leg, the landing slot (the last two unused if it turns) */
-    uint64_t w_enter = rs_next(s), w_exit = rs_next(s), w_slot = rs_next(s);
     /* enter with probability L_min / L_i */
     uint64_t r = below(w_enter, (uint64_t)L[i]);
     if ((int64_t)r >= Lmin) { lx->e[iw].dir ^= 1; return; }

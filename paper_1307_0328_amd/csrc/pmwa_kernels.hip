@@ -476,11 +476,11 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 // (cycle-major, worm-list order), at most one attempt per worm in a window.
 // Lane k evaluates attempt s0+k on the state at the start of the window.
 // The first attempt whose read set meets a node an earlier attempt of the
-// window may write ends the window (owner stamps, LDS atomicMax).  An attempt
-// facing an interior vertex draws three words, so the stream position of
-// each attempt is a prefix count.  The surviving moves touch disjoint nodes
-// and are applied together; decisions and the final state equal those of the
-// attempts made one at a time in order.
+// window may write ends the window (owner stamps, LDS atomicMax).  Attempt s
+// draws stream words 3s, 3s+1, 3s+2 (enter test, exit leg, landing slot),
+// used or not.  The surviving moves touch disjoint nodes and are applied
+// together; decisions and the final state equal those of the attempts made
+// one at a time in order.
 //
 // One attempt (Step 5): a worm facing another worm, a temporal boundary or a
 // boundary vertex reverses; facing an interior vertex it enters with
@@ -491,11 +491,12 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 template <typename Idx>
 PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
                                    int NN, int nw, const ChainDev& C, uint32_t sweep, uint32_t D,
-                                   const double* __restrict__ scat)
+                                   const double* __restrict__ scat, unsigned int* flag)
 {
     long long windows = 0;
     const int lane = (int)threadIdx.x;
     const long long total = (long long)C.ncycle * nw;
+    if (total > 0x50000000LL) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return 0; }
     const int wmax = nw < 64 ? nw : 64;
     const uint32_t k0 = C.key0, k1 = C.key1, c1 = D, c2 = sweep, c3 = (C.chain_id << 8) | RNG_S;
     uint32_t cur = 0, filled = 0, wid = 0;
@@ -573,9 +574,8 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             atomicMax(&own[yp], stamp);
             atomicMax(&own[yn], stamp);
         }
-        // stream position: three words per attempt facing an interior vertex
-        const unsigned long long mmask = __ballot(mover);
-        const uint32_t myc = cur + 3u * (uint32_t)__popcll(mmask & ((1ULL << lane) - 1ULL));
+        // stream position: three words per attempt
+        const uint32_t myc = cur + 3u * (uint32_t)lane;
         __syncthreads();
         bool conflict = !act;
         if (act) {
@@ -643,7 +643,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             }
         }
         __syncthreads();
-        cur += 3u * (uint32_t)__popcll(mmask & (kc >= 64 ? ~0ULL : ((1ULL << kc) - 1ULL)));
+        cur += 3u * (uint32_t)kc;
         s0 += kc;
         iw0 += kc;
         if (iw0 >= nw) iw0 -= nw;
@@ -755,8 +755,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     // 4. N_cycle cycles, worms in list order, evaluated in windows
     for (int i = lane; i < NE + 2 * nloc; i += 64) own[i] = 0u;
     __syncthreads();
-    const long long windows =
-        scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain], (uint32_t)D, scat);
+    const long long windows = scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
+                                              (uint32_t)D, scat, &P.flags[chain]);
 
     // 5. measurement (Step 6) and write-back, one lane per site
     long long nv = 0, nkink = 0, nwc = 0, occ = 0;
