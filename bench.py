@@ -7,11 +7,15 @@ V = 1, mu = 0.5, eta = 0.05, 8x8 spatial x 2 temporal domains); the metric is
 vertex updates per second (bond vertices present after the vertex phase,
 summed over the timed sweeps, divided by the wall time).
 
-Also reported: the same chain replayed as a captured graph; 256 uneven chains
-batched in one launch sequence versus the same chains one chain per launch
-sequence; per-kernel device times (HIP events around every launch in the
-timed region) with the roofline of the dominant kernel; and the serial CPU
-oracle timed on a bounded sample of the headline workload.
+Also reported:
+- the same chain replayed as a captured graph;
+- 256 uneven chains batched in one launch sequence (launch form picked by
+  the autotuner) versus the same chains one chain per launch sequence;
+- a bounded continuous-batching serving run (p50/p99 job latency);
+- one 2048x2048 system (beta*t = 16, 64x64 x 4 domains);
+- per-kernel device times (HIP events around every launch in the timed
+  region) with the roofline of the dominant kernel;
+- the serial CPU oracle timed on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -59,9 +63,10 @@ def params_of(P, cfgs):
     return [P.make_params(**c) for c in cfgs]
 
 
-def run_timed(P, cfgs, steps, warmup, use_graph=False, timing=False):
+def run_timed(P, cfgs, steps, warmup, use_graph=False, timing=False, scatter_mode=0):
     """Warm up, then time exactly `steps` sweeps; returns a result dict."""
-    with P.Sim(params_of(P, cfgs), use_graph=use_graph, series_cap=max(4096, steps + warmup + 8)) as sim:
+    with P.Sim(params_of(P, cfgs), use_graph=use_graph, scatter_mode=scatter_mode,
+               series_cap=max(4096, steps + warmup + 8)) as sim:
         if warmup:
             sim.sweep(warmup)
         if sim.status() != 0:
@@ -156,6 +161,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--skip-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--serving-jobs", type=int, default=24, help="jobs of the serving run (0: skip)")
+    ap.add_argument("--large-sweeps", type=int, default=5, help="timed sweeps of the 2048^2 system (0: skip)")
+    ap.add_argument("--large-warmup", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -196,12 +204,12 @@ def main():
     nw_per = head["nw"] / args.steps
     alg_bytes = {
         "k_scatter": 32.0 * nv_per + 16.0 * nw_per,
-        # vertex phase: read both sites' records of each bond, write the new
-        # diagonal list (4 B each, about half the vertices)
-        "k_vertex": 32.0 * nv_per + 16.0 * nw_per + 2.0 * nv_per,
-        # assembly: read old records, read new diagonal entries at both ends,
-        # write the new records
-        "k_assemble": 32.0 * nv_per + 16.0 * nw_per + 4.0 * nv_per,
+        # vertex phase: read every site record once (16 B per vertex, 8 B per
+        # worm), write each bond's vertex list (4 B per vertex)
+        "k_vertex": 20.0 * nv_per + 8.0 * nw_per,
+        # re-generation: read each bond-list entry from both ends (8 B per
+        # vertex), write the site records (16 B per vertex, 8 B per worm)
+        "k_assemble": 24.0 * nv_per + 8.0 * nw_per,
     }
     hash_now = kernel_source_hash()
     traffic, prof = traffic_from_profile(hash_now)
@@ -237,19 +245,56 @@ def main():
         log("[bench] headline chain as a captured graph")
         g = run_timed(P, single, args.steps, args.warmup, use_graph=True)
         result["graph_form"] = {"value": g["nv"] / g["seconds"], "ms_per_step": g["seconds"] * 1e3 / args.steps}
+        from paper_1307_0328_amd import autotune as T
         batch = W.batched_256()
-        log(f"[bench] 256 chains batched (graph), {args.batched_steps} sweeps")
-        b = run_timed(P, batch, args.batched_steps, 20, use_graph=True)
+        log("[bench] autotuning the launch form of the 256-chain batch")
+        form, table = T.Tuner(sweeps=10, warmup=10).tune_launch(batch)
+        mode, graph = form
+        log(f"[bench] 256 chains batched (scatter_mode {mode}, graph {graph}), {args.batched_steps} sweeps")
+        b = run_timed(P, batch, args.batched_steps, 20, use_graph=graph, scatter_mode=mode)
         bsteps = max(4, args.batched_steps // 10)
         log(f"[bench] the same 256 chains, one chain per launch sequence, {bsteps} sweeps")
         p = run_one_chain_per_launch(P, batch, bsteps, 5)
         result["batched_256"] = {
             "workload": "256 chains: L in {16,24,32,48}, beta*t in {4,8,16}, mu on a 16-point grid "
                         "in [-2,2], V=0, eta=0.05, 4x4 spatial domains",
+            "launch_form": {"scatter_mode": mode, "graph": bool(graph)},
+            "autotune_table": [{"scatter_mode": f[0], "graph": bool(f[1]), "value": v} for f, v in table],
             "batched_value": b["nv"] / b["seconds"], "batched_ms_per_step": b["seconds"] * 1e3 / args.batched_steps,
             "one_chain_per_launch_value": p["nv"] / p["seconds"],
             "speedup": (b["nv"] / b["seconds"]) / (p["nv"] / p["seconds"]),
         }
+        if args.serving_jobs > 0:
+            from paper_1307_0328_amd import serve as S
+            specs = W.serving_jobs(args.serving_jobs, rate=50.0, seed=4, L_lo=16, L_hi=128, beta_lo=2.0,
+                                   beta_hi=16.0, sweeps_lo=200, sweeps_hi=2000)
+            shape = W.serving_slot_shape(128, 16.0)
+            log(f"[bench] serving: {args.serving_jobs} Poisson jobs at 50/s on 16 slots")
+            srv = S.Server([shape] * 16, event_cap=256, chunk=20)
+            try:
+                rep = srv.run(S.jobs_from_workload(specs), realtime=True, max_seconds=240)
+            finally:
+                srv.close()
+            rep["workload"] = (f"{args.serving_jobs} jobs, Poisson arrivals at 50/s: L uniform over multiples of 8 "
+                               "in [16,128], beta*t in [2,16], mu in [-2,2], V in {0,1}, eta=0.05, "
+                               "200-2000 sweeps (log-uniform); 16 slots of the largest shape, 20 sweeps "
+                               "between scheduling points")
+            result["serving"] = rep
+        if args.large_sweeps > 0:
+            big = W.large_2048()
+            log(f"[bench] 2048x2048 system: warm-up {args.large_warmup}, {args.large_sweeps} sweeps")
+            g2 = run_timed(P, big, args.large_sweeps, args.large_warmup, use_graph=False, timing=True)
+            nvb = g2["nv"] / args.large_sweeps
+            msb = g2["seconds"] * 1e3 / args.large_sweeps
+            kb = {PHASES[i]: float(g2["ms"][i]) / max(int(g2["launches"][i]), 1) for i in range(7)}
+            result["large_2048"] = {
+                "workload": "hard-core Bose-Hubbard 2048x2048, beta*t=16, t=1, V=0, mu=0, eta=0.02, "
+                            "domains 64x64 spatial x 4 temporal, one chain",
+                "value": g2["nv"] / g2["seconds"], "ms_per_step": msb, "vertices_per_sweep": nvb,
+                "sweeps_timed": args.large_sweeps, "warmup": args.large_warmup,
+                "algorithmic_GBps": (32.0 * nvb + 16.0 * g2["nw"] / args.large_sweeps) / (msb * 1e-3) / 1e9,
+                "kernel_ms_per_sweep": kb,
+            }
     if args.cpu_seconds > 0:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         result["cpu_baseline"] = cpu_baseline(single[0], args.cpu_seconds)
