@@ -71,7 +71,8 @@ typedef struct pmwa_params {
 
 /* Launch options.  Zero-initialise for the defaults. */
 typedef struct pmwa_opts {
-    void*   stream;           /* hipStream_t (borrowed); NULL = null stream      */
+    void*   stream;           /* hipStream_t (borrowed); NULL: the handle creates
+                                 one (default priority) and destroys it       */
     int32_t scatter_mode;     /* 0 auto, 1 domain in LDS, 2 domain in HBM        */
     int32_t series_cap;       /* per-chain device rows of per-sweep records     */
     int32_t event_cap;        /* events per (site, slab); 0 = from the density  */
