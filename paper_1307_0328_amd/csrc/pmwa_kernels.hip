@@ -474,9 +474,10 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 
 // Steps 5-6 over windows of consecutive attempts of the serial sequence
 // (cycle-major, worm-list order), at most one attempt per worm in a window.
-// Lane k evaluates attempt s0+k on the state at the start of the window.
-// The first attempt whose read set meets a node an earlier attempt of the
-// window may write ends the window (owner stamps, LDS atomicMax).  Attempt s
+// Lane k evaluates attempt s0+k, its whole decision included, on the state
+// at the start of the window.  The first attempt whose read set meets a node
+// an earlier move of the window writes ends the window (owner stamps, LDS
+// atomicMax).  Attempt s
 // draws stream words 3s, 3s+1, 3s+2 (enter test, exit leg, landing slot),
 // used or not.  The surviving moves touch disjoint nodes and are applied
 // together; decisions and the final state equal those of the attempts made
@@ -561,21 +562,59 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         Lmin = L3 < Lmin ? L3 : Lmin;
         const int32_t Li = up ? Lxb : Lxa;
         const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
-        // ---- nodes a moving attempt may write; conflicts with earlier attempts.
-        //      (A turning attempt only flips its own worm's direction, which no
-        //      other attempt of the window reads.)
-        const bool mover = act && !blocked;
+        // ---- the decision on the window's starting state: enter test, exit
+        //      leg and landing slot (stream words 3s, 3s+1, 3s+2)
+        const uint32_t myc = cur + 3u * (uint32_t)lane;
+        bool moved = false, above = false;
+        uint32_t Pn = 0, Nn = 0, fv = 0, newup = 0, fx_now = fx;
+        int32_t ntick = 0;
+        if (act && !blocked) {
+            const uint32_t r = below32(ring[myc & 511u], (uint32_t)Li);
+            moved = (int32_t)r < Lmin;
+            if (moved) {
+                // vertex roots with the worm in place
+                const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;
+                const uint32_t rxa = (fx >> 3) & 1u;
+                const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
+                const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
+                                 : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
+                const int S0 = S ^ (1 << i);
+                const double uu = u53(ring[(myc + 1u) & 511u]);
+                const double* row = scat + S0 * 16 + i * 4;
+                const int j = uu < row[0] ? 0 : uu < row[1] ? 1 : uu < row[2] ? 2 : 3;
+                const int32_t Lj = j == 0 ? L0 : j == 1 ? L1 : j == 2 ? L2 : L3;
+                const uint32_t r2 = below32(ring[(myc + 2u) & 511u], (uint32_t)Lj);
+                // leave leg i: above the end on x, that segment takes the worm's state
+                fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
+                const bool on_x = ((j & 1) != 0) != xa;
+                above = j >= 2;
+                if (above) {
+                    Pn = on_x ? x : y;
+                    Nn = on_x ? (up ? xf : wf) : yn;
+                    fv = on_x ? fx_now : fy;
+                    newup = fv & F_UP;
+                } else {
+                    Nn = on_x ? x : y;
+                    Pn = on_x ? (up ? wf : xf) : yp;
+                    const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
+                    newup = (fp & F_UP) ^ F_UP;
+                }
+                ntick = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
+            }
+        }
+        // ---- nodes a move writes: the worm's old and new neighbours (the
+        //      vertex end it leaves is one of the old ones).  Anything reading
+        //      the worm node itself reads one of its old neighbours.  A turn
+        //      only flips its own worm's direction, which no other attempt of
+        //      the window reads.  The first attempt that reads a node an
+        //      earlier one writes ends the window.
         const uint32_t stamp = (wid << 8) | (uint32_t)(255 - lane);
-        if (mover) {
+        if (moved) {
             atomicMax(&own[pw], stamp);
             atomicMax(&own[nn_], stamp);
-            atomicMax(&own[xf], stamp);
-            atomicMax(&own[y], stamp);
-            atomicMax(&own[yp], stamp);
-            atomicMax(&own[yn], stamp);
+            atomicMax(&own[Pn], stamp);
+            atomicMax(&own[Nn], stamp);
         }
-        // stream position: three words per attempt
-        const uint32_t myc = cur + 3u * (uint32_t)lane;
         __syncthreads();
         bool conflict = !act;
         if (act) {
@@ -594,47 +633,14 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
         // ---- apply the surviving attempts (disjoint nodes)
         if (lane < kc) {
-            bool moved = false;
-            if (!blocked) {
-                const uint32_t r = below32(ring[myc & 511u], (uint32_t)Li);
-                moved = (int32_t)r < Lmin;
-            }
             if (!moved) {
                 A.fl[w] = (uint8_t)(fw ^ F_DIRUP);
             } else {
-                // vertex roots with the worm in place
-                const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;
-                const uint32_t rxa = (fx >> 3) & 1u;
-                const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
-                const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
-                                 : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
-                const int S0 = S ^ (1 << i);
-                const double uu = u53(ring[(myc + 1u) & 511u]);
-                const double* row = scat + S0 * 16 + i * 4;
-                const int j = uu < row[0] ? 0 : uu < row[1] ? 1 : uu < row[2] ? 2 : 3;
-                const int32_t Lj = j == 0 ? L0 : j == 1 ? L1 : j == 2 ? L2 : L3;
-                const uint32_t r2 = below32(ring[(myc + 2u) & 511u], (uint32_t)Lj);
-                // leave leg i: above the end on x, that segment takes the worm's state
-                const uint32_t fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
-                const bool on_x = ((j & 1) != 0) != xa;
-                const bool above = j >= 2;
-                uint32_t Pn, Nn, newup, fv = 0;
-                if (above) {
-                    Pn = on_x ? x : y;
-                    Nn = on_x ? (up ? xf : wf) : yn;
-                    fv = on_x ? fx_now : fy;
-                    newup = fv & F_UP;
-                } else {
-                    Nn = on_x ? x : y;
-                    Pn = on_x ? (up ? wf : xf) : yp;
-                    const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
-                    newup = (fp & F_UP) ^ F_UP;
-                }
                 if (!up) A.fl[x] = (uint8_t)fx_now;
                 A.nxt[pw] = (Idx)nn_;
                 A.prv[nn_] = (Idx)pw;
                 if (above) A.fl[Pn] = (uint8_t)(fv ^ F_UP);
-                A.tick[w] = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
+                A.tick[w] = ntick;
                 A.fl[w] = (uint8_t)(F_WORM | (above ? F_DIRUP : 0u) | newup);
                 A.prv[w] = (Idx)Pn;
                 A.nxt[w] = (Idx)Nn;
