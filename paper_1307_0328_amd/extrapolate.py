@@ -1,0 +1,183 @@
+"""eta -> 0 extrapolation of PMWA observables (the paper's Benchmark section).
+
+The sweep samples H_eta = H - eta Q, so every expectation value carries an
+eta dependence. It is removed by simulating several eta and fitting a
+power series in eta. For the energy, the O(eta) coefficient of Eq. (Eng)
+vanishes in a finite system whenever Q measures a broken symmetry. The
+solid phase is therefore fitted as a + c eta^2. In the superfluid phase the
+paper fits a line at low temperature.
+
+Per-sweep estimators (per site), from the records of pmwa_measure:
+  E = 2 C - N_v / (beta N)    energy of the physical H in the eta ensemble
+                              (every operator of the expansion but the worms
+                              is a vertex of H; the shift C is per bond)
+  Q = N_w / (beta eta N)      order parameter (b + b^dagger per site)
+  n = occ2 / (2 M N)          density
+Errors come from a binning analysis. The fits are weighted least squares.
+
+The runs are batched: all (mu, eta) chains advance in the same launches.
+
+    python -m paper_1307_0328_amd.extrapolate --L 128 --beta 16 --V 3 --mu 4.2 \
+        --etas 0.01,0.02,0.03,0.04,0.05 --fit quad --therm 4000 --sweeps 40000
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# statistics
+# ---------------------------------------------------------------------------
+def binning(x, min_bins: int = 32):
+    """Mean, binned error and the error ratio err_binned / err_naive.
+
+    Consecutive samples are averaged in blocks of 2^k. The error estimate of
+    the largest block size that still leaves at least `min_bins` blocks is
+    returned. 0.5 * ratio^2 is an estimate of the integrated autocorrelation
+    time.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    if n < 2:
+        raise ValueError("binning needs at least two samples")
+    mean = float(x.mean())
+    naive = float(x.std(ddof=1) / math.sqrt(n))
+    err = naive
+    b = x.copy()
+    while len(b) // 2 >= min_bins:
+        m = len(b) // 2
+        b = 0.5 * (b[: 2 * m: 2] + b[1: 2 * m: 2])
+        err = max(err, float(b.std(ddof=1) / math.sqrt(len(b))))
+    return mean, err, (err / naive if naive > 0 else 1.0)
+
+
+def fit(eta, y, dy, powers):
+    """Weighted least squares y = sum_p c_p eta^p over `powers` (0 must be
+    among them).
+
+    Returns the extrapolated value c_0, its error, the coefficients, their
+    covariance and chi^2 / dof.
+    """
+    eta = np.asarray(eta, float)
+    y = np.asarray(y, float)
+    dy = np.asarray(dy, float)
+    if 0 not in powers:
+        raise ValueError("the constant term is the extrapolation")
+    X = np.stack([eta ** p for p in powers], axis=1)
+    w = 1.0 / dy ** 2
+    A = X.T @ (X * w[:, None])
+    cov = np.linalg.inv(A)
+    c = cov @ (X.T @ (w * y))
+    r = y - X @ c
+    dof = max(len(y) - len(powers), 1)
+    chi2 = float((w * r * r).sum() / dof)
+    i0 = list(powers).index(0)
+    return float(c[i0]), float(math.sqrt(cov[i0, i0])), c, cov, chi2
+
+
+FITS = {"quad": (0, 2), "lin": (0, 1), "quad+lin": (0, 1, 2)}
+
+
+# ---------------------------------------------------------------------------
+# per-sweep estimators
+# ---------------------------------------------------------------------------
+def estimators(rows, C: float, beta: float, N: int, eta: float, M: int):
+    nv = rows["nv"].astype(np.float64)
+    nw = rows["nw"].astype(np.float64)
+    occ = rows["occ2"].astype(np.float64)
+    return {"E": 2.0 * C - nv / (beta * N), "Q": nw / (beta * eta * N), "n": occ / (2.0 * M * N)}
+
+
+# ---------------------------------------------------------------------------
+# batched eta scan on the device
+# ---------------------------------------------------------------------------
+def run_scan(chains: list[dict], therm: int, sweeps: int, chunk: int = 500, progress=None,
+             use_graph: bool = True):
+    """Run every chain of `chains` (parameter dicts) in one handle: `therm`
+    sweeps, then `sweeps` measured sweeps. Returns per chain a dict of
+    per-sweep estimator arrays and the derived constants."""
+    from . import pmwa as P
+    ps = [P.make_params(**c) for c in chains]
+    out = []
+    with P.Sim(ps, use_graph=use_graph, series_cap=max(4096, 2 * chunk)) as sim:
+        infos = [sim.info(i) for i in range(len(ps))]
+        done = 0
+        t0 = time.time()
+        while done < therm:
+            n = min(chunk, therm - done)
+            sim.sweep(n)
+            for i in range(len(ps)):
+                sim.measure(i)
+            done += n
+            if progress:
+                progress(f"thermalise {done}/{therm} sweeps, {time.time() - t0:.0f} s")
+        rows = [[] for _ in ps]
+        done = 0
+        while done < sweeps:
+            n = min(chunk, sweeps - done)
+            sim.sweep(n)
+            for i in range(len(ps)):
+                rows[i].append(sim.measure(i))
+            done += n
+            if progress:
+                progress(f"measure {done}/{sweeps} sweeps, {time.time() - t0:.0f} s")
+        if sim.status() != 0:
+            raise RuntimeError(f"device error {sim.status()}")
+    for i, c in enumerate(chains):
+        r = np.concatenate(rows[i])
+        N = c.get("Lx", c.get("L")) * c.get("Ly", c.get("L"))
+        est = estimators(r, infos[i].C, c["beta"], N, c["eta"], infos[i].M)
+        out.append(dict(params=c, C=infos[i].C, est=est))
+    return out
+
+
+def summarize(results, fit_name: str, key: str = "E"):
+    """Binned mean and error per eta, then the fit to eta = 0."""
+    pts = []
+    for r in results:
+        m, e, ratio = binning(r["est"][key])
+        pts.append(dict(eta=r["params"]["eta"], mean=m, err=e, tau=0.5 * ratio * ratio))
+    pts.sort(key=lambda p: p["eta"])
+    e0, de0, c, cov, chi2 = fit([p["eta"] for p in pts], [p["mean"] for p in pts],
+                                [p["err"] for p in pts], FITS[fit_name])
+    return dict(points=pts, fit=fit_name, value=e0, error=de0, chi2_dof=chi2, coefficients=c.tolist())
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--L", type=int, default=128)
+    ap.add_argument("--beta", type=float, default=16.0)
+    ap.add_argument("--t", type=float, default=1.0)
+    ap.add_argument("--V", type=float, default=3.0)
+    ap.add_argument("--mu", type=float, default=4.2)
+    ap.add_argument("--etas", default="0.01,0.02,0.03,0.04,0.05")
+    ap.add_argument("--fit", default="quad", choices=sorted(FITS))
+    ap.add_argument("--grid", default="16,16,2", help="domains dom_x,dom_y,dom_tau")
+    ap.add_argument("--therm", type=int, default=2000)
+    ap.add_argument("--sweeps", type=int, default=20000)
+    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--out", default=None, help="write the summary as JSON")
+    a = ap.parse_args(argv)
+    gx, gy, gt = (int(v) for v in a.grid.split(","))
+    chains = [dict(Lx=a.L, Ly=a.L, beta=a.beta, t=a.t, V=a.V, mu=a.mu, eta=float(e), dom_x=gx, dom_y=gy,
+                   dom_tau=gt, seed=a.seed, chain_id=i) for i, e in enumerate(a.etas.split(","))]
+    res = run_scan(chains, a.therm, a.sweeps, a.chunk, progress=lambda s: print(s, flush=True))
+    summ = {k: summarize(res, a.fit if k == "E" else "lin", k) for k in ("E", "n", "Q")}
+    summ["config"] = vars(a)
+    text = json.dumps(summ, indent=1)
+    print(text, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    return summ
+
+
+if __name__ == "__main__":
+    sys.exit(0 if main() else 1)
