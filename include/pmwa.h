@@ -75,9 +75,13 @@ typedef struct pmwa_opts {
                                  one (default priority) and destroys it       */
     int32_t scatter_mode;     /* 0 auto, 1 domain in LDS, 2 domain in HBM        */
     int32_t series_cap;       /* per-chain device rows of per-sweep records     */
-    int32_t event_cap;        /* events per (site, slab); 0 = from the density  */
+    int32_t event_cap;        /* events per (site, slab), <= 32767; 0 = from the
+                                 density                                      */
     int32_t use_graph;        /* 1: replay a captured sweep (hipGraph)          */
-    int32_t reserved[4];
+    int32_t regen_mode;       /* worm re-generation: 0 auto, 1 a lane per (site,
+                                 slab), 2 a wavefront per (site, slab); the
+                                 result is the same                           */
+    int32_t reserved[3];
 } pmwa_opts;
 
 /* Raw per-sweep record of one chain (all sums over the whole lattice). */

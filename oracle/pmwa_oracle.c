@@ -696,6 +696,10 @@ static void worm_phase_R(orc_chain* c)
                 int32_t hi_tick; int q;
                 if (j < nv) { hi_tick = vs[j].tick; q = vs[j].below; }
                 else { hi_tick = c->T[k + 1]; q = c->bstate[(size_t)((k + 1) % c->ntau) * c->N + i]; }
+                /* interval j (j-th gap between the slab's vertices, from the
+                   bottom) draws from word 2^17 j of the (site, slab) stream */
+                s.w = (uint64_t)j << 17;
+                s.have = 0;
                 int n = sample_worms(c, &s, (int64_t)hi_tick - lo_tick, p ^ q, off, dirs);
                 el_reserve(c, &fresh, fresh.n + n + 1);
                 if (c->flags & FLAG_NOMEM) { free(vs); free(fresh.e); return; }

@@ -22,6 +22,7 @@
 
 namespace pmwa {
 __global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows);
+__global__ void k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
 __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
@@ -73,8 +74,11 @@ struct pmwa_handle {
     ChainDev* d_cd = nullptr;
     double* d_cdf = nullptr;
     int2 *d_blk_v = nullptr, *d_blk_r = nullptr, *d_blk_s = nullptr, *d_blk_bt = nullptr,
-         *d_blk_bsx = nullptr, *d_blk_bsy = nullptr;
-    int nblk_v = 0, nblk_r = 0, nblk_s = 0, nblk_bt = 0, nblk_bsx = 0, nblk_bsy = 0;
+         *d_blk_bsx = nullptr, *d_blk_bsy = nullptr, *d_blk_rw = nullptr;
+    int nblk_v = 0, nblk_r = 0, nblk_s = 0, nblk_bt = 0, nblk_bsx = 0, nblk_bsy = 0, nblk_rw = 0;
+    bool regen_wave = false;   // worm re-generation with one wavefront per (site, slab)
+    int rw_nmax = 4;           // bond-buffer entries of a site in a slab, at most
+    size_t rw_lds = 0;
     size_t lds_bytes = 0;
     size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
     int vs = 1;              // candidate column length of the vertex kernel
@@ -266,6 +270,7 @@ static int build_chain(const pmwa_params& p, uint32_t cap_override, HostChain& h
     d.ncycle = (int32_t)nc;
 
     d.cap = cap_override ? (int)cap_override : pmwa_default_event_cap(&p);
+    if (d.cap < 1 || d.cap > 32767) return PMWA_EINVAL;   // interval index < 2^15 (stream words)
     if (d.cap < 4 || (int64_t)d.nloc * (d.cap + 2) >= (int64_t)0x7FFFFFFF) return PMWA_EINVAL;
     hc.n_units_v = 2LL * d.ntau * d.N;
     hc.n_units_r = (int64_t)d.ntau * d.N;
@@ -335,7 +340,11 @@ static int launch_kernel(pmwa_t* h, int phase)
         if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows);
         break;
     case 2:
-        if (h->nblk_r) hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(64), 0, s, h->P, h->d_blk_r);
+        if (h->regen_wave) {
+            if (h->nblk_rw) hipLaunchKernelGGL(k_assemble_w, dim3(h->nblk_rw), dim3(64), h->rw_lds, s, h->P, h->d_blk_rw, h->rw_nmax);
+        } else if (h->nblk_r) {
+            hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(64), 0, s, h->P, h->d_blk_r);
+        }
         break;
     case 3:
         if (h->nblk_s) hipLaunchKernelGGL(k_scatter, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
@@ -422,7 +431,7 @@ void pmwa_destroy(pmwa_t* h)
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
                     h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->d_blk_v, h->d_blk_r,
-                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy};
+                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete h;
@@ -438,7 +447,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (!h) return PMWA_ENOMEM;
     if (opts) h->opts = *opts;
     if (h->opts.series_cap <= 0) h->opts.series_cap = 4096;
-    if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0) { delete h; return PMWA_EINVAL; }
+    if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0 ||
+        h->opts.event_cap > 32767 || h->opts.regen_mode < 0 || h->opts.regen_mode > 2) { delete h; return PMWA_EINVAL; }
     h->stream = (hipStream_t)h->opts.stream;
     if (!h->stream) {
         // work goes to a stream of the handle (default priority)
@@ -566,6 +576,27 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
     {
+        // worm re-generation: one lane per (site, slab), or one wavefront
+        // where there are too few units for lanes to fill the device
+        int64_t units = 0;
+        int maxcapb = 1;
+        for (auto& hc : h->ch) {
+            units += hc.n_units_r;
+            maxcapb = std::max(maxcapb, hc.d.capb);
+        }
+        const int mode = h->opts.regen_mode;
+        h->regen_wave = mode == 2 || (mode == 0 && units <= 65536);
+        h->rw_nmax = 4 * maxcapb;
+        h->rw_lds = (size_t)h->rw_nmax * 4 * sizeof(uint32_t) + (size_t)NWL * 64 * sizeof(int32_t);
+        if (h->rw_lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)k_assemble_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)h->rw_lds);
+        if (!r2 && h->regen_wave) {
+            block_table(h->ch, 1, &HostChain::n_units_r, t);
+            r2 = upload_table(t, &h->d_blk_rw, &h->nblk_rw);
+        }
+    }
+    {
         int maxcap = 0;
         for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
         // F table; A, B, A2, B2; 10 int arrays; the per-vertex records; one
@@ -643,7 +674,8 @@ int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_swe
     if (ev > hc.cap_ev || su > hc.cap_su || bv > hc.cap_bv || job.n_dom > hc.cap_dom ||
         (int64_t)job.cdf.size() > hc.cap_cdf || job.n_units_v > hc.cap_units_v ||
         job.n_units_r > hc.cap_units_r || job.n_bt > hc.cap_bt || job.n_bsx > hc.cap_bsx ||
-        job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc || d.cdf_stride > h->vs)
+        job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc || d.cdf_stride > h->vs ||
+        (h->regen_wave && 4 * d.capb > h->rw_nmax))
         return PMWA_EINVAL;
     const ChainDev& s = hc.d;
     d.ev_off = s.ev_off; d.cnt_off = s.cnt_off; d.bs_off = s.bs_off; d.bv_off = s.bv_off;

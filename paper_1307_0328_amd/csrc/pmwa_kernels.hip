@@ -349,8 +349,10 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
 // ===========================================================================
 // Step 4: per (site, slab) merge the vertex lists of the four bonds of the
 // site (kinks and new diagonal vertices, from the bond buffers) in (tick,
-// bond id) order, and generate the worms of every interval with Eq. (worm).
-// The site's old list (old vertices and worms) is overwritten.
+// bond id) order, and generate the worms of every interval with Eq. (worm);
+// interval r (from the bottom) draws from word 2^17 r of the (site, slab)
+// stream.  The site's old list (old vertices and worms) is overwritten.
+// k_assemble: one lane per (site, slab); k_assemble_w: one wavefront.
 // ===========================================================================
 __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict__ blk)
 {
@@ -398,6 +400,7 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     int32_t lo = C.T[k];
     int p = s_lo;
     int out = 0;
+    uint32_t ri = 0;                // interval index: vertices passed so far
     for (;;) {
         // next vertex in (tick, bond id) order
         int best = -1;
@@ -428,9 +431,12 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
             above = q ^ (int)((v >> 29) & 1u);
         }
         uint64_t dirs;
+        rs.w = ri << 17;            // interval ri draws from word 2^17 ri on
+        rs.blk = 0;
         const int n = sample_worms(sE, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
         if (n < 0) return;
         if (out + n + (best >= 0 ? 1 : 0) > C.cap) { atomicOr(flag, FL_OVERFLOW); return; }
+        ri++;
         int s = p;
         for (int w = 0; w < n; w++) {
             s ^= 1;
@@ -1287,7 +1293,10 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
                 const double g3 = (s2p ^ q2) ? f1[3] : f0[3];
                 W[m] = (((g0 * g1) * g2) * g3) * vwa[m];
             }
-            m4 |= (uint32_t)choose(W, uu) << (4 * x);
+            // an occupation pair with no allowed root pattern (zero-length
+            // legs of the wrong parity) gets the marker 15; only the pair
+            // the chain actually reaches is used, and it always has one
+            m4 |= ((uint32_t)choose(W, uu) & 15u) << (4 * x);
         }
         Vv.m4 = m4;
         VV[v] = Vv;
@@ -1304,7 +1313,11 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
             const int p2 = (fl & 32u) ? s2p_prev : (int)((fl >> 1) & 1u);
             const int m = (int)((m4 >> (4 * (p1 | (p2 << 1)))) & 15u);
             const int S = m == 0 ? 0 : m == 1 ? 5 : m == 2 ? 6 : m == 3 ? 9 : m == 4 ? 10 : 15;
-            if (lane == 0) { VV[v].S = (uint32_t)S; VV[v].p12 = (uint32_t)(p1 | (p2 << 1)); }
+            if (lane == 0) {
+                if (m > 5) atomicOr(flag, FL_STATE);
+                VV[v].S = (uint32_t)S;
+                VV[v].p12 = (uint32_t)(p1 | (p2 << 1));
+            }
             s1p_prev = (S >> 2) & 1;
             s2p_prev = S >> 3;
         }
@@ -1383,6 +1396,139 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
         for (int j = lane; j < nb2; j += 64) OB[(long long)j * C.nloc] = B2[j];
         if (lane == 0) { P.cnt[cua] = na2; P.cnt[cuc] = nb2; }
     }
+}
+
+// ===========================================================================
+// Step 4 with one wavefront per (site, slab): the entries of the four bond
+// buffers are ranked in (tick, bond id) order by counting, every interval
+// draws its worms from its own word range in parallel, and a prefix sum
+// places the events.  Same result as k_assemble.
+// dynamic LDS: val[nmax], slot[nmax], merged val[nmax], merged slot[nmax],
+// then one NWL-entry column of worm offsets per lane
+// ===========================================================================
+__global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blk[blockIdx.x];
+    const ChainDev& C = P.cd[bt.x];
+    const int u = bt.y;
+    const int lane = (int)threadIdx.x;
+    if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
+    uint32_t* val = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* vsl = val + nmax;
+    uint32_t* mval = vsl + nmax;
+    uint32_t* msl = mval + nmax;
+    int32_t* off = reinterpret_cast<int32_t*>(msl + nmax) + lane;
+    unsigned int* flag = &P.flags[bt.x];
+    const int sl = u % C.nloc;
+    const int rr = u / C.nloc;
+    const int dsp = rr % C.ndsp, k = rr / C.ndsp;
+    const int i = site_join(C, dsp, sl);
+    const int st = C.nloc;
+    uint2* E = P.ev + ev_base(C, k, dsp, sl);
+    const long long cu = C.cnt_off + unit_su(C, k, dsp, sl);
+    const int s_lo = P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
+    const int s_hi = P.bs[C.bs_off + unit_su(C, (k + 1) % C.ntau, dsp, sl)];
+    long long bids[4];
+    int base = 0;
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+        const int a = (d < 2) ? i : nbr(C, i, d);
+        int dspa, sla;
+        site_split(C, a, dspa, sla);
+        const int bd = d & 1;
+        const long long row = (long long)((k * 2 + bd) * C.ndsp + dspa);
+        const uint32_t* src = P.bv + C.bv_off + row * C.capb * C.nloc + sla;
+        const int ns = P.bvc[C.bvc_off + row * C.nloc + sla];
+        bids[d] = 2LL * a + bd;
+        if (base + ns > nmax) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
+        for (int j = lane; j < ns; j += 64) {
+            val[base + j] = src[(long long)j * st];
+            vsl[base + j] = (uint32_t)d;
+        }
+        base += ns;
+    }
+    const int nv = base;
+    __syncthreads();
+    // merged order: (tick, bond id) keys of a site are distinct
+    for (int e = lane; e < nv; e += 64) {
+        const uint32_t v = val[e];
+        const int32_t t = (int32_t)(v & BV_TICK);
+        const uint32_t dme = vsl[e];
+        const long long b = dme == 0 ? bids[0] : dme == 1 ? bids[1] : dme == 2 ? bids[2] : bids[3];
+        int rank = 0;
+        for (int e2 = 0; e2 < nv; e2++) {
+            const int32_t t2 = (int32_t)(val[e2] & BV_TICK);
+            const uint32_t d2 = vsl[e2];
+            const long long b2 = d2 == 0 ? bids[0] : d2 == 1 ? bids[1] : d2 == 2 ? bids[2] : bids[3];
+            rank += (t2 < t || (t2 == t && b2 < b)) ? 1 : 0;
+        }
+        mval[rank] = v;
+        msl[rank] = dme;
+    }
+    __syncthreads();
+    // intervals r = 0..nv (below vertex r; the last one ends at T_k+1)
+    const uint32_t sweep = (uint32_t)P.sweep[bt.x];
+    const uint32_t unit = (uint32_t)((long long)i * C.ntau + k);
+    const double lambda = C.lambda;
+    const int nint = nv + 1;
+    int carry = 0;
+    bool bad = false;
+    for (int r0 = 0; r0 < nint; r0 += 64) {
+        const int r = r0 + lane;
+        int nwr = 0;
+        uint64_t dirs = 0;
+        int32_t lo = 0, hi = 0;
+        int p = 0;
+        bool has_v = false;
+        uint32_t vinfo = 0;
+        if (r < nint) {
+            if (r > 0) {
+                const uint32_t v = mval[r - 1];
+                const uint32_t d = msl[r - 1];
+                lo = (int32_t)(v & BV_TICK);
+                const int qq = (int)((d < 2 ? v >> 30 : v >> 31) & 1u);
+                p = qq ^ (int)((v >> 29) & 1u);
+            } else {
+                lo = C.T[k];
+                p = s_lo;
+            }
+            int q;
+            if (r < nv) {
+                const uint32_t v = mval[r];
+                const uint32_t d = msl[r];
+                hi = (int32_t)(v & BV_TICK);
+                q = (int)((d < 2 ? v >> 30 : v >> 31) & 1u);
+                const int above = q ^ (int)((v >> 29) & 1u);
+                has_v = true;
+                vinfo = (d << 1) | ((uint32_t)above << 3);
+            } else {
+                hi = C.T[k + 1];
+                q = s_hi;
+            }
+            Stream rs;
+            rs.init(C, sweep, RNG_R, unit);
+            rs.w = (uint32_t)r << 17;
+            nwr = sample_worms(C.F, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
+            if (nwr < 0) { bad = true; nwr = 0; }
+        }
+        const int x = nwr + (has_v ? 1 : 0);
+        const int incl = wave_incl_sum(x);
+        const int pos = carry + incl - x;
+        carry += __shfl(incl, 63, 64);
+        if (r < nint && pos + x <= C.cap) {
+            int s = p;
+            for (int w = 0; w < nwr; w++) {
+                s ^= 1;
+                E[(long long)(pos + w) * st] = make_uint2((uint32_t)(lo + off[w * 64]),
+                                                          1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3));
+            }
+            if (has_v) E[(long long)(pos + nwr) * st] = make_uint2((uint32_t)hi, vinfo);
+        }
+    }
+    if (__ballot(bad)) return;
+    if (carry > C.cap) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
+    if (lane == 0) P.cnt[cu] = carry;
 }
 
 // ===========================================================================

@@ -97,16 +97,31 @@ def estimators(rows, C: float, beta: float, N: int, eta: float, M: int):
 # ---------------------------------------------------------------------------
 # batched eta scan on the device
 # ---------------------------------------------------------------------------
+def checkerboard_state(Lx: int, Ly: int, ntau: int, parity: int = 0) -> dict:
+    """A valid starting configuration: sites with (x + y) % 2 == parity
+    occupied at all times, no vertices, no worms (canonical state format)."""
+    occ = np.array([((x + y) & 1) == parity for y in range(Ly) for x in range(Lx)], dtype=np.uint8)
+    N = Lx * Ly
+    return dict(bstate=np.tile(occ, ntau), counts=np.zeros(N * ntau, np.int32),
+                ticks=np.zeros(0, np.int32), infos=np.zeros(0, np.uint32), sweep=0)
+
+
 def run_scan(chains: list[dict], therm: int, sweeps: int, chunk: int = 500, progress=None,
-             use_graph: bool = True):
+             use_graph: bool = True, init_states=None):
     """Run every chain of `chains` (parameter dicts) in one handle: `therm`
-    sweeps, then `sweeps` measured sweeps. Returns per chain a dict of
-    per-sweep estimator arrays and the derived constants."""
+    sweeps, then `sweeps` measured sweeps. `init_states` (optional, one
+    canonical state or None per chain) replaces the empty start. Returns
+    per chain a dict of per-sweep estimator arrays and the derived
+    constants."""
     from . import pmwa as P
     ps = [P.make_params(**c) for c in chains]
     out = []
     with P.Sim(ps, use_graph=use_graph, series_cap=max(4096, 2 * chunk)) as sim:
         infos = [sim.info(i) for i in range(len(ps))]
+        if init_states is not None:
+            for i, st in enumerate(init_states):
+                if st is not None:
+                    sim.set_state(st, i)
         done = 0
         t0 = time.time()
         while done < therm:
@@ -163,12 +178,17 @@ def main(argv=None):
     ap.add_argument("--sweeps", type=int, default=20000)
     ap.add_argument("--chunk", type=int, default=500)
     ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--start", default="empty", choices=["empty", "checkerboard"],
+                    help="initial configuration (an ordered solid for the CS phase)")
     ap.add_argument("--out", default=None, help="write the summary as JSON")
     a = ap.parse_args(argv)
     gx, gy, gt = (int(v) for v in a.grid.split(","))
     chains = [dict(Lx=a.L, Ly=a.L, beta=a.beta, t=a.t, V=a.V, mu=a.mu, eta=float(e), dom_x=gx, dom_y=gy,
                    dom_tau=gt, seed=a.seed, chain_id=i) for i, e in enumerate(a.etas.split(","))]
-    res = run_scan(chains, a.therm, a.sweeps, a.chunk, progress=lambda s: print(s, flush=True))
+    init = None
+    if a.start == "checkerboard":
+        init = [checkerboard_state(a.L, a.L, gt) for _ in chains]
+    res = run_scan(chains, a.therm, a.sweeps, a.chunk, progress=lambda s: print(s, flush=True), init_states=init)
     summ = {k: summarize(res, a.fit if k == "E" else "lin", k) for k in ("E", "n", "Q")}
     summ["config"] = vars(a)
     text = json.dumps(summ, indent=1)

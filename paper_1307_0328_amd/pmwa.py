@@ -33,7 +33,8 @@ class pmwa_params(C.Structure):
 
 class pmwa_opts(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("scatter_mode", C.c_int32), ("series_cap", C.c_int32),
-                ("event_cap", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("event_cap", C.c_int32), ("use_graph", C.c_int32), ("regen_mode", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class pmwa_obs(C.Structure):
@@ -225,7 +226,7 @@ class Sim:
     """A handle of one or more chains (convenience around the calls above)."""
 
     def __init__(self, chains, stream=None, scatter_mode=0, series_cap=4096, event_cap=0,
-                 use_graph=False):
+                 use_graph=False, regen_mode=0):
         if isinstance(chains, pmwa_params):
             chains = [chains]
         self.chains = list(chains)
@@ -235,6 +236,7 @@ class Sim:
         o.series_cap = series_cap
         o.event_cap = event_cap
         o.use_graph = 1 if use_graph else 0
+        o.regen_mode = regen_mode
         self.h = pmwa_create(self.chains, o)
 
     def close(self):

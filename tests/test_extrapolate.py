@@ -58,3 +58,14 @@ def test_estimators_from_records():
     np.testing.assert_allclose(est["E"], [2.5 - 100 / 18, 2.5 - 140 / 18])
     np.testing.assert_allclose(est["Q"], [4 / 1.8, 6 / 1.8])
     np.testing.assert_allclose(est["n"], [0.5, 1.0])
+
+
+def test_checkerboard_start_is_a_valid_configuration():
+    from oracle import oracle as O
+    st = X.checkerboard_state(6, 4, 2, parity=1)
+    assert st["bstate"].reshape(2, 24)[0].sum() == 12
+    ch = O.Chain(Lx=6, Ly=4, beta=2.0, V=3.0, mu=4.2, eta=0.05, dom_x=3, dom_y=2, dom_tau=2, seed=3)
+    ch.set_state(st)
+    assert ch.check() == 0
+    ch.sweep(3)
+    assert ch.check() == 0

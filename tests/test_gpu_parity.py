@@ -96,6 +96,70 @@ def test_each_phase_bit_exact(name):
         assert_series_equal(sim.measure(), ch.series(), name)
 
 
+def _zero_leg_vertices(st, Lx, Ly, dom_x, ntau, T):
+    """Vertices of x-direction bonds crossing a domain boundary with at least
+    three legs of zero length (other vertices at the same tick directly below
+    and above).  For them some occupation pairs below the vertex admit no
+    allowed root pattern."""
+    N = Lx * Ly
+    cnt = np.asarray(st["counts"]); tk = np.asarray(st["ticks"]); inf = np.asarray(st["infos"])
+    ev, o = {}, 0
+    for k in range(ntau):
+        for site in range(N):
+            n = int(cnt[k * N + site])
+            ev[(k, site)] = [(int(tk[o + j]), int(inf[o + j])) for j in range(n)]
+            o += n
+
+    def legs(lst, j, k):
+        lo = next((lst[m][0] for m in range(j - 1, -1, -1) if not lst[m][1] & 1), T[k])
+        hi = next((lst[m][0] for m in range(j + 1, len(lst)) if not lst[m][1] & 1), T[k + 1])
+        return lst[j][0] - lo, hi - lst[j][0]
+
+    found = 0
+    ex = Lx // dom_x
+    for k in range(ntau):
+        for y in range(Ly):
+            for dx in range(dom_x):
+                a = y * Lx + dx * ex + ex - 1
+                c = y * Lx + (a % Lx + 1) % Lx
+                A, B = ev[(k, a)], ev[(k, c)]
+                va = [j for j, e in enumerate(A) if not e[1] & 1 and (e[1] >> 1) & 3 == 0]
+                vc = [j for j, e in enumerate(B) if not e[1] & 1 and (e[1] >> 1) & 3 == 2]
+                for ja, jc in zip(va, vc):
+                    l0, l2 = legs(A, ja, k)
+                    l1, l3 = legs(B, jc, k)
+                    if [l0, l1, l2, l3].count(0) >= 3:
+                        found += 1
+    return found
+
+
+def test_spatial_boundary_infeasible_pair():
+    """Spatial-boundary update of a vertex whose legs mostly have zero length
+    (2^8 ticks per beta): the choice is precomputed for every occupation pair
+    below the vertex, some pairs admit no allowed root pattern, and that must
+    not disturb the choice for the pair the update reaches."""
+    P = _pm()
+    name = "4x4_tiny_ticks"
+    cfg = CASES[name]
+    ch = O.Chain(**cfg)
+    ch.sweep(15)
+    ch.series()
+    with P.Sim(P.make_params(**cfg)) as sim:
+        sim.set_state(ch.get_state())
+        for ph in (O.PH_V, O.PH_R, O.PH_S, O.PH_BT):
+            sim.phase(ph)
+            ch.phase(ph)
+        d = ch.derived()
+        T = list(d.T)[: d.ntau + 1]
+        assert _zero_leg_vertices(ch.get_state(), 4, 4, 2, d.ntau, T) > 0, "the state no longer has the case"
+        for ph in (O.PH_BSX, O.PH_BSY, O.PH_END):
+            say(f"[parity-infeasible] phase={ph}")
+            sim.phase(ph)
+            ch.phase(ph)
+            assert sim.status() == 0
+            assert_state_equal(sim.get_state(), ch.get_state(), f"{name} phase {ph}")
+
+
 def test_workload_64x64_grid8x8x2_bit_exact():
     """The single-chain 64x64 workload (beta*t = 16, V = 1, mu = 0.5, eta = 0.05,
     8x8 spatial x 2 temporal domains), a few sweeps."""
@@ -143,6 +207,23 @@ def test_graph_and_hbm_scatter_paths_match():
             sim.sweep(15)
             assert sim.status() == 0
             assert_state_equal(sim.get_state(), ref, f"mode {mode} graph {graph}")
+
+
+@pytest.mark.parametrize("regen_mode", [1, 2])
+def test_regeneration_forms_match(regen_mode):
+    """Worm re-generation with a lane per (site, slab) and with a wavefront
+    per (site, slab) give the oracle's trajectory."""
+    P = _pm()
+    for name in ("6x4_grid3x2x3", "4x4_tiny_ticks", "12x8_grid4x2x1"):
+        cfg = CASES[name]
+        ch = O.Chain(**cfg)
+        ch.sweep(12)
+        say(f"[regen] mode={regen_mode} case={name}")
+        with P.Sim(P.make_params(**cfg), regen_mode=regen_mode) as sim:
+            sim.sweep(12)
+            assert sim.status() == 0
+            assert_state_equal(sim.get_state(), ch.get_state(), f"regen {regen_mode} {name}")
+            assert_series_equal(sim.measure(), ch.series(), f"regen {regen_mode} {name}")
 
 
 def test_series_ring_drains():
