@@ -689,77 +689,136 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     const uint32_t BOT = (uint32_t)NE, TOP = (uint32_t)(NE + nloc);
     const Idx NIL = (Idx)~(Idx)0;
 
-    // 1. nodes from the events of the domain's sites
-    for (int idx = lane; idx < NE; idx += 64) {
-        int lo = 0, hi = nloc - 1;           // site s with off[s] <= idx < off[s+1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= idx) lo = mid; else hi = mid - 1;
-        }
-        const int s = lo, j = idx - off[s];
-        const uint2 e = P.ev[ev_base(C, k, dsp, s) + (long long)j * nloc];
-        A.tick[idx] = (int32_t)e.x;
-        A.fl[idx] = (uint8_t)(e.y & 15u);
-        A.prv[idx] = (Idx)(j > 0 ? (uint32_t)idx - 1 : BOT + s);
-        A.nxt[idx] = (Idx)(j + 1 < cnt[s] ? (uint32_t)idx + 1 : TOP + s);
-        A.aux[idx] = NIL;
-    }
+    // Steps 1-3 take one lane per site and walk the site's events in order.
+    // The vertices of a bond carry the same ticks on its two sites, so the
+    // partner of the r-th vertex of direction d on site s is the r-th vertex
+    // of direction d ^ 2 on the neighbouring site.  Before the windows start,
+    // the owner-stamp array serves as scratch for those ranks: per site
+    // (4 x 16 bit) the first rank slot of directions 1, 2, 3 and the vertex
+    // count, then per site (from off[s]) the node of every vertex, grouped by
+    // direction.
+    uint16_t* vtab = reinterpret_cast<uint16_t*>(own);
+    Idx* vnode = reinterpret_cast<Idx*>(vtab + 4 * nloc);
+
+    // 1. nodes from the events (loads of consecutive sites are adjacent in
+    //    HBM), the sentinels, and the vertex count per direction
     for (int s = lane; s < nloc; s += 64) {
+        const int o = off[s], n = cnt[s];
+        const uint2* E = P.ev + ev_base(C, k, dsp, s);
+        int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (int j0 = 0; j0 < n; j0 += 8) {
+            uint2 e[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (j0 + u < n) e[u] = E[(long long)(j0 + u) * nloc];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int j = j0 + u;
+                if (j < n) {
+                    const uint32_t idx = (uint32_t)(o + j);
+                    const uint32_t f = e[u].y & 15u;
+                    A.tick[idx] = (int32_t)e[u].x;
+                    A.fl[idx] = (uint8_t)f;
+                    A.prv[idx] = (Idx)(j > 0 ? idx - 1u : BOT + (uint32_t)s);
+                    A.nxt[idx] = (Idx)(j + 1 < n ? idx + 1u : TOP + (uint32_t)s);
+                    A.aux[idx] = NIL;
+                    const uint32_t vd = (f >> 1) & 3u;
+                    const bool v = (f & F_WORM) == 0u;
+                    c0 += v && vd == 0u;
+                    c1 += v && vd == 1u;
+                    c2 += v && vd == 2u;
+                    c3 += v && vd == 3u;
+                }
+            }
+        }
+        vtab[4 * s + 0] = (uint16_t)c0;
+        vtab[4 * s + 1] = (uint16_t)(c0 + c1);
+        vtab[4 * s + 2] = (uint16_t)(c0 + c1 + c2);
+        vtab[4 * s + 3] = (uint16_t)(c0 + c1 + c2 + c3);
         const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
         A.tick[BOT + s] = C.T[k];
         A.fl[BOT + s] = (uint8_t)(F_SBOT | (bsv ? F_UP : 0u));
-        A.nxt[BOT + s] = (Idx)(cnt[s] ? (uint32_t)off[s] : TOP + s);
+        A.nxt[BOT + s] = (Idx)(n ? (uint32_t)o : TOP + s);
         A.prv[BOT + s] = NIL;
         A.aux[BOT + s] = NIL;
         A.tick[TOP + s] = C.T[k + 1];
         A.fl[TOP + s] = (uint8_t)F_STOP;
-        A.prv[TOP + s] = (Idx)(cnt[s] ? (uint32_t)(off[s] + cnt[s] - 1) : BOT + s);
+        A.prv[TOP + s] = (Idx)(n ? (uint32_t)(o + n - 1) : BOT + s);
         A.nxt[TOP + s] = NIL;
         A.aux[TOP + s] = NIL;
     }
     __syncthreads();
-    // 2. partner ends of vertices; bonds leaving the domain are boundary
-    //    vertices (a worm bounces off them)
-    for (int idx = lane; idx < NE; idx += 64) {
-        const uint32_t f = A.fl[idx];
-        if (f & F_WORM) continue;
-        int lo = 0, hi = nloc - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= idx) lo = mid; else hi = mid - 1;
-        }
-        const int s = lo, lx = s % ex, ly = s / ex;
-        const int vd = (int)((f >> 1) & 3u);
-        int s2;
-        bool cross;
-        if (vd == 0) { cross = C.dom_x > 1 && lx == ex - 1; s2 = lx == ex - 1 ? s - (ex - 1) : s + 1; }
-        else if (vd == 2) { cross = C.dom_x > 1 && lx == 0; s2 = lx == 0 ? s + (ex - 1) : s - 1; }
-        else if (vd == 1) { cross = C.dom_y > 1 && ly == ey - 1; s2 = ly == ey - 1 ? s - (ey - 1) * ex : s + ex; }
-        else { cross = C.dom_y > 1 && ly == 0; s2 = ly == 0 ? s + (ey - 1) * ex : s - ex; }
-        if (cross) { A.fl[idx] = (uint8_t)(f | F_CROSS); continue; }
-        const int32_t t = A.tick[idx];
-        int a = off[s2], b = off[s2] + cnt[s2];   // first node of s2 with tick >= t
-        while (a < b) {
-            const int mid = (a + b) >> 1;
-            if (A.tick[mid] < t) a = mid + 1; else b = mid;
-        }
-        uint32_t found = NONE;
-        for (int m = a; m < off[s2] + cnt[s2] && A.tick[m] == t; m++) {
-            const uint32_t g = A.fl[m];
-            if (!(g & F_WORM) && (int)((g >> 1) & 3u) == (vd ^ 2)) { found = (uint32_t)m; break; }
-        }
-        if (found == NONE) atomicOr(&P.flags[chain], FL_STATE);
-        A.aux[idx] = (Idx)found;
-    }
-    // 3. worm list in (site, slot) order = node order
+    // 2. vertex nodes by (site, direction, rank), and the worm list in
+    //    (site, slot) order = node order
     int nw = 0;
-    for (int base = 0; base < NE; base += 64) {
-        const int idx = base + lane;
-        const int isw = (idx < NE) && (A.fl[idx] & F_WORM);
+    for (int base = 0; base < nloc; base += 64) {
+        const int s = base + lane;
+        const int nws = s < nloc ? cnt[s] - (int)vtab[4 * s + 3] : 0;
         int tot;
-        const int pos = wave_excl_scan(isw, tot);
-        if (isw) A.wl[nw + pos] = (Idx)idx;
+        const int wpos = nw + wave_excl_scan(nws, tot);
+        if (s < nloc) {
+            const int o = off[s], n = cnt[s];
+            int r0 = 0, r1 = (int)vtab[4 * s], r2 = (int)vtab[4 * s + 1], r3 = (int)vtab[4 * s + 2];
+            int rw = wpos;
+            for (int j = 0; j < n; j++) {
+                const uint32_t idx = (uint32_t)(o + j);
+                const uint32_t f = A.fl[idx];
+                if (f & F_WORM) {
+                    A.wl[rw++] = (Idx)idx;
+                } else {
+                    const uint32_t vd = (f >> 1) & 3u;
+                    const int r = vd == 0u ? r0 : vd == 1u ? r1 : vd == 2u ? r2 : r3;
+                    vnode[o + r] = (Idx)idx;
+                    r0 += vd == 0u;
+                    r1 += vd == 1u;
+                    r2 += vd == 2u;
+                    r3 += vd == 3u;
+                }
+            }
+        }
         nw += tot;
+    }
+    __syncthreads();
+    // 3. partner ends of vertices; bonds leaving the domain are boundary
+    //    vertices (a worm bounces off them)
+    for (int s = lane; s < nloc; s += 64) {
+        const int o = off[s], n = cnt[s];
+        const int lx = s % ex, ly = s / ex;
+        const bool cr0 = C.dom_x > 1 && lx == ex - 1, cr2 = C.dom_x > 1 && lx == 0;
+        const bool cr1 = C.dom_y > 1 && ly == ey - 1, cr3 = C.dom_y > 1 && ly == 0;
+        const int n0 = lx == ex - 1 ? s - (ex - 1) : s + 1;
+        const int n2 = lx == 0 ? s + (ex - 1) : s - 1;
+        const int n1 = ly == ey - 1 ? s - (ey - 1) * ex : s + ex;
+        const int n3 = ly == 0 ? s + (ey - 1) * ex : s - ex;
+        // rank slots of the partner direction on each neighbour: [first, end)
+        const int b0 = off[n0] + (int)vtab[4 * n0 + 1], e0 = off[n0] + (int)vtab[4 * n0 + 2];
+        const int b1 = off[n1] + (int)vtab[4 * n1 + 2], e1 = off[n1] + (int)vtab[4 * n1 + 3];
+        const int b2 = off[n2], e2 = off[n2] + (int)vtab[4 * n2];
+        const int b3 = off[n3] + (int)vtab[4 * n3], e3 = off[n3] + (int)vtab[4 * n3 + 1];
+        int q0 = b0, q1 = b1, q2 = b2, q3 = b3;
+        bool bad = false;
+        for (int j = 0; j < n; j++) {
+            const uint32_t idx = (uint32_t)(o + j);
+            const uint32_t f = A.fl[idx];
+            if (f & F_WORM) continue;
+            const uint32_t vd = (f >> 1) & 3u;
+            const bool cross = vd == 0u ? cr0 : vd == 1u ? cr1 : vd == 2u ? cr2 : cr3;
+            if (cross) { A.fl[idx] = (uint8_t)(f | F_CROSS); continue; }
+            const int q = vd == 0u ? q0 : vd == 1u ? q1 : vd == 2u ? q2 : q3;
+            const int qe = vd == 0u ? e0 : vd == 1u ? e1 : vd == 2u ? e2 : e3;
+            q0 += vd == 0u;
+            q1 += vd == 1u;
+            q2 += vd == 2u;
+            q3 += vd == 3u;
+            uint32_t m = NONE;
+            if (q < qe) {
+                m = (uint32_t)vnode[q];
+                if (A.tick[m] != A.tick[idx]) m = NONE;
+            }
+            bad |= m == NONE;
+            A.aux[idx] = (Idx)m;
+        }
+        if (bad) atomicOr(&P.flags[chain], FL_STATE);
     }
     __syncthreads();
     if (__any(P.flags[chain] != 0)) return;
@@ -770,61 +829,77 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     const long long windows = scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
                                               (uint32_t)D, scat, &P.flags[chain]);
 
-    // 5. measurement (Step 6) and write-back, one lane per site
+    // 5. measurement (Step 6) and write-back.  One lane per site follows the
+    //    site's node list and writes the events back; the length and worm
+    //    parity of every interval between vertices go to a table (the owner
+    //    stamps' memory; vertices never leave their site, so site s has at
+    //    most cnt[s] + 1 intervals, from slot off[s] + s), whose terms of the
+    //    improved worm-density estimator all lanes then evaluate at once.
+    uint32_t* qint = own;
+    const int NN = NE + 2 * nloc;
+    for (int i = lane; i < NN; i += 64) qint[i] = 0u;
+    __syncthreads();
     long long nv = 0, nkink = 0, nwc = 0, occ = 0;
-    double qimp = 0.0;
     bool bad = false;
     for (int s = lane; s < nloc; s += 64) {
         const long long ebase = ev_base(C, k, dsp, s);
+        uint32_t* qi = qint + off[s] + s;
+        const int qmax = cnt[s] + 1;
+        int nq = 0;
         int stt = (A.fl[BOT + s] >> 3) & 1;
         long long last = 2LL * C.T[k];
         int32_t ilo = C.T[k];
-        int par = 0, j = 0;
+        uint32_t par = 0;
+        int j = 0;
         uint32_t node = A.nxt[BOT + s];
         int guard = 0;
         for (;;) {
             if (node == TOP + (uint32_t)s) {
                 occ += (long long)stt * (2LL * C.T[k + 1] - last);
-                const long long ell = (long long)C.T[k + 1] - ilo;
-                if (ell > 0) {
-                    const double m = em1(sE, ell);
-                    const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
-                    qimp += (double)ell * (par ? 1.0 / th : th);
-                }
+                if (nq < qmax) qi[nq] = ((uint32_t)(C.T[k + 1] - ilo) << 1) | par;
+                else bad = true;
                 break;
             }
             if (node >= (uint32_t)NE || ++guard > NE) { bad = true; break; }
             const uint32_t f = A.fl[node];
             const int32_t tk = A.tick[node];
+            const uint32_t nx = A.nxt[node];
             const long long pos = 2LL * tk + (f & F_WORM);
             occ += (long long)stt * (pos - last);
             last = pos;
             if (f & F_WORM) {
                 nwc++;
-                par ^= 1;
+                par ^= 1u;
             } else {
-                const long long ell = (long long)tk - ilo;
-                if (ell > 0) {
-                    const double m = em1(sE, ell);
-                    const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
-                    qimp += (double)ell * (par ? 1.0 / th : th);
-                }
+                if (nq < qmax) qi[nq++] = ((uint32_t)(tk - ilo) << 1) | par;
+                else bad = true;
                 if (((f >> 1) & 3u) < 2) {
                     nv++;
                     if ((int)((f >> 3) & 1u) != stt) nkink++;
                 }
                 ilo = tk;
-                par = 0;
+                par = 0u;
             }
             stt = (int)((f >> 3) & 1u);
             if (j < C.cap) P.ev[ebase + (long long)j * nloc] = make_uint2((uint32_t)tk, f & 15u);
             j++;
-            node = A.nxt[node];
+            node = nx;
         }
         if (j > C.cap) bad = true;
         P.cnt[C.cnt_off + unit_su(C, k, dsp, s)] = j > C.cap ? C.cap : j;
     }
     if (bad) atomicOr(&P.flags[chain], FL_OVERFLOW);
+    __syncthreads();
+    double qimp = 0.0;
+    for (int i = lane; i < NN; i += 64) {
+        const uint32_t q = qint[i];
+        const long long ell = (long long)(q >> 1);
+        if (ell > 0) {
+            const double m = em1(sE, ell);
+            const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
+            qimp += (double)ell * ((q & 1u) ? 1.0 / th : th);
+        }
+    }
     for (int o = 32; o > 0; o >>= 1) {
         nv += __shfl_down(nv, o, 64);
         nkink += __shfl_down(nkink, o, 64);

@@ -81,7 +81,7 @@ def fit(eta, y, dy, powers):
     return float(c[i0]), float(math.sqrt(cov[i0, i0])), c, cov, chi2
 
 
-FITS = {"quad": (0, 2), "lin": (0, 1), "quad+lin": (0, 1, 2)}
+FITS = {"quad": (0, 2), "lin": (0, 1), "quad+lin": (0, 1, 2), "quad+quartic": (0, 2, 4)}
 
 
 # ---------------------------------------------------------------------------
