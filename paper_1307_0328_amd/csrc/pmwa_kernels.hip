@@ -498,7 +498,7 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 template <typename Idx>
 PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
                                    int NN, int nw, const ChainDev& C, uint32_t sweep, uint32_t D,
-                                   const double* __restrict__ scat, unsigned int* flag)
+                                   const uint64_t* __restrict__ sthr, unsigned int* flag)
 {
     long long windows = 0;
     const int lane = (int)threadIdx.x;
@@ -585,9 +585,10 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
                 const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
                                  : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
                 const int S0 = S ^ (1 << i);
-                const double uu = u53(ring[(myc + 1u) & 511u]);
-                const double* row = scat + S0 * 16 + i * 4;
-                const int j = uu < row[0] ? 0 : uu < row[1] ? 1 : uu < row[2] ? 2 : 3;
+                // u53(word) < P  <=>  (word >> 11) < ceil(P 2^53), exactly
+                const uint64_t w53 = ring[(myc + 1u) & 511u] >> 11;
+                const uint64_t* row = sthr + S0 * 16 + i * 4;
+                const int j = w53 < row[0] ? 0 : w53 < row[1] ? 1 : w53 < row[2] ? 2 : 3;
                 const int32_t Lj = j == 0 ? L0 : j == 1 ? L1 : j == 2 ? L2 : L3;
                 const uint32_t r2 = below32(ring[(myc + 2u) & 511u], (uint32_t)Lj);
                 // leave leg i: above the end on x, that segment takes the worm's state
@@ -622,18 +623,13 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             atomicMax(&own[Nn], stamp);
         }
         __syncthreads();
+        // stamps of earlier windows are below wid << 8; in this window a
+        // stamp exceeds the lane's own value exactly when an earlier lane set it
         bool conflict = !act;
         if (act) {
-            uint32_t v;
-            v = own[w];   conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-            v = own[pw];  conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-            v = own[nn_]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-            if (!blocked) {
-                v = own[xf]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-                v = own[y];  conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-                v = own[yp]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-                v = own[yn]; conflict |= (v >> 8) == wid && (int)(255u - (v & 255u)) < lane;
-            }
+            uint32_t v = max(own[w], max(own[pw], own[nn_]));
+            if (!blocked) v = max(v, max(max(own[xf], own[y]), max(own[yp], own[yn])));
+            conflict = v > stamp;
         }
         const unsigned long long cmask = __ballot(conflict);
         const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
@@ -681,7 +677,7 @@ template <typename Idx>
 PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D,
                              Nodes<Idx> A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
                              const int* __restrict__ off, const int* __restrict__ cnt,
-                             const double* __restrict__ scat, const double* __restrict__ sE, int NE)
+                             const uint64_t* __restrict__ sthr, const double* __restrict__ sE, int NE)
 {
     const int lane = (int)threadIdx.x;
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
@@ -827,7 +823,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     for (int i = lane; i < NE + 2 * nloc; i += 64) own[i] = 0u;
     __syncthreads();
     const long long windows = scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
-                                              (uint32_t)D, scat, &P.flags[chain]);
+                                              (uint32_t)D, sthr, &P.flags[chain]);
 
     // 5. measurement (Step 6) and write-back.  One lane per site follows the
     //    site's node list and writes the events back; the length and worm
@@ -914,7 +910,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     }
 }
 
-// dynamic LDS: [scat 256 doubles][off nloc+1][cnt nloc][nodes: tick 4B, nxt, prv,
+// dynamic LDS: [exit thresholds 256 x u64][expm1 table 1024 doubles][ring 512 words][off nloc+1][cnt nloc][nodes: tick 4B, nxt, prv,
 // aux, wl 2B each, fl 1B]
 __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict__ blk)
 {
@@ -926,12 +922,14 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     if (D >= C.ntau * C.ndsp) return;
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
     const int nloc = C.nloc;
-    double* scat = reinterpret_cast<double*>(smem);
-    double* sE = scat + 256;
+    uint64_t* sthr = reinterpret_cast<uint64_t*>(smem);
+    double* sE = reinterpret_cast<double*>(smem) + 256;
     uint64_t* ring = reinterpret_cast<uint64_t*>(smem + 1280 * sizeof(double));
     int* off = reinterpret_cast<int*>(smem + 1792 * sizeof(double));
     int* cnt = off + (nloc + 1);
-    for (int i = lane; i < 256; i += 64) scat[i] = C.scat[i];
+    // exit-leg thresholds ceil(P 2^53) of the cumulative scattering table
+    // (exact: a power-of-two scaling, then an integral value below 2^55)
+    for (int i = lane; i < 256; i += 64) sthr[i] = (uint64_t)ceil(C.scat[i] * 0x1.0p53);
     for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
     for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
     __syncthreads();
@@ -964,7 +962,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
         A.wl = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
         uint32_t* own = reinterpret_cast<uint32_t*>(p); p += (size_t)cap_l * 4;
         A.fl = reinterpret_cast<uint8_t*>(p);
-        scatter_domain(P, C, bt.x, D, A, own, ring, off, cnt, scat, sE, NE);
+        scatter_domain(P, C, bt.x, D, A, own, ring, off, cnt, sthr, sE, NE);
     } else {
         if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
         const long long b = C.scr_off + (long long)D * C.scr_nodes;
@@ -975,7 +973,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
         A.aux = P.s_aux + b;
         A.fl = P.s_fl + b;
         A.wl = P.s_wl + b;
-        scatter_domain(P, C, bt.x, D, A, P.s_own + b, ring, off, cnt, scat, sE, NE);
+        scatter_domain(P, C, bt.x, D, A, P.s_own + b, ring, off, cnt, sthr, sE, NE);
     }
 }
 
