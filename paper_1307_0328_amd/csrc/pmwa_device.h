@@ -30,6 +30,7 @@ namespace pmwa {
 constexpr int NT_MAX = 64;      // temporal domains
 constexpr int KMAXC = 256;      // Poisson table entries = max candidates per bond-slab
 constexpr int NWL = 48;         // worms drawn on one interval
+constexpr int RW_POOL = 256;    // worm-offset pool of the wavefront re-generation
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr uint32_t BV_TICK = (1u << 29) - 1u;   // bond-buffer entry: tick bits
 constexpr uint32_t BV_KINK = 1u << 29;          //   kink (occupations flip)
@@ -284,14 +285,13 @@ PMWA_DEV bool sort_col(int32_t* v, int n)
 // Worms of one interval with `ell` free slots and end-state parity sigma:
 // count by inversion of x^n/n!/f_sigma(x), x = lambda*ell, n <= ell (redraw
 // otherwise); distinct uniform offsets in [0, ell), sorted; one direction
-// bit per worm in ascending order.  Offsets go to off[0], off[64], ... (the
-// lane's column of an LDS array), direction bit i to bit i of `dirs`.
-// Returns n, or -1 on failure (flagged).
+// bit per worm in ascending order.  The count and the slots are two calls on
+// the same stream (the words follow each other as in one call).
+// worm_count returns n, or -1 on failure (flagged).
 template <class RS>
-PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, long long ell,
-                          int sigma, int32_t* off, uint64_t& dirs, unsigned int* flag)
+PMWA_DEV int worm_count(const double* __restrict__ E, double lambda, RS& s, long long ell, int sigma,
+                        unsigned int* flag)
 {
-    dirs = 0;
     if (ell == 0) {
         if (sigma) atomicOr(flag, FL_SAMPLER);
         return 0;
@@ -314,6 +314,15 @@ PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, lo
         if (U < S && k <= nmax) { n = (int)k; break; }
     }
     if (n < 0 || n > NWL) { atomicOr(flag, FL_SAMPLER); return -1; }
+    return n;
+}
+
+// the n slots: offsets to off[0], off[ST], ... (sorted), direction bit i to
+// bit i of `dirs`.  Returns false on failure (flagged).
+template <int ST, class RS>
+PMWA_DEV bool worm_slots(RS& s, long long ell, int n, int32_t* off, uint64_t& dirs, unsigned int* flag)
+{
+    dirs = 0;
     for (int i = 0; i < n; i++) {
         int32_t r;
         bool again;
@@ -321,14 +330,34 @@ PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, lo
         do {
             r = (int32_t)below(s.next(), (uint64_t)ell);
             again = false;
-            for (int j = 0; j < i; j++) again |= (off[j * 64] == r);
+            for (int j = 0; j < i; j++) again |= (off[j * ST] == r);
         } while (again && ++guard < 100000);
-        if (again) { atomicOr(flag, FL_SAMPLER); return -1; }
-        off[i * 64] = r;
+        if (again) { atomicOr(flag, FL_SAMPLER); return false; }
+        off[i * ST] = r;
     }
-    sort_col(off, n);
+    for (int x = 1; x < n; x++) {            // insertion sort
+        const int32_t t = off[x * ST];
+        int y = x - 1;
+        while (y >= 0 && off[y * ST] > t) {
+            off[(y + 1) * ST] = off[y * ST];
+            y--;
+        }
+        off[(y + 1) * ST] = t;
+    }
     for (int i = 0; i < n; i++) dirs |= (s.next() >> 63) << i;
-    return n;
+    return true;
+}
+
+// both steps; offsets in one lane's column of an LDS array (stride 64).
+// Returns n, or -1 on failure (flagged).
+template <class RS>
+PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, long long ell,
+                          int sigma, int32_t* off, uint64_t& dirs, unsigned int* flag)
+{
+    dirs = 0;
+    const int n = worm_count(E, lambda, s, ell, sigma, flag);
+    if (n <= 0) return n;
+    return worm_slots<64>(s, ell, n, off, dirs, flag) ? n : -1;
 }
 
 // the chain takes part in this sweep

@@ -1476,8 +1476,10 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
 // buffers are ranked in (tick, bond id) order by counting, every interval
 // draws its worms from its own word range in parallel, and a prefix sum
 // places the events.  Same result as k_assemble.
-// dynamic LDS: val[nmax], slot[nmax], merged val[nmax], merged slot[nmax],
-// then one NWL-entry column of worm offsets per lane
+// dynamic LDS: val[nmax], merged val[nmax] (u32), a pool of RW_POOL worm
+// offsets, slot[nmax], merged slot[nmax] (u8).  The intervals' worm counts
+// are drawn first; a prefix sum over the wave places every lane's offsets in
+// the pool, in rounds if the 64 intervals together have more than RW_POOL.
 // ===========================================================================
 __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax)
 {
@@ -1488,10 +1490,10 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
     const int lane = (int)threadIdx.x;
     if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
     uint32_t* val = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* vsl = val + nmax;
-    uint32_t* mval = vsl + nmax;
-    uint32_t* msl = mval + nmax;
-    int32_t* off = reinterpret_cast<int32_t*>(msl + nmax) + lane;
+    uint32_t* mval = val + nmax;
+    int32_t* pool = reinterpret_cast<int32_t*>(mval + nmax);
+    uint8_t* vsl = reinterpret_cast<uint8_t*>(pool + RW_POOL);
+    uint8_t* msl = vsl + nmax;
     unsigned int* flag = &P.flags[bt.x];
     const int sl = u % C.nloc;
     const int rr = u / C.nloc;
@@ -1517,7 +1519,7 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
         if (base + ns > nmax) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
         for (int j = lane; j < ns; j += 64) {
             val[base + j] = src[(long long)j * st];
-            vsl[base + j] = (uint32_t)d;
+            vsl[base + j] = (uint8_t)d;
         }
         base += ns;
     }
@@ -1537,7 +1539,7 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
             rank += (t2 < t || (t2 == t && b2 < b)) ? 1 : 0;
         }
         mval[rank] = v;
-        msl[rank] = dme;
+        msl[rank] = (uint8_t)dme;
     }
     __syncthreads();
     // intervals r = 0..nv (below vertex r; the last one ends at T_k+1)
@@ -1550,11 +1552,11 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
     for (int r0 = 0; r0 < nint; r0 += 64) {
         const int r = r0 + lane;
         int nwr = 0;
-        uint64_t dirs = 0;
         int32_t lo = 0, hi = 0;
         int p = 0;
         bool has_v = false;
         uint32_t vinfo = 0;
+        Stream rs;
         if (r < nint) {
             if (r > 0) {
                 const uint32_t v = mval[r - 1];
@@ -1579,25 +1581,41 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
                 hi = C.T[k + 1];
                 q = s_hi;
             }
-            Stream rs;
             rs.init(C, sweep, RNG_R, unit);
             rs.w = (uint32_t)r << 17;
-            nwr = sample_worms(C.F, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
+            nwr = worm_count(C.F, lambda, rs, (long long)hi - lo, p ^ q, flag);
             if (nwr < 0) { bad = true; nwr = 0; }
         }
         const int x = nwr + (has_v ? 1 : 0);
         const int incl = wave_incl_sum(x);
         const int pos = carry + incl - x;
         carry += __shfl(incl, 63, 64);
-        if (r < nint && pos + x <= C.cap) {
-            int s = p;
-            for (int w = 0; w < nwr; w++) {
-                s ^= 1;
-                E[(long long)(pos + w) * st] = make_uint2((uint32_t)(lo + off[w * 64]),
-                                                          1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3));
+        const bool fits = r < nint && pos + x <= C.cap;
+        // slots through the pool; the first pending lane always fits
+        // (nwr <= NWL < RW_POOL), so every round makes progress
+        const int wst = wave_incl_sum(nwr) - nwr;
+        bool todo = nwr > 0;
+        for (unsigned long long pend = __ballot(todo); pend; pend = __ballot(todo)) {
+            const int first = __ffsll((long long)pend) - 1;
+            const int pb = __shfl(wst, first, 64);
+            if (todo && wst + nwr <= pb + RW_POOL) {
+                int32_t* o = pool + (wst - pb);
+                uint64_t dirs;
+                if (!worm_slots<1>(rs, (long long)hi - lo, nwr, o, dirs, flag)) {
+                    bad = true;
+                } else if (fits) {
+                    int sst = p;
+                    for (int w = 0; w < nwr; w++) {
+                        sst ^= 1;
+                        E[(long long)(pos + w) * st] = make_uint2((uint32_t)(lo + o[w]),
+                                                                  1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)sst << 3));
+                    }
+                }
+                todo = false;
             }
-            if (has_v) E[(long long)(pos + nwr) * st] = make_uint2((uint32_t)hi, vinfo);
+            __builtin_amdgcn_wave_barrier();
         }
+        if (has_v && fits) E[(long long)(pos + nwr) * st] = make_uint2((uint32_t)hi, vinfo);
     }
     if (__ballot(bad)) return;
     if (carry > C.cap) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
