@@ -31,6 +31,11 @@ constexpr int NT_MAX = 64;      // temporal domains
 constexpr int KMAXC = 256;      // Poisson table entries = max candidates per bond-slab
 constexpr int NWL = 48;         // worms drawn on one interval
 constexpr int RW_POOL = 256;    // worm-offset pool of the wavefront re-generation
+// lanes per workgroup of the lane-per-unit kernels (vertex phase, temporal
+// boundaries).  Full wavefronts: with fewer lanes the same work takes more
+// memory and LDS instructions per CU, which measured slower than leaving
+// SIMDs idle.
+constexpr int VL = 64;
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr uint32_t BV_TICK = (1u << 29) - 1u;   // bond-buffer entry: tick bits
 constexpr uint32_t BV_KINK = 1u << 29;          //   kink (occupations flip)
@@ -262,22 +267,23 @@ PMWA_DEV int choose(const double (&W)[N], double u)
     return pick >= 0 ? pick : last;
 }
 
-// Sorts v[0], v[64], ..., v[64(n-1)] (one lane's column of an LDS array)
+// Sorts v[0], v[ST], ..., v[ST(n-1)] (one lane's column of an LDS array)
 // ascending; returns true when two entries are equal.
+template <int ST = 64>
 PMWA_DEV bool sort_col(int32_t* v, int n)
 {
     bool rep = false;
     for (int x = 1; x < n; x++) {
-        const int32_t t = v[x * 64];
+        const int32_t t = v[x * ST];
         int y = x - 1;
-        int32_t w = v[y * 64];
+        int32_t w = v[y * ST];
         while (w > t) {
-            v[(y + 1) * 64] = w;
+            v[(y + 1) * ST] = w;
             if (--y < 0) break;
-            w = v[y * 64];
+            w = v[y * ST];
         }
         rep |= (y >= 0 && w == t);
-        v[(y + 1) * 64] = t;
+        v[(y + 1) * ST] = t;
     }
     return rep;
 }
@@ -348,16 +354,16 @@ PMWA_DEV bool worm_slots(RS& s, long long ell, int n, int32_t* off, uint64_t& di
     return true;
 }
 
-// both steps; offsets in one lane's column of an LDS array (stride 64).
+// both steps; offsets in one lane's column of an LDS array (stride ST).
 // Returns n, or -1 on failure (flagged).
-template <class RS>
+template <int ST = 64, class RS>
 PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, long long ell,
                           int sigma, int32_t* off, uint64_t& dirs, unsigned int* flag)
 {
     dirs = 0;
     const int n = worm_count(E, lambda, s, ell, sigma, flag);
     if (n <= 0) return n;
-    return worm_slots<64>(s, ell, n, off, dirs, flag) ? n : -1;
+    return worm_slots<ST>(s, ell, n, off, dirs, flag) ? n : -1;
 }
 
 // the chain takes part in this sweep

@@ -337,7 +337,7 @@ static int launch_kernel(pmwa_t* h, int phase)
     hipStream_t s = h->stream;
     switch (phase) {
     case 1:
-        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(64), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows);
+        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(VL), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows);
         break;
     case 2:
         if (h->regen_wave) {
@@ -350,7 +350,7 @@ static int launch_kernel(pmwa_t* h, int phase)
         if (h->nblk_s) hipLaunchKernelGGL(k_scatter, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
         break;
     case 4:
-        if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(64), 0, s, h->P, h->d_blk_bt);
+        if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(VL), 0, s, h->P, h->d_blk_bt);
         break;
     case 5:
         if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsx, 0);
@@ -569,10 +569,10 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (hipMemcpy(h->d_cd, cds.data(), n_chains * sizeof(ChainDev), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_cdf, cdfs.data(), cdf * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         r2 = PMWA_EDEVICE;
-    if (!r2) { block_table(h->ch, 64, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
+    if (!r2) { block_table(h->ch, VL, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
     if (!r2) { block_table(h->ch, 64, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_dom, t); r2 = upload_table(t, &h->d_blk_s, &h->nblk_s); }
-    if (!r2) { block_table(h->ch, 64, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
+    if (!r2) { block_table(h->ch, VL, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
     {
@@ -599,10 +599,9 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     {
         int maxcap = 0;
         for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
-        // F table; A, B, A2, B2; 10 int arrays; the per-vertex records; one
-        // worm-offset column per lane
-        h->bs_lds = 1024 * sizeof(double) + (size_t)maxcap * (4 * sizeof(uint2) + 10 * sizeof(int) + sizeof(BsVert)) +
-                    (size_t)NWL * 64 * sizeof(int32_t);
+        // A, B, A2, B2; 10 int arrays; the per-vertex records; the worm-offset pool
+        h->bs_lds = (size_t)maxcap * (4 * sizeof(uint2) + 10 * sizeof(int) + sizeof(BsVert)) +
+                    (size_t)RW_POOL * sizeof(int32_t);
         if (h->bs_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->bs_lds);
@@ -611,9 +610,9 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         h->vs = vs;
         // occupation-changing objects (kinks and worms) of a site in a slab
         // staged in LDS; a lane with more reads its lists from HBM
-        const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + 64 * sizeof(int32_t));
+        const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + VL * sizeof(int32_t));
         h->v_rows = std::max(8, std::min(std::max(maxcap, 8), 64));
-        h->v_lds = v_fixed + (size_t)h->v_rows * 128 * sizeof(uint32_t);
+        h->v_lds = v_fixed + (size_t)h->v_rows * 2 * VL * sizeof(uint32_t);
         if (h->v_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_vertex, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->v_lds);

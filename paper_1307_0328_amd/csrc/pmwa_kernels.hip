@@ -35,13 +35,13 @@ struct FlipList {
     int n, s0, d;
     PMWA_DEV uint32_t get(int j) const
     {
-        const uint32_t x = r[j * 64];
+        const uint32_t x = r[j * VL];
         const uint32_t w = (x >> 29) & 1u;
         const uint32_t up = (uint32_t)(s0 ^ ((j + 1) & 1));
         const uint32_t m = (!w && (int)(x >> 30) == d) ? 1u : 0u;
         return (x & (BV_TICK | (1u << 29))) | (up << 30) | (m << 31);
     }
-    PMWA_DEV int dir(int j) const { return (int)(r[j * 64] >> 30); }
+    PMWA_DEV int dir(int j) const { return (int)(r[j * VL] >> 30); }
 };
 struct FullList {
     const uint2* E;
@@ -117,7 +117,7 @@ PMWA_DEV int bond_walk(const ChainDev& C, const BondCtx& B, const Lst& LA, const
                 nout++;
             }
             i++;
-            if (i < np) { const uint32_t cw = (uint32_t)cand[i * 64]; tau = (int32_t)(cw & BV_TICK); rank = cw >> 29; }
+            if (i < np) { const uint32_t cw = (uint32_t)cand[i * VL]; tau = (int32_t)(cw & BV_TICK); rank = cw >> 29; }
             continue;
         }
         if (!ha && !hc) break;
@@ -180,7 +180,7 @@ struct AccRank {
 // the acceptance words of the sorted candidates follow the tick words
 PMWA_DEV void tag_ranks(int32_t* cand, int n, Stream& rs, const AccRank& AR)
 {
-    for (int i = 0; i < n; i++) cand[i * 64] = (int32_t)((uint32_t)cand[i * 64] | (AR.rank(rs.next()) << 29));
+    for (int i = 0; i < n; i++) cand[i * VL] = (int32_t)((uint32_t)cand[i * VL] | (AR.rank(rs.next()) << 29));
 }
 
 // kinks of the bond, exact sequential candidate draws (a tick on a kink of
@@ -217,12 +217,12 @@ PMWA_DEV int vertex_exact(const ChainDev& C, const BondCtx& B, const Lst& LA, co
             tau = Tk + (int32_t)below(rs.next(), dT);
             again = false;
             for (int j = 0; j < nk; j++) again |= ((int32_t)out[(long long)j * B.st] == tau);
-            for (int j = 0; j < i; j++) again |= (cand[j * 64] == tau);
+            for (int j = 0; j < i; j++) again |= (cand[j * VL] == tau);
         } while (again && ++guard < 100000);
         if (again) { atomicOr(flag, FL_SAMPLER); n = i; break; }
-        cand[i * 64] = tau;
+        cand[i * VL] = tau;
     }
-    sort_col(cand, n);
+    sort_col<VL>(cand, n);
     tag_ranks(cand, n, rs, AR);
     long long unused = 0;
     const int nout = bond_walk<false>(C, B, LA, LC, Tk, Tk1, cand, n, AR.cnt, out, capb, unused);
@@ -245,7 +245,7 @@ PMWA_DEV int stage_flips(const uint2* E, int n, int st, int s0, uint32_t* F, int
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const int up = (int)ev_up(e[q].y);
-            F[(nf < rows ? nf : rows - 1) * 64] = e[q].x | ((e[q].y & 1u) << 29) | (((e[q].y >> 1) & 3u) << 30);
+            F[(nf < rows ? nf : rows - 1) * VL] = e[q].x | ((e[q].y & 1u) << 29) | (((e[q].y >> 1) & 3u) << 30);
             nf += up != s ? 1 : 0;
             s = up;
         }
@@ -253,7 +253,7 @@ PMWA_DEV int stage_flips(const uint2* E, int n, int st, int s0, uint32_t* F, int
     for (; j < n; j++) {
         const uint2 e = E[(long long)j * st];
         const int up = (int)ev_up(e.y);
-        F[(nf < rows ? nf : rows - 1) * 64] = e.x | ((e.y & 1u) << 29) | (((e.y >> 1) & 3u) << 30);
+        F[(nf < rows ? nf : rows - 1) * VL] = e.x | ((e.y & 1u) << 29) | (((e.y >> 1) & 3u) << 30);
         nf += up != s ? 1 : 0;
         s = up;
     }
@@ -264,7 +264,7 @@ PMWA_DEV int stage_flips(const uint2* E, int n, int st, int s0, uint32_t* F, int
 // doubles), the candidate ticks (one column of vs entries per lane), and the
 // occupation-changing objects of both ends of each lane's bond (two columns
 // of `rows` entries per lane)
-__global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows)
+__global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
@@ -273,10 +273,10 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
     const int u = bt.y + lane;
     double* s_cdf = reinterpret_cast<double*>(smem);
     int32_t* cand = reinterpret_cast<int32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + lane;
-    uint32_t* FA = reinterpret_cast<uint32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + (size_t)vs * 64 + lane;
-    uint32_t* FC = FA + (size_t)rows * 64;
+    uint32_t* FA = reinterpret_cast<uint32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + (size_t)vs * VL + lane;
+    uint32_t* FC = FA + (size_t)rows * VL;
     const int k_first = bt.y / (2 * C.N);
-    for (int i = lane; i < 2 * C.cdf_stride; i += 64) {
+    for (int i = lane; i < 2 * C.cdf_stride; i += VL) {
         const int kk = k_first + i / C.cdf_stride;
         s_cdf[i] = kk < C.ntau ? P.cdf[C.cdf_off + (long long)kk * C.cdf_stride + i % C.cdf_stride] : 2.0;
     }
@@ -328,8 +328,8 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
         const uint64_t dT = (uint64_t)(Tk1 - Tk);
         // ticks as first drawn; they are the ticks kept unless one repeats
         // a kink of the bond or another candidate
-        for (int i = 0; i < n; i++) cand[i * 64] = Tk + (int32_t)below(rs.next(), dT);
-        const bool rep = sort_col(cand, n);
+        for (int i = 0; i < n; i++) cand[i * VL] = Tk + (int32_t)below(rs.next(), dT);
+        const bool rep = sort_col<VL>(cand, n);
         AccRank AR;
         AR.init(C);
         if (!rep) tag_ranks(cand, n, rs, AR);
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(64) k_vertex(Pools P, const int2* __restrict__
         P.bvc[C.bvc_off + (long long)((k * 2 + d) * C.ndsp + dsp) * C.nloc + sl] = nout;
     }
     // wave sum of the bond occupation integral -> one atomic per block
-    for (int o = 32; o > 0; o >>= 1) nn += __shfl_down(nn, o, 64);
+    for (int o = VL / 2; o > 0; o >>= 1) nn += __shfl_down(nn, o, 64);
     if (threadIdx.x == 0 && nn) atomicAdd(&P.nnacc[bt.x], (unsigned long long)nn);
 }
 
@@ -1000,26 +1000,27 @@ struct SiteArr {
 
 // writes the n worms of an interval (slot base + off[64 w], direction bit w
 // of dirs) as events from position j0, occupation starting at p
+template <int ST>
 PMWA_DEV void put_worms(SiteArr& A, int j0, int32_t base, const int32_t* off, uint64_t dirs, int n, int p)
 {
     int s = p;
     for (int w = 0; w < n; w++) {
         s ^= 1;
-        A.put(j0 + w, make_uint2((uint32_t)(base + off[w * 64]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3)));
+        A.put(j0 + w, make_uint2((uint32_t)(base + off[w * ST]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3)));
     }
 }
 
 // Step 1, Eq. (Para): one lane per site, temporal boundaries k = 0.. in order;
 // the upper domain's stream (site, k) makes the choice, then the worms of the
 // two legs I_1 (above) and I_2 (below) are regenerated.
-__global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restrict__ blk)
+__global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restrict__ blk)
 {
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
     __shared__ double sE[1024];
-    __shared__ int32_t s_off[2 * NWL * 64];
-    for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
+    __shared__ int32_t s_off[2 * NWL * VL];
+    for (int i = (int)threadIdx.x; i < 1024; i += VL) sE[i] = C.F[i];
     __syncthreads();
     if (u >= C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
@@ -1029,7 +1030,7 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
     const int nt = C.ntau;
     const uint32_t sweep = (uint32_t)P.sweep[bt.x];
     int32_t* o1 = s_off + threadIdx.x;
-    int32_t* o2 = s_off + NWL * 64 + threadIdx.x;
+    int32_t* o2 = s_off + NWL * VL + threadIdx.x;
     for (int k = 0; k < nt; k++) {
         Stream rs;
         rs.init(C, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
@@ -1044,10 +1045,10 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
                 const double W[2] = {1.0, 1.0};
                 const int sp = choose(W, u53(rs.next()));
                 uint64_t d1;
-                const int m = sample_worms(sE, lambda, rs, C.M, 0, o1, d1, flag);
+                const int m = sample_worms<VL>(sE, lambda, rs, C.M, 0, o1, d1, flag);
                 if (m < 0) return;
                 if (!Ak.resize(0, Ak.n, m)) { atomicOr(flag, FL_OVERFLOW); return; }
-                put_worms(Ak, 0, 0, o1, d1, m, sp);
+                put_worms<VL>(Ak, 0, 0, o1, d1, m, sp);
                 P.cnt[cuk] = Ak.n;
                 *sk = (uint8_t)sp;
                 continue;
@@ -1076,21 +1077,21 @@ __global__ void __launch_bounds__(64) k_btemporal(Pools P, const int2* __restric
         for (int sp = 0; sp < 2; sp++) W[sp] = fleg(sE, sp ^ q, l1) * fleg(sE, p ^ sp, l2);
         const int sp = choose(W, u53(rs.next()));
         uint64_t d1, d2;
-        const int m1 = sample_worms(sE, lambda, rs, l1, sp ^ q, o1, d1, flag);
+        const int m1 = sample_worms<VL>(sE, lambda, rs, l1, sp ^ q, o1, d1, flag);
         if (m1 < 0) return;
-        const int m2 = sample_worms(sE, lambda, rs, l2, p ^ sp, o2, d2, flag);
+        const int m2 = sample_worms<VL>(sE, lambda, rs, l2, p ^ sp, o2, d2, flag);
         if (m2 < 0) return;
         if (nt == 1) {
             // same array: suffix first, then prefix
             if (!Ak.resize(jl + 1, Ak.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms(Ak, jl + 1, t2, o2, d2, m2, p);
+            put_worms<VL>(Ak, jl + 1, t2, o2, d2, m2, p);
             if (!Ak.resize(0, jv, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms(Ak, 0, C.T[k], o1, d1, m1, sp);
+            put_worms<VL>(Ak, 0, C.T[k], o1, d1, m1, sp);
             P.cnt[cuk] = Ak.n;
         } else {
             if (!Ak.resize(0, jv, m1) || !Bk.resize(jl + 1, Bk.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms(Ak, 0, C.T[k], o1, d1, m1, sp);
-            put_worms(Bk, jl + 1, t2, o2, d2, m2, p);
+            put_worms<VL>(Ak, 0, C.T[k], o1, d1, m1, sp);
+            put_worms<VL>(Bk, jl + 1, t2, o2, d2, m2, p);
             P.cnt[cuk] = Ak.n;
             P.cnt[cukp] = Bk.n;
         }
@@ -1238,12 +1239,14 @@ PMWA_DEV void rebuild_copy(const uint2* A, int n, const int* pv, const int* nv, 
     }
 }
 
-// dynamic LDS: the F table (1024 doubles), then (cap = event capacity)
+// dynamic LDS (cap = event capacity):
 //   A, B, A2, B2           4 x cap uint2
 //   pvA nvA ordA posA, the same for B      8 x cap int
 //   VA, VB                  2 x cap int
 //   VV                      cap BsVert
-//   one NWL-entry column of worm offsets per lane
+//   a pool of RW_POOL worm offsets (the lanes' offsets placed by a prefix
+//   sum of their counts, in rounds if they need more)
+// The expm1 table is read from global memory (it stays in L2).
 __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict__ blk, int d)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1263,8 +1266,8 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     site_split(C, a, dspa, sla);
     site_split(C, c, dspc, slc);
     const int cap = C.cap;
-    double* sE = reinterpret_cast<double*>(smem);
-    uint2* A = reinterpret_cast<uint2*>(smem + 1024 * sizeof(double));
+    const double* sE = C.F;
+    uint2* A = reinterpret_cast<uint2*>(smem);
     uint2* B = A + cap;
     uint2* A2 = B + cap;
     uint2* B2 = A2 + cap;
@@ -1279,7 +1282,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     int* VA = posB + cap;
     int* VB = VA + cap;
     BsVert* VV = reinterpret_cast<BsVert*>(VB + cap);
-    int32_t* off = reinterpret_cast<int32_t*>(VV + cap) + lane;
+    int32_t* pool = reinterpret_cast<int32_t*>(VV + cap);
 
     const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
     const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
@@ -1289,7 +1292,6 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
         const uint2* GB = P.ev + ev_base(C, k, dspc, slc);
         for (int j = lane; j < na; j += 64) A[j] = GA[(long long)j * C.nloc];
         for (int j = lane; j < nb; j += 64) B[j] = GB[(long long)j * C.nloc];
-        for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
     }
     __syncthreads();
     const int nva = bond_vertices(A, na, (uint32_t)d, VA, ordA);
@@ -1414,8 +1416,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
                 Stream rs;
                 rs.init(C, sweep, RNG_BSL + (uint32_t)g, unit);
                 rs.w = (uint32_t)v << 17;
-                uint64_t dirs;
-                n = sample_worms(sE, lambda, rs, (long long)Vv.l[g], sig, off, dirs, flag);
+                n = worm_count(sE, lambda, rs, (long long)Vv.l[g], sig, flag);
                 if (n < 0) n = 0;
             }
             VV[v].cnt[g] = n;
@@ -1432,10 +1433,18 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     rebuild_copy(B, nb, pvB, nvB, ordB, VV, (uint32_t)(d + 2), 1, posB, B2);
     for (int w0 = 0; w0 < 4 * nbv; w0 += 64) {
         const int uvg = w0 + lane;
-        if (uvg < 4 * nbv) {
-            const int v = uvg >> 2, g = uvg & 3;
-            const BsVert& Vv = VV[v];
-            if (Vv.cnt[g] > 0) {
+        int n = 0;
+        if (uvg < 4 * nbv) n = VV[uvg >> 2].cnt[uvg & 3];
+        // offsets through the pool; the first pending lane always fits
+        // (n <= NWL < RW_POOL), so every round makes progress
+        const int wst = wave_incl_sum(n) - n;
+        bool todo = n > 0;
+        for (unsigned long long pend = __ballot(todo); pend; pend = __ballot(todo)) {
+            const int first = __ffsll((long long)pend) - 1;
+            const int pb = __shfl(wst, first, 64);
+            if (todo && wst + n <= pb + RW_POOL) {
+                const int v = uvg >> 2, g = uvg & 3;
+                const BsVert& Vv = VV[v];
                 const int S = (int)Vv.S, p1 = (int)(Vv.p12 & 1u), p2 = (int)(Vv.p12 >> 1);
                 const int s1 = S & 1, s2 = (S >> 1) & 1, s1p = (S >> 2) & 1, s2p = S >> 3;
                 const int q1 = (int)((Vv.fl >> 2) & 1u), q2 = (int)((Vv.fl >> 3) & 1u);
@@ -1449,16 +1458,22 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
                 else if (g == 2) at = posA[VA[v]] + 1;
                 else at = posB[VB[v]] + 1;
                 uint2* O = (g == 0 || g == 2) ? A2 : B2;
+                // the count words again, then the slots (same stream)
                 Stream rs;
                 rs.init(C, sweep, RNG_BSL + (uint32_t)g, unit);
                 rs.w = (uint32_t)v << 17;
+                (void)worm_count(sE, lambda, rs, (long long)Vv.l[g], sig, flag);
+                int32_t* o = pool + (wst - pb);
                 uint64_t dirs;
-                const int n = sample_worms(sE, lambda, rs, (long long)Vv.l[g], sig, off, dirs, flag);
-                for (int w = 0; w < n; w++) {
-                    const uint32_t occ = (uint32_t)((start_occ + w + 1) & 1);
-                    O[at + w] = make_uint2((uint32_t)(base + off[w * 64]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (occ << 3));
+                if (worm_slots<1>(rs, (long long)Vv.l[g], n, o, dirs, flag)) {
+                    for (int w = 0; w < n; w++) {
+                        const uint32_t occ = (uint32_t)((start_occ + w + 1) & 1);
+                        O[at + w] = make_uint2((uint32_t)(base + o[w]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (occ << 3));
+                    }
                 }
+                todo = false;
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();
