@@ -118,8 +118,10 @@ PMWA_DEV void philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
 {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, x0), lo0 = 0xD2511F53u * x0;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, x2), lo1 = 0xCD9E8D57u * x2;
+        // one 32x32 -> 64-bit product each (a single multiply-add instruction)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0, p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
         x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
         k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
