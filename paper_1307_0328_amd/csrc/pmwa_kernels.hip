@@ -571,11 +571,12 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         // ---- the decision on the window's starting state: enter test, exit
         //      leg and landing slot (stream words 3s, 3s+1, 3s+2)
         const uint32_t myc = cur + 3u * (uint32_t)lane;
+        const uint64_t wd0 = ring[myc & 511u], wd1 = ring[(myc + 1u) & 511u], wd2 = ring[(myc + 2u) & 511u];
         bool moved = false, above = false;
         uint32_t Pn = 0, Nn = 0, fv = 0, newup = 0, fx_now = fx;
         int32_t ntick = 0;
         if (act && !blocked) {
-            const uint32_t r = below32(ring[myc & 511u], (uint32_t)Li);
+            const uint32_t r = below32(wd0, (uint32_t)Li);
             moved = (int32_t)r < Lmin;
             if (moved) {
                 // vertex roots with the worm in place
@@ -585,12 +586,15 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
                 const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
                                  : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
                 const int S0 = S ^ (1 << i);
-                // u53(word) < P  <=>  (word >> 11) < ceil(P 2^53), exactly
-                const uint64_t w53 = ring[(myc + 1u) & 511u] >> 11;
+                // u53(word) < P  <=>  (word >> 11) < ceil(P 2^53), exactly; the
+                // cumulative thresholds do not decrease, so the exit leg (the
+                // first j with word < row[j]) is the number at or below the word
+                const uint64_t w53 = wd1 >> 11;
                 const uint64_t* row = sthr + S0 * 16 + i * 4;
-                const int j = w53 < row[0] ? 0 : w53 < row[1] ? 1 : w53 < row[2] ? 2 : 3;
+                const uint64_t t0 = row[0], t1 = row[1], t2 = row[2];
+                const int j = (int)(w53 >= t0) + (int)(w53 >= t1) + (int)(w53 >= t2);
                 const int32_t Lj = j == 0 ? L0 : j == 1 ? L1 : j == 2 ? L2 : L3;
-                const uint32_t r2 = below32(ring[(myc + 2u) & 511u], (uint32_t)Lj);
+                const uint32_t r2 = below32(wd2, (uint32_t)Lj);
                 // leave leg i: above the end on x, that segment takes the worm's state
                 fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
                 const bool on_x = ((j & 1) != 0) != xa;
