@@ -538,14 +538,16 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             up = (fw & F_DIRUP) != 0;
             x = up ? nn_ : pw;
             wf = up ? pw : nn_;
+            // x and wf are nodes (sentinels included), so their fields are
+            // read in one round; y and xf exist only past a vertex end
             fx = A.fl[x];
+            t = A.tick[x];
+            y = A.aux[x];
+            xf = up ? A.nxt[x] : A.prv[x];
+            t_wf = A.tick[wf];
+            f_wf = A.fl[wf];
             blocked = (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) != 0;
             if (!blocked) {
-                t = A.tick[x];
-                y = A.aux[x];
-                xf = up ? A.nxt[x] : A.prv[x];
-                t_wf = A.tick[wf];
-                f_wf = A.fl[wf];
                 fy = A.fl[y];
                 yp = A.prv[y];
                 yn = A.nxt[y];
