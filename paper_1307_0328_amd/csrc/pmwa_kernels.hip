@@ -703,29 +703,36 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     Idx* vnode = reinterpret_cast<Idx*>(vtab + 4 * nloc);
 
     // 1. nodes from the events (loads of consecutive sites are adjacent in
-    //    HBM), the sentinels, and the vertex count per direction
+    //    HBM), the sentinels, and the vertex count per direction; vertices
+    //    of bonds that leave the domain are marked as boundary vertices (a
+    //    worm bounces off them)
+    const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
     for (int s = lane; s < nloc; s += 64) {
         const int o = off[s], n = cnt[s];
+        const int lx = s % ex, ly = s / ex;
+        // bit vd set: the bond in direction vd leaves the domain
+        const uint32_t crm = ((C.dom_x > 1 && lx == ex - 1) ? 1u : 0u) | ((C.dom_y > 1 && ly == ey - 1) ? 2u : 0u) |
+                             ((C.dom_x > 1 && lx == 0) ? 4u : 0u) | ((C.dom_y > 1 && ly == 0) ? 8u : 0u);
         const uint2* E = P.ev + ev_base(C, k, dsp, s);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-        for (int j0 = 0; j0 < n; j0 += 8) {
-            uint2 e[8];
+        for (int j0 = 0; j0 < n; j0 += 16) {
+            uint2 e[16];
 #pragma unroll
-            for (int u = 0; u < 8; u++)
+            for (int u = 0; u < 16; u++)
                 if (j0 + u < n) e[u] = E[(long long)(j0 + u) * nloc];
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
+            for (int u = 0; u < 16; u++) {
                 const int j = j0 + u;
                 if (j < n) {
                     const uint32_t idx = (uint32_t)(o + j);
                     const uint32_t f = e[u].y & 15u;
+                    const uint32_t vd = (f >> 1) & 3u;
+                    const bool v = (f & F_WORM) == 0u;
                     A.tick[idx] = (int32_t)e[u].x;
-                    A.fl[idx] = (uint8_t)f;
+                    A.fl[idx] = (uint8_t)(f | ((v && ((crm >> vd) & 1u)) ? F_CROSS : 0u));
                     A.prv[idx] = (Idx)(j > 0 ? idx - 1u : BOT + (uint32_t)s);
                     A.nxt[idx] = (Idx)(j + 1 < n ? idx + 1u : TOP + (uint32_t)s);
                     A.aux[idx] = NIL;
-                    const uint32_t vd = (f >> 1) & 3u;
-                    const bool v = (f & F_WORM) == 0u;
                     c0 += v && vd == 0u;
                     c1 += v && vd == 1u;
                     c2 += v && vd == 2u;
@@ -738,12 +745,12 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         vtab[4 * s + 2] = (uint16_t)(c0 + c1 + c2);
         vtab[4 * s + 3] = (uint16_t)(c0 + c1 + c2 + c3);
         const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
-        A.tick[BOT + s] = C.T[k];
+        A.tick[BOT + s] = Tk;
         A.fl[BOT + s] = (uint8_t)(F_SBOT | (bsv ? F_UP : 0u));
         A.nxt[BOT + s] = (Idx)(n ? (uint32_t)o : TOP + s);
         A.prv[BOT + s] = NIL;
         A.aux[BOT + s] = NIL;
-        A.tick[TOP + s] = C.T[k + 1];
+        A.tick[TOP + s] = Tk1;
         A.fl[TOP + s] = (uint8_t)F_STOP;
         A.prv[TOP + s] = (Idx)(n ? (uint32_t)(o + n - 1) : BOT + s);
         A.nxt[TOP + s] = NIL;
@@ -751,7 +758,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     }
     __syncthreads();
     // 2. vertex nodes by (site, direction, rank), and the worm list in
-    //    (site, slot) order = node order
+    //    (site, slot) order = node order; the flags are read in batches and
+    //    every entry is written with predication
     int nw = 0;
     for (int base = 0; base < nloc; base += 64) {
         const int s = base + lane;
@@ -762,66 +770,68 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             const int o = off[s], n = cnt[s];
             int r0 = 0, r1 = (int)vtab[4 * s], r2 = (int)vtab[4 * s + 1], r3 = (int)vtab[4 * s + 2];
             int rw = wpos;
-            for (int j = 0; j < n; j++) {
-                const uint32_t idx = (uint32_t)(o + j);
-                const uint32_t f = A.fl[idx];
-                if (f & F_WORM) {
-                    A.wl[rw++] = (Idx)idx;
-                } else {
-                    const uint32_t vd = (f >> 1) & 3u;
-                    const int r = vd == 0u ? r0 : vd == 1u ? r1 : vd == 2u ? r2 : r3;
-                    vnode[o + r] = (Idx)idx;
-                    r0 += vd == 0u;
-                    r1 += vd == 1u;
-                    r2 += vd == 2u;
-                    r3 += vd == 3u;
+            for (int j0 = 0; j0 < n; j0 += 8) {
+                uint32_t fb[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) fb[u] = j0 + u < n ? (uint32_t)A.fl[o + j0 + u] : 0u;
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    if (j0 + u < n) {
+                        const uint32_t idx = (uint32_t)(o + j0 + u);
+                        const uint32_t f = fb[u];
+                        const uint32_t vd = (f >> 1) & 3u;
+                        if (f & F_WORM) {
+                            A.wl[rw++] = (Idx)idx;
+                        } else {
+                            const int r = vd == 0u ? r0 : vd == 1u ? r1 : vd == 2u ? r2 : r3;
+                            vnode[o + r] = (Idx)idx;
+                            r0 += vd == 0u;
+                            r1 += vd == 1u;
+                            r2 += vd == 2u;
+                            r3 += vd == 3u;
+                        }
+                    }
                 }
             }
         }
         nw += tot;
     }
     __syncthreads();
-    // 3. partner ends of vertices; bonds leaving the domain are boundary
-    //    vertices (a worm bounces off them)
+    // 3. partner ends of vertices: per site and inner direction, the r-th
+    //    vertex of direction d is matched with the r-th vertex of direction
+    //    d ^ 2 on the neighbour (independent iterations)
+    bool bad3 = false;
     for (int s = lane; s < nloc; s += 64) {
-        const int o = off[s], n = cnt[s];
+        const int o = off[s];
         const int lx = s % ex, ly = s / ex;
-        const bool cr0 = C.dom_x > 1 && lx == ex - 1, cr2 = C.dom_x > 1 && lx == 0;
-        const bool cr1 = C.dom_y > 1 && ly == ey - 1, cr3 = C.dom_y > 1 && ly == 0;
-        const int n0 = lx == ex - 1 ? s - (ex - 1) : s + 1;
-        const int n2 = lx == 0 ? s + (ex - 1) : s - 1;
-        const int n1 = ly == ey - 1 ? s - (ey - 1) * ex : s + ex;
-        const int n3 = ly == 0 ? s + (ey - 1) * ex : s - ex;
-        // rank slots of the partner direction on each neighbour: [first, end)
-        const int b0 = off[n0] + (int)vtab[4 * n0 + 1], e0 = off[n0] + (int)vtab[4 * n0 + 2];
-        const int b1 = off[n1] + (int)vtab[4 * n1 + 2], e1 = off[n1] + (int)vtab[4 * n1 + 3];
-        const int b2 = off[n2], e2 = off[n2] + (int)vtab[4 * n2];
-        const int b3 = off[n3] + (int)vtab[4 * n3], e3 = off[n3] + (int)vtab[4 * n3 + 1];
-        int q0 = b0, q1 = b1, q2 = b2, q3 = b3;
-        bool bad = false;
-        for (int j = 0; j < n; j++) {
-            const uint32_t idx = (uint32_t)(o + j);
-            const uint32_t f = A.fl[idx];
-            if (f & F_WORM) continue;
-            const uint32_t vd = (f >> 1) & 3u;
-            const bool cross = vd == 0u ? cr0 : vd == 1u ? cr1 : vd == 2u ? cr2 : cr3;
-            if (cross) { A.fl[idx] = (uint8_t)(f | F_CROSS); continue; }
-            const int q = vd == 0u ? q0 : vd == 1u ? q1 : vd == 2u ? q2 : q3;
-            const int qe = vd == 0u ? e0 : vd == 1u ? e1 : vd == 2u ? e2 : e3;
-            q0 += vd == 0u;
-            q1 += vd == 1u;
-            q2 += vd == 2u;
-            q3 += vd == 3u;
-            uint32_t m = NONE;
-            if (q < qe) {
-                m = (uint32_t)vnode[q];
-                if (A.tick[m] != A.tick[idx]) m = NONE;
+        const int st[5] = {0, (int)vtab[4 * s], (int)vtab[4 * s + 1], (int)vtab[4 * s + 2], (int)vtab[4 * s + 3]};
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            const bool cross = d == 0 ? (C.dom_x > 1 && lx == ex - 1) : d == 1 ? (C.dom_y > 1 && ly == ey - 1)
+                             : d == 2 ? (C.dom_x > 1 && lx == 0) : (C.dom_y > 1 && ly == 0);
+            if (cross) continue;
+            const int nb = d == 0 ? (lx == ex - 1 ? s - (ex - 1) : s + 1)
+                         : d == 1 ? (ly == ey - 1 ? s - (ey - 1) * ex : s + ex)
+                         : d == 2 ? (lx == 0 ? s + (ex - 1) : s - 1)
+                                  : (ly == 0 ? s + (ey - 1) * ex : s - ex);
+            const int pd = d ^ 2;
+            const int nb_lo = pd == 0 ? 0 : (int)vtab[4 * nb + pd - 1];
+            const int nb_hi = (int)vtab[4 * nb + pd];
+            const int nown = st[d + 1] - st[d];
+            bad3 |= nown != nb_hi - nb_lo;
+            const int m_n = nown < nb_hi - nb_lo ? nown : nb_hi - nb_lo;
+            const Idx* own_v = vnode + o + st[d];
+            const Idx* nb_v = vnode + off[nb] + nb_lo;
+#pragma unroll 4
+            for (int r = 0; r < m_n; r++) {
+                const uint32_t idx = (uint32_t)own_v[r];
+                const uint32_t m = (uint32_t)nb_v[r];
+                bad3 |= A.tick[idx] != A.tick[m];
+                A.aux[idx] = (Idx)m;
             }
-            bad |= m == NONE;
-            A.aux[idx] = (Idx)m;
         }
-        if (bad) atomicOr(&P.flags[chain], FL_STATE);
     }
+    if (bad3) atomicOr(&P.flags[chain], FL_STATE);
     __syncthreads();
     if (__any(P.flags[chain] != 0)) return;
 
@@ -841,6 +851,10 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     const int NN = NE + 2 * nloc;
     for (int i = lane; i < NN; i += 64) qint[i] = 0u;
     __syncthreads();
+    // chain fields in registers: the loop's global stores could otherwise
+    // alias them and force reloads
+    const int capc = C.cap;
+    const long long cnt_base = C.cnt_off;
     long long nv = 0, nkink = 0, nwc = 0, occ = 0;
     bool bad = false;
     for (int s = lane; s < nloc; s += 64) {
@@ -849,16 +863,17 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         const int qmax = cnt[s] + 1;
         int nq = 0;
         int stt = (A.fl[BOT + s] >> 3) & 1;
-        long long last = 2LL * C.T[k];
-        int32_t ilo = C.T[k];
+        int32_t lastp = 2 * Tk;                 // positions in half ticks (< 2^31)
+        int32_t ilo = Tk;
         uint32_t par = 0;
         int j = 0;
         uint32_t node = A.nxt[BOT + s];
         int guard = 0;
+        int occs = 0;                          // this site's occupation integral
         for (;;) {
             if (node == TOP + (uint32_t)s) {
-                occ += (long long)stt * (2LL * C.T[k + 1] - last);
-                if (nq < qmax) qi[nq] = ((uint32_t)(C.T[k + 1] - ilo) << 1) | par;
+                occs += stt * (2 * Tk1 - lastp);
+                if (nq < qmax) qi[nq] = ((uint32_t)(Tk1 - ilo) << 1) | par;
                 else bad = true;
                 break;
             }
@@ -866,9 +881,9 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             const uint32_t f = A.fl[node];
             const int32_t tk = A.tick[node];
             const uint32_t nx = A.nxt[node];
-            const long long pos = 2LL * tk + (f & F_WORM);
-            occ += (long long)stt * (pos - last);
-            last = pos;
+            const int32_t pos = 2 * tk + (int32_t)(f & F_WORM);
+            occs += stt * (pos - lastp);
+            lastp = pos;
             if (f & F_WORM) {
                 nwc++;
                 par ^= 1u;
@@ -883,23 +898,27 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                 par = 0u;
             }
             stt = (int)((f >> 3) & 1u);
-            if (j < C.cap) P.ev[ebase + (long long)j * nloc] = make_uint2((uint32_t)tk, f & 15u);
+            if (j < capc) P.ev[ebase + (long long)j * nloc] = make_uint2((uint32_t)tk, f & 15u);
             j++;
             node = nx;
         }
-        if (j > C.cap) bad = true;
-        P.cnt[C.cnt_off + unit_su(C, k, dsp, s)] = j > C.cap ? C.cap : j;
+        occ += occs;
+        if (j > capc) bad = true;
+        P.cnt[cnt_base + unit_su(C, k, dsp, s)] = j > capc ? capc : j;
     }
     if (bad) atomicOr(&P.flags[chain], FL_OVERFLOW);
     __syncthreads();
+    // terms of the improved estimator: l tanh(lambda l) for an even number
+    // of worms in the interval, l / tanh(lambda l) for an odd number (one
+    // division each)
     double qimp = 0.0;
     for (int i = lane; i < NN; i += 64) {
         const uint32_t q = qint[i];
         const long long ell = (long long)(q >> 1);
         if (ell > 0) {
             const double m = em1(sE, ell);
-            const double th = (m * (2.0 + m)) / (2.0 * (1.0 + m) + m * m);
-            qimp += (double)ell * ((q & 1u) ? 1.0 / th : th);
+            const double num = m * (2.0 + m), den = 2.0 * (1.0 + m) + m * m;
+            qimp += (double)ell * ((q & 1u) ? den / num : num / den);
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
