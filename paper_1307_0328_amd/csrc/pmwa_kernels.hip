@@ -869,7 +869,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         int j = 0;
         uint32_t node = A.nxt[BOT + s];
         int guard = 0;
-        int occs = 0;                          // this site's occupation integral
+        // this site's tallies (the occupation integral is below 2^31)
+        int occs = 0, nvs = 0, nks = 0, nws = 0;
         for (;;) {
             if (node == TOP + (uint32_t)s) {
                 occs += stt * (2 * Tk1 - lastp);
@@ -881,28 +882,29 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             const uint32_t f = A.fl[node];
             const int32_t tk = A.tick[node];
             const uint32_t nx = A.nxt[node];
-            const int32_t pos = 2 * tk + (int32_t)(f & F_WORM);
+            const uint32_t isw = f & F_WORM, isv = isw ^ 1u;
+            const int32_t pos = 2 * tk + (int32_t)isw;
             occs += stt * (pos - lastp);
             lastp = pos;
-            if (f & F_WORM) {
-                nwc++;
-                par ^= 1u;
-            } else {
-                if (nq < qmax) qi[nq++] = ((uint32_t)(tk - ilo) << 1) | par;
-                else bad = true;
-                if (((f >> 1) & 3u) < 2) {
-                    nv++;
-                    if ((int)((f >> 3) & 1u) != stt) nkink++;
-                }
-                ilo = tk;
-                par = 0u;
-            }
+            // the interval below a vertex ends here; a worm writes the same
+            // slot, which the next vertex or the top of the slab overwrites
+            qi[nq < qmax ? nq : qmax - 1] = ((uint32_t)(tk - ilo) << 1) | par;
+            nq += (int)isv;
+            nws += (int)isw;
+            const uint32_t own_v = isv & (((f >> 1) & 3u) < 2u ? 1u : 0u);
+            nvs += (int)own_v;
+            nks += (int)(own_v & ((((f >> 3) & 1u) != (uint32_t)stt) ? 1u : 0u));
+            ilo = isv ? tk : ilo;
+            par = isv ? 0u : (par ^ 1u);
             stt = (int)((f >> 3) & 1u);
             if (j < capc) P.ev[ebase + (long long)j * nloc] = make_uint2((uint32_t)tk, f & 15u);
             j++;
             node = nx;
         }
         occ += occs;
+        nv += nvs;
+        nkink += nks;
+        nwc += nws;
         if (j > capc) bad = true;
         P.cnt[cnt_base + unit_su(C, k, dsp, s)] = j > capc ? capc : j;
     }
@@ -910,16 +912,16 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     __syncthreads();
     // terms of the improved estimator: l tanh(lambda l) for an even number
     // of worms in the interval, l / tanh(lambda l) for an odd number (one
-    // division each)
+    // division each; empty slots hold l = 0 and add nothing)
     double qimp = 0.0;
+#pragma unroll 2
     for (int i = lane; i < NN; i += 64) {
         const uint32_t q = qint[i];
         const long long ell = (long long)(q >> 1);
-        if (ell > 0) {
-            const double m = em1(sE, ell);
-            const double num = m * (2.0 + m), den = 2.0 * (1.0 + m) + m * m;
-            qimp += (double)ell * ((q & 1u) ? den / num : num / den);
-        }
+        const double m = em1(sE, ell);
+        const double num = m * (2.0 + m), den = 2.0 * (1.0 + m) + m * m;
+        const double term = (double)ell * ((q & 1u) ? den / num : num / den);
+        qimp += ell > 0 ? term : 0.0;
     }
     for (int o = 32; o > 0; o >>= 1) {
         nv += __shfl_down(nv, o, 64);
