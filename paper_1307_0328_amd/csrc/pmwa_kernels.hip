@@ -478,16 +478,21 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
     return (uint32_t)(hi >> 32);
 }
 
-// Steps 5-6 over windows of consecutive attempts of the serial sequence
-// (cycle-major, worm-list order), at most one attempt per worm in a window.
-// Lane k evaluates attempt s0+k, its whole decision included, on the state
-// at the start of the window.  The first attempt whose read set meets a node
-// an earlier move of the window writes ends the window (owner stamps, LDS
-// atomicMax).  Attempt s
-// draws stream words 3s, 3s+1, 3s+2 (enter test, exit leg, landing slot),
-// used or not.  The surviving moves touch disjoint nodes and are applied
-// together; decisions and the final state equal those of the attempts made
-// one at a time in order.
+// Steps 5-6 over windows of up to 64 consecutive attempts of the serial
+// sequence (cycle-major, worm-list order).  Lane k evaluates attempt s0+k,
+// its whole decision included, on the state at the start of the window.  A
+// worm with fewer than 64 worms in its domain can appear several times in a
+// window: a repeat is evaluated as if its earlier attempts in the window
+// turned the worm round (a turn changes nothing but the worm's direction,
+// which no other attempt reads); had one of them moved the worm, the move
+// wrote the worm's old neighbours, which the repeat reads, so the repeat
+// conflicts.  The first attempt whose read set meets a node an earlier move
+// of the window writes ends the window (owner stamps, LDS atomicMax).
+// Attempt s draws stream words 3s, 3s+1, 3s+2 (enter test, exit leg, landing
+// slot), used or not.  The surviving moves touch disjoint nodes and are
+// applied together, a worm's turns by its last surviving attempt; decisions
+// and the final state equal those of the attempts made one at a time in
+// order.
 //
 // One attempt (Step 5): a worm facing another worm, a temporal boundary or a
 // boundary vertex reverses; facing an interior vertex it enters with
@@ -504,7 +509,12 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
     const int lane = (int)threadIdx.x;
     const long long total = (long long)C.ncycle * nw;
     if (total > 0x50000000LL) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return 0; }
-    const int wmax = nw < 64 ? nw : 64;
+    const int wmax = 64;
+    // lane k holds attempt s0 + k: worm-list position iw0 + (k mod nw), with
+    // k / nw earlier attempts of the same worm in the window
+    const int lm = nw > 0 ? lane % nw : 0;
+    const int rep = nw > 0 ? lane / nw : 0;
+    const int m64 = nw > 0 ? 64 % nw : 0;
     const uint32_t k0 = C.key0, k1 = C.key1, c1 = D, c2 = sweep, c3 = (C.chain_id << 8) | RNG_S;
     uint32_t cur = 0, filled = 0, wid = 0;
     int iw0 = 0;                       // worm-list position of attempt s0
@@ -529,10 +539,10 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         int32_t t = 0, t_wf = 0, t_xf = 0, t_yp = 0, t_yn = 0;
         bool blocked = true, up = false;
         if (act) {
-            int iw = iw0 + lane;
+            int iw = iw0 + lm;
             if (iw >= nw) iw -= nw;
             w = A.wl[iw];
-            fw = A.fl[w];
+            fw = (uint32_t)A.fl[w] ^ ((rep & 1) ? F_DIRUP : 0u);
             pw = A.prv[w];
             nn_ = A.nxt[w];
             up = (fw & F_DIRUP) != 0;
@@ -642,7 +652,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         // ---- apply the surviving attempts (disjoint nodes)
         if (lane < kc) {
             if (!moved) {
-                A.fl[w] = (uint8_t)(fw ^ F_DIRUP);
+                if (lane + nw >= kc) A.fl[w] = (uint8_t)(fw ^ F_DIRUP);   // the worm's last attempt here
             } else {
                 if (!up) A.fl[x] = (uint8_t)fx_now;
                 A.nxt[pw] = (Idx)nn_;
@@ -659,7 +669,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         __syncthreads();
         cur += 3u * (uint32_t)kc;
         s0 += kc;
-        iw0 += kc;
+        iw0 += kc < 64 ? __shfl(lm, kc, 64) : m64;   // (iw0 + kc) mod nw
         if (iw0 >= nw) iw0 -= nw;
         windows++;
     }
