@@ -269,6 +269,28 @@ PMWA_DEV int choose(const double (&W)[N], double u)
     return pick >= 0 ? pick : last;
 }
 
+// Sorts 32 values held in registers ascending (bitonic network; every index
+// is a constant after unrolling, so nothing leaves the registers).
+PMWA_DEV void sort32(int32_t (&c)[32])
+{
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < 32; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t a = c[i], b = c[l];
+                    const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    if ((i & k) == 0) { c[i] = lo; c[l] = hi; }
+                    else { c[i] = hi; c[l] = lo; }
+                }
+            }
+        }
+    }
+}
+
 // Sorts v[0], v[ST], ..., v[ST(n-1)] (one lane's column of an LDS array)
 // ascending; returns true when two entries are equal.
 template <int ST = 64>

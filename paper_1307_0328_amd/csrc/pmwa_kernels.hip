@@ -327,12 +327,37 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         }
         const uint64_t dT = (uint64_t)(Tk1 - Tk);
         // ticks as first drawn; they are the ticks kept unless one repeats
-        // a kink of the bond or another candidate
-        for (int i = 0; i < n; i++) cand[i * VL] = Tk + (int32_t)below(rs.next(), dT);
-        const bool rep = sort_col<VL>(cand, n);
+        // a kink of the bond or another candidate.  Up to 32 candidates are
+        // drawn, sorted (bitonic network) and ranked in registers; the stream
+        // is read in the same order either way (the n tick words, then the
+        // acceptance words of the sorted candidates)
         AccRank AR;
         AR.init(C);
-        if (!rep) tag_ranks(cand, n, rs, AR);
+        bool rep;
+        if (n <= 32) {
+            int32_t c[32];
+#pragma unroll
+            for (int i = 0; i < 32; i++) c[i] = 0x7FFFFFFF;
+#pragma unroll
+            for (int i = 0; i < 32; i++)
+                if (i < n) c[i] = Tk + (int32_t)below(rs.next(), dT);
+            sort32(c);
+            rep = false;
+#pragma unroll
+            for (int i = 0; i + 1 < 32; i++) rep |= (i + 1 < n) && c[i] == c[i + 1];
+            if (!rep) {
+#pragma unroll
+                for (int i = 0; i < 32; i++)
+                    if (i < n) c[i] = (int32_t)((uint32_t)c[i] | (AR.rank(rs.next()) << 29));
+            }
+#pragma unroll
+            for (int i = 0; i < 32; i++)
+                if (i < n) cand[i * VL] = c[i];
+        } else {
+            for (int i = 0; i < n; i++) cand[i * VL] = Tk + (int32_t)below(rs.next(), dT);
+            rep = sort_col<VL>(cand, n);
+            if (!rep) tag_ranks(cand, n, rs, AR);
+        }
         int nout = staged ? bond_walk<true>(C, B, fla, flc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn)
                           : bond_walk<true>(C, B, gla, glc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn);
         if (rep || nout < 0)
