@@ -149,6 +149,94 @@ PMWA_DEV int bond_walk(const ChainDev& C, const BondCtx& B, const Lst& LA, const
     return clash ? -1 : nout;
 }
 
+// bit dir set: the bond of `site` in direction dir orders before bond `bid`
+PMWA_DEV uint32_t bond_before_mask(const ChainDev& C, int site, long long bid)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int dir = 0; dir < 4; dir++) m |= (bond_id(C, site, dir) < bid ? 1u : 0u) << dir;
+    return m;
+}
+
+// bond_walk<true> on flip lists in LDS columns, as a merge on integer keys:
+// key = 4 tick + class, the class being 1 for the candidate, 0 for a vertex
+// whose bond orders before the candidate's bond, 2 for a vertex whose bond
+// orders after it, 3 for a worm (worms sit on the half-tick slot above).  A
+// flip precedes the candidate exactly when its key is smaller.  Flips of the
+// two ends at one position may be taken in either order: the n_a n_c
+// integral gains nothing between them and only flips of end a write output.
+// Each step advances one of the three streams (one LDS read through a
+// selected pointer).  Same result and the same -1 on a clash.
+PMWA_DEV int bond_walk_flips(const BondCtx& B, const uint32_t* __restrict__ FA, int na,
+                             const uint32_t* __restrict__ FC, int nc, uint32_t mask_a, uint32_t mask_c,
+                             uint32_t d, int32_t Tk, int32_t Tk1, const int32_t* cand, int np, uint32_t acc_cnt,
+                             uint32_t* out, int capb, long long& nn)
+{
+    const uint32_t INF = 0xFFFFFFFFu;
+    auto fkey = [](uint32_t r, uint32_t mask) -> uint32_t {
+        const uint32_t w = (r >> 29) & 1u, dir = r >> 30;
+        const uint32_t cls = w ? 3u : (((mask >> dir) & 1u) ? 0u : 2u);
+        return ((r & BV_TICK) << 2) | cls;
+    };
+    int ia = 0, ic = 0, i = 0, nout = 0;
+    uint32_t s_a = (uint32_t)B.sa0, s_c = (uint32_t)B.sc0;
+    bool clash = false;
+    int32_t last = 2 * Tk;                  // positions in half ticks (< 2^31)
+    long long acc = 0;
+    uint32_t ra = na > 0 ? FA[0] : 0u, rc = nc > 0 ? FC[0] : 0u;
+    uint32_t rx = np > 0 ? (uint32_t)cand[0] : 0u;
+    uint32_t ka = na > 0 ? fkey(ra, mask_a) : INF;
+    uint32_t kc = nc > 0 ? fkey(rc, mask_c) : INF;
+    uint32_t kx = np > 0 ? (((rx & BV_TICK) << 2) | 1u) : INF;
+    while ((ka & kc & kx) != INF) {
+        const bool isx = kx < ka && kx < kc;
+        const bool isa = !isx && ka <= kc;
+        if (isx) {
+            const uint32_t tau = rx & BV_TICK, rank = rx >> 29;
+            // the next flip of end a is a kink of this bond on the candidate's tick
+            const bool cl = ka == ((tau << 2) | 2u) && ((ra >> 29) & 1u) == 0u && (ra >> 30) == d;
+            if (cl) {
+                clash = true;
+                kx = INF;
+                continue;
+            }
+            const uint32_t need = (acc_cnt >> (3u * (s_a | (s_c << 1)))) & 7u;
+            if (rank < need) {
+                if (nout < capb) out[(long long)nout * B.st] = tau | (s_a << 30) | (s_c << 31);
+                nout++;
+            }
+            i++;
+            rx = i < np ? (uint32_t)cand[i * VL] : 0u;
+            kx = i < np ? (((rx & BV_TICK) << 2) | 1u) : INF;
+        } else {
+            const uint32_t r = isa ? ra : rc;
+            const int32_t pos = 2 * (int32_t)(r & BV_TICK) + (int32_t)((r >> 29) & 1u);
+            acc += (long long)(int32_t)(s_a & s_c) * (pos - last);
+            last = pos;
+            if (isa) {
+                // a kink of this bond (a vertex of direction d) is kept
+                if (!clash && ((ra >> 29) & 1u) == 0u && (ra >> 30) == d) {
+                    if (nout < capb)
+                        out[(long long)nout * B.st] = (ra & BV_TICK) | BV_KINK | (s_a << 30) | ((s_a ^ 1u) << 31);
+                    nout++;
+                }
+                s_a ^= 1u;
+                ia++;
+                ra = ia < na ? FA[ia * VL] : 0u;
+                ka = ia < na ? fkey(ra, mask_a) : INF;
+            } else {
+                s_c ^= 1u;
+                ic++;
+                rc = ic < nc ? FC[ic * VL] : 0u;
+                kc = ic < nc ? fkey(rc, mask_c) : INF;
+            }
+        }
+    }
+    acc += (long long)(int32_t)(s_a & s_c) * (2 * Tk1 - last);
+    nn += acc;
+    return clash ? -1 : nout;
+}
+
 // Acceptance with probability w_d(state)/rho_max by the word w: u53(w) <
 // acc[s] is the same as (w >> 11) < ceil(acc[s] * 2^53) (exact integers), so
 // a word is summarised by its rank r = number of the four thresholds at or
@@ -358,8 +446,14 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
             rep = sort_col<VL>(cand, n);
             if (!rep) tag_ranks(cand, n, rs, AR);
         }
-        int nout = staged ? bond_walk<true>(C, B, fla, flc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn)
-                          : bond_walk<true>(C, B, gla, glc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn);
+        int nout;
+        if (staged) {
+            const uint32_t mask_a = bond_before_mask(C, B.a, B.bid), mask_c = bond_before_mask(C, B.c, B.bid);
+            nout = bond_walk_flips(B, FA, nfa, FC, nfc, mask_a, mask_c, (uint32_t)d, Tk, Tk1, cand, rep ? 0 : n,
+                                   AR.cnt, out, capb, nn);
+        } else {
+            nout = bond_walk<true>(C, B, gla, glc, Tk, Tk1, cand, rep ? 0 : n, AR.cnt, out, capb, nn);
+        }
         if (rep || nout < 0)
             nout = staged ? vertex_exact(C, B, fla, flc, Tk, Tk1, cand, n, sweep, unit, AR, out, capb, flag)
                           : vertex_exact(C, B, gla, glc, Tk, Tk1, cand, n, sweep, unit, AR, out, capb, flag);
