@@ -189,48 +189,44 @@ PMWA_DEV int bond_walk_flips(const BondCtx& B, const uint32_t* __restrict__ FA, 
     uint32_t kc = nc > 0 ? fkey(rc, mask_c) : INF;
     uint32_t kx = np > 0 ? (((rx & BV_TICK) << 2) | 1u) : INF;
     while ((ka & kc & kx) != INF) {
+        // which stream comes next; every update below is a select, so the
+        // lanes of a wavefront stay together whatever stream each takes
         const bool isx = kx < ka && kx < kc;
         const bool isa = !isx && ka <= kc;
-        if (isx) {
-            const uint32_t tau = rx & BV_TICK, rank = rx >> 29;
-            // the next flip of end a is a kink of this bond on the candidate's tick
-            const bool cl = ka == ((tau << 2) | 2u) && ((ra >> 29) & 1u) == 0u && (ra >> 30) == d;
-            if (cl) {
-                clash = true;
-                kx = INF;
-                continue;
-            }
-            const uint32_t need = (acc_cnt >> (3u * (s_a | (s_c << 1)))) & 7u;
-            if (rank < need) {
-                if (nout < capb) out[(long long)nout * B.st] = tau | (s_a << 30) | (s_c << 31);
-                nout++;
-            }
-            i++;
-            rx = i < np ? (uint32_t)cand[i * VL] : 0u;
-            kx = i < np ? (((rx & BV_TICK) << 2) | 1u) : INF;
-        } else {
-            const uint32_t r = isa ? ra : rc;
-            const int32_t pos = 2 * (int32_t)(r & BV_TICK) + (int32_t)((r >> 29) & 1u);
-            acc += (long long)(int32_t)(s_a & s_c) * (pos - last);
-            last = pos;
-            if (isa) {
-                // a kink of this bond (a vertex of direction d) is kept
-                if (!clash && ((ra >> 29) & 1u) == 0u && (ra >> 30) == d) {
-                    if (nout < capb)
-                        out[(long long)nout * B.st] = (ra & BV_TICK) | BV_KINK | (s_a << 30) | ((s_a ^ 1u) << 31);
-                    nout++;
-                }
-                s_a ^= 1u;
-                ia++;
-                ra = ia < na ? FA[ia * VL] : 0u;
-                ka = ia < na ? fkey(ra, mask_a) : INF;
-            } else {
-                s_c ^= 1u;
-                ic++;
-                rc = ic < nc ? FC[ic * VL] : 0u;
-                kc = ic < nc ? fkey(rc, mask_c) : INF;
-            }
-        }
+        const bool isc = !isx && !isa;
+        const uint32_t tau = rx & BV_TICK, rank = rx >> 29;
+        const bool a_kink = ((ra >> 29) & 1u) == 0u && (ra >> 30) == d;   // a vertex of this bond
+        // a candidate on the tick of the next kink of this bond on end a
+        const bool cl = isx && a_kink && ka == ((tau << 2) | 2u);
+        const uint32_t need = (acc_cnt >> (3u * (s_a | (s_c << 1)))) & 7u;
+        const bool wr = (isx && !cl && rank < need) || (isa && !clash && a_kink);
+        const uint32_t val = isx ? (tau | (s_a << 30) | (s_c << 31))
+                                 : ((ra & BV_TICK) | BV_KINK | (s_a << 30) | ((s_a ^ 1u) << 31));
+        if (wr && nout < capb) out[(long long)nout * B.st] = val;
+        nout += wr ? 1 : 0;
+        // n_a n_c integral up to a flip
+        const uint32_t rf = isa ? ra : rc;
+        const int32_t pos = 2 * (int32_t)(rf & BV_TICK) + (int32_t)((rf >> 29) & 1u);
+        acc += isx ? 0LL : (long long)(int32_t)(s_a & s_c) * (pos - last);
+        last = isx ? last : pos;
+        s_a ^= isa ? 1u : 0u;
+        s_c ^= isc ? 1u : 0u;
+        clash |= cl;
+        i += (isx && !cl) ? 1 : 0;
+        ia += isa ? 1 : 0;
+        ic += isc ? 1 : 0;
+        // next record of the stream that advanced (one LDS read)
+        const int nx = isx ? i : isa ? ia : ic;
+        const int lim = isx ? np : isa ? na : nc;
+        const uint32_t* src = isx ? reinterpret_cast<const uint32_t*>(cand) : isa ? FA : FC;
+        const uint32_t rn = nx < lim ? src[nx * VL] : 0u;
+        const uint32_t kn = nx < lim ? (isx ? (((rn & BV_TICK) << 2) | 1u) : fkey(rn, isa ? mask_a : mask_c)) : INF;
+        rx = isx ? rn : rx;
+        kx = isx ? (cl ? INF : kn) : kx;
+        ra = isa ? rn : ra;
+        ka = isa ? kn : ka;
+        rc = isc ? rn : rc;
+        kc = isc ? kn : kc;
     }
     acc += (long long)(int32_t)(s_a & s_c) * (2 * Tk1 - last);
     nn += acc;
