@@ -648,6 +648,11 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         }
         __syncthreads();
         const bool act = lane < wmax && s0 + lane < total;
+        // the attempt's three stream words, read with the first loads of the
+        // window (the empty asm below consumes them before the decision, so
+        // that they are not deferred behind the evaluation)
+        const uint32_t myc = cur + 3u * (uint32_t)lane;
+        const uint64_t wd0 = ring[myc & 511u], wd1 = ring[(myc + 1u) & 511u], wd2 = ring[(myc + 2u) & 511u];
         // ---- evaluate on the window's starting state
         uint32_t w = 0, fw = 0, pw = 0, nn_ = 0, x = 0, fx = 0, y = 0, xf = 0, wf = 0;
         uint32_t fy = 0, yp = 0, yn = 0, f_wf = 0, f_xf = 0, f_yp = 0;
@@ -697,8 +702,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
         // ---- the decision on the window's starting state: enter test, exit
         //      leg and landing slot (stream words 3s, 3s+1, 3s+2)
-        const uint32_t myc = cur + 3u * (uint32_t)lane;
-        const uint64_t wd0 = ring[myc & 511u], wd1 = ring[(myc + 1u) & 511u], wd2 = ring[(myc + 2u) & 511u];
+        asm volatile("" ::"v"(wd0), "v"(wd1), "v"(wd2));
         bool moved = false, above = false;
         uint32_t Pn = 0, Nn = 0, fv = 0, newup = 0, fx_now = fx;
         int32_t ntick = 0;
