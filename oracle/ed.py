@@ -86,6 +86,31 @@ def thermal_dense(Lx, Ly, beta, t, V, mu, eta):
     return _finish(r, N, V, mu, eta)
 
 
+def green_dense(Lx, Ly, beta, t, V, mu, eta, disps):
+    """Equal-time <(b_i + b_i^+)(b_j + b_j^+)> = <sigma^x_i sigma^x_j>,
+    averaged over sites i with j = i + (rx, ry), for each displacement."""
+    N = Lx * Ly
+    H, _, _, _, _ = hamiltonian_dense(Lx, Ly, t, V, mu, eta)
+    evals, evecs = np.linalg.eigh(H)
+    w = np.exp(-beta * (evals - evals.min()))
+    Z = w.sum()
+    states = np.arange(1 << N, dtype=np.int64)
+    out = []
+    for rx, ry in disps:
+        acc = 0.0
+        for i in range(N):
+            x, y = i % Lx, i // Lx
+            j = ((y + ry) % Ly) * Lx + (x + rx) % Lx
+            if i == j:
+                acc += 1.0
+                continue
+            flipped = states ^ ((1 << i) | (1 << j))
+            dm = (evecs * evecs[flipped, :]).sum(axis=0)
+            acc += float((w * dm).sum() / Z)
+        out.append(acc / N)
+    return np.array(out)
+
+
 def _finish(r, N, V, mu, eta):
     E_eta = r["E_eta_total"] / N
     Q = r["Q"] / N

@@ -93,6 +93,7 @@ def lib():
         L.orc_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_stream_word.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint64]
         L.orc_stream_word.restype = C.c_uint64
+        L.orc_green.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
         _lib = L
     return _lib
 
@@ -232,6 +233,15 @@ class Chain:
 
     def temporal_p0(self, p, q, l1, l2):
         return lib().orc_test_temporal_p0(self.h, p, q, l1, l2)
+
+    def green(self, disps):
+        """Equal-time Green function G(r) of b + b^+ on the current
+        configuration, for each displacement (rx, ry) in `disps`."""
+        d = np.ascontiguousarray(np.asarray(disps, dtype=np.int32).reshape(-1, 2))
+        out = np.zeros(len(d))
+        if lib().orc_green(self.h, d.ctypes.data, len(d), out.ctypes.data) != 0:
+            raise RuntimeError("orc_green failed")
+        return out
 
     def stream_word(self, phase, unit, w):
         return int(lib().orc_stream_word(self.h, phase, unit, w))

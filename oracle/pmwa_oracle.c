@@ -868,6 +868,76 @@ static void measure_site(orc_chain* c, int i)
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Equal-time Green function of Q = b + b^+ (Supplemental S-I, n = 2)  */
+/* ------------------------------------------------------------------ */
+/* rho(X)/eta on the interval holding X: tanh(lambda l) for an even number
+   of worms in it, coth(lambda l) for an odd number (the ratio of the
+   hard-core propagators f split at X; it does not depend on where X lies in
+   the interval).  Intervals are delimited by vertices and the temporal
+   domain boundaries.  gi_t describes one interval: its end tick and g. */
+typedef struct { int32_t end; double g; } gi_t;
+
+/* the interval of `site` in slab k that starts at tick `start`, its events
+   from index *j on (slab events end at hi); *j moves past the vertex that
+   closes it */
+static gi_t green_interval(const orc_chain* c, int site, int k, int hi, int* j, int32_t start)
+{
+    const elist* l = &c->site[site];
+    int par = 0, m = *j;
+    while (m < hi && l->e[m].worm) { par ^= 1; m++; }
+    gi_t r;
+    r.end = (m < hi) ? l->e[m].tick : c->T[k + 1];
+    *j = (m < hi) ? m + 1 : hi;
+    int64_t ell = (int64_t)r.end - start;
+    if (ell > 0) {
+        double th = tanh_ell(c, ell);
+        r.g = par ? 1.0 / th : th;
+    } else {
+        r.g = 0.0;                     /* no worm fits an empty interval */
+    }
+    return r;
+}
+
+/* G(r) = (1/N) sum_i <Q_i Q_{i+r}>, the equal-time correlation averaged
+   over imaginary time: on the current configuration,
+   (1 / (M N)) sum_i sum_k int_slab k g_i(tau) g_{i+r}(tau) dtau, since two
+   different sites never share an interval (the product rule of S-I holds);
+   r = (0, 0) gives 1 (Q_i^2 = 1).  disp holds (rx, ry) pairs. */
+int orc_green(const orc_chain* c, const int32_t* disp, int n, double* out)
+{
+    if (n < 0 || (n > 0 && (!disp || !out))) return ORC_EINVAL;
+    for (int d = 0; d < n; d++) {
+        int rx = ((disp[2 * d] % c->Lx) + c->Lx) % c->Lx;
+        int ry = ((disp[2 * d + 1] % c->Ly) + c->Ly) % c->Ly;
+        if (rx == 0 && ry == 0) { out[d] = 1.0; continue; }
+        double sum = 0.0;
+        for (int i = 0; i < c->N; i++) {
+            int x = i % c->Lx, y = i / c->Lx;
+            int jj = ((y + ry) % c->Ly) * c->Lx + (x + rx) % c->Lx;
+            for (int k = 0; k < c->ntau; k++) {
+                int loA, hiA, loB, hiB;
+                slab_range(c, i, k, &loA, &hiA);
+                slab_range(c, jj, k, &loB, &hiB);
+                int pa = loA, pb = loB;
+                int32_t cur = c->T[k], top = c->T[k + 1];
+                gi_t A = green_interval(c, i, k, hiA, &pa, cur);
+                gi_t B = green_interval(c, jj, k, hiB, &pb, cur);
+                while (cur < top) {
+                    int32_t nxt = A.end < B.end ? A.end : B.end;
+                    sum += (double)(nxt - cur) * A.g * B.g;
+                    cur = nxt;
+                    if (cur >= top) break;
+                    if (A.end == cur) A = green_interval(c, i, k, hiA, &pa, cur);
+                    if (B.end == cur) B = green_interval(c, jj, k, hiB, &pb, cur);
+                }
+            }
+        }
+        out[d] = sum / ((double)c->M * (double)c->N);
+    }
+    return ORC_OK;
+}
+
 static void scatter_phase(orc_chain* c)
 {
     int ndsp = c->p.dom_x * c->p.dom_y;
