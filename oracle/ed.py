@@ -87,26 +87,30 @@ def thermal_dense(Lx, Ly, beta, t, V, mu, eta):
 
 
 def green_dense(Lx, Ly, beta, t, V, mu, eta, disps):
-    """Equal-time <(b_i + b_i^+)(b_j + b_j^+)> = <sigma^x_i sigma^x_j>,
-    averaged over sites i with j = i + (rx, ry), for each displacement."""
+    """<T (b_j + b_j^+)(tau) (b_i + b_i^+)(0)> = Tr(e^{-(beta-tau) H} X_j
+    e^{-tau H} X_i) / Z (X = sigma^x, H = H_eta), averaged over sites i with
+    j = i + (rx, ry), for each displacement (rx, ry) or (rx, ry, tau)."""
     N = Lx * Ly
     H, _, _, _, _ = hamiltonian_dense(Lx, Ly, t, V, mu, eta)
     evals, evecs = np.linalg.eigh(H)
-    w = np.exp(-beta * (evals - evals.min()))
-    Z = w.sum()
+    e = evals - evals.min()
+    Z = np.exp(-beta * e).sum()
     states = np.arange(1 << N, dtype=np.int64)
+    # sigma^x_i in the eigenbasis
+    X = []
+    for i in range(N):
+        X.append(evecs.T @ evecs[states ^ (1 << i), :])
     out = []
-    for rx, ry in disps:
+    for dd in disps:
+        rx, ry = dd[0], dd[1]
+        tau = float(dd[2]) if len(dd) > 2 else 0.0
+        wl = np.exp(-(beta - tau) * e)       # left  factor e^{-(beta - tau) E_m}
+        wr = np.exp(-tau * e)                # right factor e^{-tau E_n}
         acc = 0.0
         for i in range(N):
             x, y = i % Lx, i // Lx
             j = ((y + ry) % Ly) * Lx + (x + rx) % Lx
-            if i == j:
-                acc += 1.0
-                continue
-            flipped = states ^ ((1 << i) | (1 << j))
-            dm = (evecs * evecs[flipped, :]).sum(axis=0)
-            acc += float((w * dm).sum() / Z)
+            acc += float(wl @ (X[j] * X[i].T) @ wr) / Z
         out.append(acc / N)
     return np.array(out)
 

@@ -235,9 +235,10 @@ class Chain:
         return lib().orc_test_temporal_p0(self.h, p, q, l1, l2)
 
     def green(self, disps):
-        """Equal-time Green function G(r) of b + b^+ on the current
-        configuration, for each displacement (rx, ry) in `disps`."""
-        d = np.ascontiguousarray(np.asarray(disps, dtype=np.int32).reshape(-1, 2))
+        """Green function G(r, dt) of b + b^+ on the current configuration,
+        for each displacement (rx, ry) or (rx, ry, dt ticks) in `disps`."""
+        rows = [tuple(int(v) for v in dd) + (0,) * (3 - len(dd)) for dd in disps]
+        d = np.ascontiguousarray(np.array(rows, dtype=np.int64).reshape(-1, 3), dtype=np.int32)
         out = np.zeros(len(d))
         if lib().orc_green(self.h, d.ctypes.data, len(d), out.ctypes.data) != 0:
             raise RuntimeError("orc_green failed")

@@ -869,72 +869,93 @@ static void measure_site(orc_chain* c, int i)
 }
 
 /* ------------------------------------------------------------------ */
-/* Equal-time Green function of Q = b + b^+ (Supplemental S-I, n = 2)  */
+/* Green function of Q = b + b^+ (Supplemental S-I, n = 2)             */
 /* ------------------------------------------------------------------ */
 /* rho(X)/eta on the interval holding X: tanh(lambda l) for an even number
    of worms in it, coth(lambda l) for an odd number (the ratio of the
    hard-core propagators f split at X; it does not depend on where X lies in
    the interval).  Intervals are delimited by vertices and the temporal
-   domain boundaries.  gi_t describes one interval: its end tick and g. */
-typedef struct { int32_t end; double g; } gi_t;
+   domain boundaries.  Two points on different intervals give the product of
+   their ratios (the product rule of S-I).  Two points on the same interval
+   (same site): the split ratio is eta^2 <q|e^{l3 eta Q} Q e^{l2 eta Q} Q
+   e^{l1 eta Q}|p> / <q|e^{l eta Q}|p> = eta^2, because Q commutes with
+   e^{x Q} and Q^2 = 1, so the sample is 1. */
+typedef struct { int32_t lo, hi; double g; } gint_t;
 
-/* the interval of `site` in slab k that starts at tick `start`, its events
-   from index *j on (slab events end at hi); *j moves past the vertex that
-   closes it */
-static gi_t green_interval(const orc_chain* c, int site, int k, int hi, int* j, int32_t start)
+/* the intervals of `site` over [0, M), in time order; returns their count */
+static int green_intervals(const orc_chain* c, int site, gint_t* out)
 {
     const elist* l = &c->site[site];
-    int par = 0, m = *j;
-    while (m < hi && l->e[m].worm) { par ^= 1; m++; }
-    gi_t r;
-    r.end = (m < hi) ? l->e[m].tick : c->T[k + 1];
-    *j = (m < hi) ? m + 1 : hi;
-    int64_t ell = (int64_t)r.end - start;
-    if (ell > 0) {
-        double th = tanh_ell(c, ell);
-        r.g = par ? 1.0 / th : th;
-    } else {
-        r.g = 0.0;                     /* no worm fits an empty interval */
+    int n = 0;
+    for (int k = 0; k < c->ntau; k++) {
+        int lo, hi;
+        slab_range(c, site, k, &lo, &hi);
+        int32_t start = c->T[k];
+        int par = 0;
+        for (int j = lo; j <= hi; j++) {
+            if (j < hi && l->e[j].worm) { par ^= 1; continue; }
+            int32_t end = (j < hi) ? l->e[j].tick : c->T[k + 1];
+            int64_t ell = (int64_t)end - start;
+            if (ell > 0) {
+                double th = tanh_ell(c, ell);
+                out[n].lo = start; out[n].hi = end; out[n].g = par ? 1.0 / th : th;
+                n++;
+            }
+            start = end;
+            par = 0;
+        }
     }
-    return r;
+    return n;
 }
 
-/* G(r) = (1/N) sum_i <Q_i Q_{i+r}>, the equal-time correlation averaged
-   over imaginary time: on the current configuration,
-   (1 / (M N)) sum_i sum_k int_slab k g_i(tau) g_{i+r}(tau) dtau, since two
-   different sites never share an interval (the product rule of S-I holds);
-   r = (0, 0) gives 1 (Q_i^2 = 1).  disp holds (rx, ry) pairs. */
+/* G(r, dt) = (1/N) sum_i <Q_i(tau) Q_{i+r}(tau + dt)>, averaged over tau in
+   [0, beta): on the current configuration,
+   (1 / (M N)) sum_i int_0^M h_i(tau) dtau with h the two-point sample of the
+   points (i, tau) and (i + r, tau + dt mod M).  disp holds (rx, ry, dt)
+   triples; dt in ticks. */
 int orc_green(const orc_chain* c, const int32_t* disp, int n, double* out)
 {
     if (n < 0 || (n > 0 && (!disp || !out))) return ORC_EINVAL;
+    int cap = 0;
+    for (int i = 0; i < c->N; i++) if (c->site[i].n + c->ntau > cap) cap = c->site[i].n + c->ntau;
+    gint_t* A = (gint_t*)malloc(sizeof(gint_t) * (size_t)(cap + 1));
+    gint_t* B = (gint_t*)malloc(sizeof(gint_t) * (size_t)(cap + 1));
+    if (!A || !B) { free(A); free(B); return ORC_ENOMEM; }
     for (int d = 0; d < n; d++) {
-        int rx = ((disp[2 * d] % c->Lx) + c->Lx) % c->Lx;
-        int ry = ((disp[2 * d + 1] % c->Ly) + c->Ly) % c->Ly;
-        if (rx == 0 && ry == 0) { out[d] = 1.0; continue; }
+        int rx = ((disp[3 * d] % c->Lx) + c->Lx) % c->Lx;
+        int ry = ((disp[3 * d + 1] % c->Ly) + c->Ly) % c->Ly;
+        int32_t dt = (int32_t)((((int64_t)disp[3 * d + 2] % c->M) + c->M) % c->M);
         double sum = 0.0;
         for (int i = 0; i < c->N; i++) {
             int x = i % c->Lx, y = i / c->Lx;
             int jj = ((y + ry) % c->Ly) * c->Lx + (x + rx) % c->Lx;
-            for (int k = 0; k < c->ntau; k++) {
-                int loA, hiA, loB, hiB;
-                slab_range(c, i, k, &loA, &hiA);
-                slab_range(c, jj, k, &loB, &hiB);
-                int pa = loA, pb = loB;
-                int32_t cur = c->T[k], top = c->T[k + 1];
-                gi_t A = green_interval(c, i, k, hiA, &pa, cur);
-                gi_t B = green_interval(c, jj, k, hiB, &pb, cur);
-                while (cur < top) {
-                    int32_t nxt = A.end < B.end ? A.end : B.end;
-                    sum += (double)(nxt - cur) * A.g * B.g;
-                    cur = nxt;
-                    if (cur >= top) break;
-                    if (A.end == cur) A = green_interval(c, i, k, hiA, &pa, cur);
-                    if (B.end == cur) B = green_interval(c, jj, k, hiB, &pb, cur);
+            int na = green_intervals(c, i, A);
+            int nb = green_intervals(c, jj, B);
+            /* b: the interval of jj holding time dt (the partner of tau = 0) */
+            int b = 0;
+            while (B[b].hi <= dt) b++;
+            int32_t pos = dt;              /* partner time of tau */
+            int32_t tau = 0;
+            int a = 0;
+            while (tau < c->M && a < na) {
+                int32_t len = A[a].hi - tau;
+                int32_t lenb = B[b].hi - pos;
+                if (lenb < len) len = lenb;
+                double h = (jj == i && a == b) ? 1.0 : A[a].g * B[b].g;
+                sum += (double)len * h;
+                tau += len;
+                pos += len;
+                if (tau == A[a].hi) a++;
+                if (pos == B[b].hi) {
+                    b++;
+                    if (b == nb) { b = 0; pos = 0; }
                 }
             }
         }
         out[d] = sum / ((double)c->M * (double)c->N);
     }
+    free(A);
+    free(B);
     return ORC_OK;
 }
 

@@ -103,8 +103,9 @@ int  orc_get_scatter_table(const orc_chain* c, double* tab /*16*4*4*/,
 double orc_vertex_weight(const orc_chain* c, int S);
 double orc_fleg(const orc_chain* c, int sigma, int64_t ell);
 double orc_tanh_ell(const orc_chain* c, int64_t ell);
-/* equal-time Green function of b + b^+ on the current configuration for the
-   n displacements (rx, ry) in disp (Supplemental S-I, n = 2); see the source */
+/* Green function of b + b^+ on the current configuration for the n
+   displacements (rx, ry, dt ticks) in disp (Supplemental S-I, n = 2); see the
+   source */
 int  orc_green(const orc_chain* c, const int32_t* disp, int n, double* out);
 int  orc_poisson_table(const orc_chain* c, int k, double* cdf, int cap);
 

@@ -1,13 +1,15 @@
-"""Pins of the oracle's equal-time Green function of Q = b + b^+
-(Supplemental S-I, the n = 2 product rule; intervals of different sites are
-always distinct, so the product of the one-point ratios rho/eta applies):
+"""Pins of the oracle's Green function G(r, dt) of Q = b + b^+
+(Supplemental S-I, n = 2): points on different intervals give the product
+of the one-point ratios rho/eta; two points on one interval give 1 (Q
+commutes with the interval propagator and Q^2 = 1):
 
-- r = (0, 0) is exactly 1 (Q_i^2 = 1);
+- r = (0, 0), dt = 0 is exactly 1;
 - on a given configuration the oracle's interval merge equals a brute-force
-  evaluation of the ratios on every tick cell, written independently here;
+  evaluation on every tick cell, written independently here;
 - with t = 0, V = 0 the sites decouple and G(r != 0) = <Q>^2 from the
   single-site closed form;
-- thermal averages agree with exact diagonalisation of H_eta.
+- thermal averages agree with exact diagonalisation of H_eta, at equal and
+  at different imaginary times.
 """
 import math
 
@@ -37,9 +39,9 @@ def sample(cfg, sweeps, therm=1000, seed=5):
 
 
 def brute_force(st, Lx, Ly, T, lam, disps):
-    """Ratio per tick cell [t, t+1) of every site (vertices sit on integer
-    ticks, worms on half ticks, so each cell lies in one interval), then the
-    time and site average of the products."""
+    """Ratio and interval id per tick cell [t, t+1) of every site (vertices
+    sit on integer ticks, worms on half ticks, so each cell lies in one
+    interval), then the time and site average of the two-point samples."""
     N = Lx * Ly
     ntau = len(T) - 1
     M = T[-1]
@@ -47,6 +49,7 @@ def brute_force(st, Lx, Ly, T, lam, disps):
     tk = np.asarray(st["ticks"])
     inf = np.asarray(st["infos"])
     g = np.zeros((N, M))
+    iid = np.full((N, M), -1, dtype=np.int64)
     o = 0
     for k in range(ntau):
         for s in range(N):
@@ -63,17 +66,23 @@ def brute_force(st, Lx, Ly, T, lam, disps):
                 if ell > 0:
                     th = math.tanh(lam * ell)
                     g[s, start:t] = 1.0 / th if par else th
+                    iid[s, start:t] = start
                 start, par = t, 0
+    assert (iid >= 0).all()
     out = []
-    for rx, ry in disps:
-        if rx % Lx == 0 and ry % Ly == 0:
-            out.append(1.0)
-            continue
+    cells = np.arange(M)
+    for dd in disps:
+        rx, ry = dd[0], dd[1]
+        dt = dd[2] % M if len(dd) > 2 else 0
         acc = 0.0
         for s in range(N):
             x, y = s % Lx, s // Lx
             j = ((y + ry) % Ly) * Lx + (x + rx) % Lx
-            acc += float(np.dot(g[s], g[j]))
+            pj = (cells + dt) % M
+            h = g[s] * g[j, pj]
+            if j == s:
+                h = np.where(iid[s] == iid[j, pj], 1.0, h)
+            acc += float(h.sum())
         out.append(acc / (M * N))
     return np.array(out)
 
@@ -81,7 +90,7 @@ def brute_force(st, Lx, Ly, T, lam, disps):
 def test_zero_displacement_is_one():
     ch = O.Chain(Lx=3, Ly=3, beta=2.0, V=1.0, mu=0.5, eta=0.2, seed=1)
     ch.sweep(20)
-    assert ch.green([(0, 0), (3, -3)]).tolist() == [1.0, 1.0]
+    assert ch.green([(0, 0), (3, -3), (0, 0, 0), (3, 0, 1 << 24)]).tolist() == [1.0] * 4
 
 
 @pytest.mark.parametrize("cfg", [
@@ -90,7 +99,9 @@ def test_zero_displacement_is_one():
 ])
 def test_merge_equals_brute_force(cfg):
     ch = O.Chain(seed=7, **cfg)
-    disps = [(0, 0), (1, 0), (0, 1), (2, 1), (-1, 3)]
+    M = 1 << cfg["ticks_log2"]
+    disps = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (2, 1, 0), (-1, 3, 0),
+             (0, 0, 1), (0, 0, 37), (0, 0, M // 2), (0, 0, M - 1), (1, 0, 5), (1, 1, M // 3 + 2), (2, -1, -7)]
     for sweeps in (3, 17):
         ch.sweep(sweeps)
         d = ch.derived()
@@ -119,3 +130,21 @@ def test_thermal_average_matches_ed(cfg):
     ref = ed.green_dense(cfg["Lx"], cfg["Ly"], cfg["beta"], cfg["t"], cfg["V"], cfg["mu"], cfg["eta"], DISPS)
     for i in range(len(DISPS)):
         assert abs(m[i] - ref[i]) < 4.5 * e[i] + 1e-12, (DISPS[i], m[i], e[i], ref[i])
+
+
+def test_imaginary_time_correlation_matches_ed():
+    """Same site and nearest neighbour at imaginary-time separations beta/8,
+    beta/4 and beta/2 (the same-interval samples matter for the site itself)."""
+    cfg = dict(Lx=3, Ly=3, beta=2.0, t=1.0, V=1.0, mu=0.5, eta=0.2, dom_tau=2, ticks_log2=20)
+    M = 1 << 20
+    disps = [(0, 0, M // 8), (0, 0, M // 4), (0, 0, M // 2), (1, 0, M // 4), (0, 1, M // 2)]
+    ch = O.Chain(seed=9, **cfg)
+    ch.sweep(1000)
+    G = []
+    for _ in range(20000):
+        ch.sweep(1)
+        G.append(ch.green(disps))
+    m, e = binned(np.array(G))
+    ref = ed.green_dense(3, 3, 2.0, 1.0, 1.0, 0.5, 0.2, [(d[0], d[1], d[2] * 2.0 / M) for d in disps])
+    for i in range(len(disps)):
+        assert abs(m[i] - ref[i]) < 4.5 * e[i], (disps[i], m[i], e[i], ref[i])
