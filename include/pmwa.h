@@ -182,6 +182,25 @@ int pmwa_slot_progress(pmwa_t* h, int slot, int64_t* sweeps_done);
    attempts in one domain.  n >= 4. */
 int pmwa_diag(pmwa_t* h, int chain, int64_t* out, int n);
 
+/* Green function of Q_i = b_i + b_i^+ (Supplemental S-I, the product rule
+   for n = 2): for each of the n displacements (rx, ry, dt) in disp[3q],
+   disp[3q+1], disp[3q+2] (any integers, taken modulo the lattice and, for
+   the imaginary-time shift dt in ticks, modulo M = 2^ticks_log2),
+   out[q] = G(r, dt) = (1/N) sum_i <Q_i(tau) Q_{i+r}(tau + dt)>, averaged over
+   tau in [0, beta), on the CURRENT configuration of `chain` (one sample;
+   average over sweeps for the thermal value).  The one-point ratio rho/eta
+   on an interval between vertices or temporal domain boundaries is
+   tanh(lambda l) for an even number of worms in it and coth(lambda l) for
+   an odd number.  Two points on different intervals give the product of
+   their ratios; two points on one interval give 1 (Q commutes with the
+   interval propagator and Q^2 = 1); (0, 0, 0) gives 1.  disp and out are
+   host arrays of 3n and n entries, 1 <= n <= PMWA_GREEN_MAX.  Synchronises
+   the handle's stream; the first call allocates a small device workspace
+   that the handle keeps.  PMWA_EINVAL on bad arguments, PMWA_ESTATE or
+   PMWA_EOVERFLOW if the chain is flagged. */
+#define PMWA_GREEN_MAX 64
+int pmwa_green(pmwa_t* h, int chain, const int32_t* disp, int n, double* out);
+
 /* Events per (site, slab) a chain would be given by default. */
 int pmwa_default_event_cap(const pmwa_params* p);
 

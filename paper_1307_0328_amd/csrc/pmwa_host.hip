@@ -26,6 +26,8 @@ __global__ void k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
 __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
+__global__ void k_green(Pools P, int chain, const int4* __restrict__ disp, int nd, int nchunk,
+                        double* __restrict__ part);
 __global__ void k_bspatial(Pools P, const int2* __restrict__ blk, int d);
 __global__ void k_finish(Pools P);
 }  // namespace pmwa
@@ -95,6 +97,10 @@ struct pmwa_handle {
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_phase;          // phase of the pair (2i, 2i+1)
     size_t ev_used = 0;
+    // Green-function measurement: displacements and per-block partials
+    int4* d_gdisp = nullptr;
+    double* d_gpart = nullptr;
+    size_t gpart_cap = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -431,7 +437,7 @@ void pmwa_destroy(pmwa_t* h)
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
                     h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->d_blk_v, h->d_blk_r,
-                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw};
+                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw, h->d_gdisp, h->d_gpart};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete h;
@@ -864,6 +870,62 @@ int pmwa_diag(pmwa_t* h, int chain, int64_t* out, int n)
         amax = std::max<int64_t>(amax, x.nw * (int64_t)hc.d.ncycle);
     }
     out[0] = wsum; out[1] = wmax; out[2] = att; out[3] = amax;
+    return PMWA_OK;
+}
+
+int pmwa_green(pmwa_t* h, int chain, const int32_t* disp, int n, double* out)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size() || n < 1 || n > PMWA_GREEN_MAX || !disp || !out)
+        return PMWA_EINVAL;
+    const ChainDev& d = h->ch[chain].d;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    unsigned int fl = 0;
+    HIPCHK(hipMemcpy(&fl, h->P.flags + chain, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl) return (fl & 1u) ? PMWA_EOVERFLOW : PMWA_ESTATE;
+    // displacements modulo the lattice and beta; (0, 0, 0) gives 1 without a
+    // launch
+    std::vector<int4> dv;
+    std::vector<int> slot(n, -1);
+    for (int q = 0; q < n; q++) {
+        const int rx = ((disp[3 * q] % d.Lx) + d.Lx) % d.Lx, ry = ((disp[3 * q + 1] % d.Ly) + d.Ly) % d.Ly;
+        const int dt = (int)((((int64_t)disp[3 * q + 2] % d.M) + d.M) % d.M);
+        if (rx == 0 && ry == 0 && dt == 0) continue;
+        slot[q] = (int)dv.size();
+        dv.push_back(make_int4(rx, ry, dt, 0));
+    }
+    std::vector<double> part;
+    const int nd = (int)dv.size();
+    const int nchunk = (d.N + 63) / 64;
+    const size_t nblk = (size_t)d.ntau * nd * nchunk;
+    if (nd > 0) {
+        if (!h->d_gdisp && hipMalloc(&h->d_gdisp, PMWA_GREEN_MAX * sizeof(int4)) != hipSuccess) {
+            h->d_gdisp = nullptr;
+            return PMWA_ENOMEM;
+        }
+        if (nblk > h->gpart_cap) {
+            if (h->d_gpart) (void)hipFree(h->d_gpart);
+            h->d_gpart = nullptr;
+            h->gpart_cap = 0;
+            if (hipMalloc(&h->d_gpart, nblk * sizeof(double)) != hipSuccess) return PMWA_ENOMEM;
+            h->gpart_cap = nblk;
+        }
+        HIPCHK(hipMemcpyAsync(h->d_gdisp, dv.data(), nd * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(k_green, dim3((unsigned)nblk), dim3(64), 0, h->stream, h->P, chain, h->d_gdisp, nd, nchunk,
+                           h->d_gpart);
+        HIPCHK(hipGetLastError());
+        part.resize(nblk);
+        HIPCHK(hipMemcpyAsync(part.data(), h->d_gpart, nblk * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    // fixed summation order: slab, then block of sites
+    const double norm = (double)d.M * (double)d.N;
+    for (int q = 0; q < n; q++) {
+        if (slot[q] < 0) { out[q] = 1.0; continue; }
+        double sum = 0.0;
+        for (int k = 0; k < d.ntau; k++)
+            for (int c = 0; c < nchunk; c++) sum += part[((size_t)k * nd + slot[q]) * nchunk + c];
+        out[q] = sum / norm;
+    }
     return PMWA_OK;
 }
 

@@ -1794,6 +1794,143 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
 }
 
 // ===========================================================================
+// Green function of Q = b + b^+ on the current configuration (Supplemental
+// S-I, n = 2): G(r, dt) = (1/N) sum_i <Q_i(tau) Q_{i+r}(tau + dt)>, averaged
+// over tau.  The one-point ratio rho/eta on an interval (delimited by
+// vertices and temporal domain boundaries) is tanh(lambda l) for an even
+// number of worms in it and coth(lambda l) for an odd number; two points on
+// different intervals give the product of their ratios, two points on one
+// interval give 1 (Q commutes with the interval propagator, Q^2 = 1).
+// One lane per (site i, slab k, displacement): the lane merges the
+// intervals of site i in slab k with those of site i + r from the partner
+// time T_k + dt on (across slabs, wrapping at beta).  Block
+// (k * nd + d) * nchunk + c covers sites 64 c .. 64 c + 63 and writes the
+// wave sum of its lanes to part[block].
+// ===========================================================================
+// sequential reader of one site's events in a slab, four loads at a time
+struct EvReader {
+    const uint2* E;
+    int st, n, j, b;
+    uint2 q0, q1, q2, q3;
+    PMWA_DEV void init(const uint2* e, int stride, int cnt) { E = e; st = stride; n = cnt; j = 0; b = 4; }
+    PMWA_DEV bool next(uint2& e)
+    {
+        if (j >= n) return false;
+        if (b == 4) {
+            const int base = j;
+            q0 = E[(long long)base * st];
+            if (base + 1 < n) q1 = E[(long long)(base + 1) * st];
+            if (base + 2 < n) q2 = E[(long long)(base + 2) * st];
+            if (base + 3 < n) q3 = E[(long long)(base + 3) * st];
+            b = 0;
+        }
+        e = b == 0 ? q0 : b == 1 ? q1 : b == 2 ? q2 : q3;
+        b++;
+        j++;
+        return true;
+    }
+};
+
+// the interval that starts at tick `start`: its end (the next vertex, else
+// the top of the slab) and its ratio g
+PMWA_DEV void green_interval(EvReader& R, int32_t top, const double* __restrict__ F, int32_t start,
+                             int32_t& end, double& g)
+{
+    uint32_t par = 0;
+    uint2 e;
+    end = top;
+    while (R.next(e)) {
+        if (e.y & 1u) { par ^= 1u; continue; }
+        end = (int32_t)e.x;
+        break;
+    }
+    const long long ell = (long long)end - start;
+    g = 0.0;                           // an empty interval holds no worm
+    if (ell > 0) {
+        const double m = em1(F, ell);
+        const double num = m * (2.0 + m), den = 2.0 * (1.0 + m) + m * m;
+        g = par ? den / num : num / den;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_green(Pools P, int chain, const int4* __restrict__ disp, int nd,
+                                              int nchunk, double* __restrict__ part)
+{
+    const ChainDev& C = P.cd[chain];
+    const int lane = (int)threadIdx.x;
+    const int blk = (int)blockIdx.x;
+    const int c = blk % nchunk, kd = blk / nchunk;
+    const int d = kd % nd, k = kd / nd;
+    const int i = c * 64 + lane;
+    const int4 r = disp[d];            // 0 <= r.x < Lx, 0 <= r.y < Ly, 0 <= r.z < M
+    double acc = 0.0;
+    if (i < C.N) {
+        const int x = i % C.Lx, y = i / C.Lx;
+        const int jj = ((y + r.y) % C.Ly) * C.Lx + (x + r.x) % C.Lx;
+        int dspi, sli, dspj, slj;
+        site_split(C, i, dspi, sli);
+        site_split(C, jj, dspj, slj);
+        const double* F = C.F;
+        const int32_t M = C.M, nt = C.ntau;
+        const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
+        // site i, slab k
+        EvReader A;
+        A.init(P.ev + ev_base(C, k, dspi, sli), C.nloc, P.cnt[C.cnt_off + unit_su(C, k, dspi, sli)]);
+        int32_t sa = Tk, ea;
+        double ga;
+        green_interval(A, Tk1, F, sa, ea, ga);
+        // site jj from the partner time of T_k: its slab kb and interval
+        int32_t pos = Tk + r.z;
+        if (pos >= M) pos -= M;
+        int kb = 0;
+        while (C.T[kb + 1] <= pos) kb++;
+        EvReader B;
+        B.init(P.ev + ev_base(C, kb, dspj, slj), C.nloc, P.cnt[C.cnt_off + unit_su(C, kb, dspj, slj)]);
+        int32_t sb = C.T[kb], eb;
+        double gb;
+        green_interval(B, C.T[kb + 1], F, sb, eb, gb);
+        while (eb <= pos) {
+            sb = eb;
+            green_interval(B, C.T[kb + 1], F, sb, eb, gb);
+        }
+        int32_t tau = Tk;
+        // every step closes an interval of one of the two sites: at most the
+        // events of both sites over all slabs plus the slab ends (a bound
+        // that only an inconsistent state could reach)
+        int guard = 2 * (C.cap + 2) * (nt + 1);
+        while (tau < Tk1 && --guard > 0) {
+            int32_t len = ea - tau;
+            const int32_t lb = eb - pos;
+            if (lb < len) len = lb;
+            if (len < 0) break;
+            const bool same = jj == i && kb == k && sb == sa;
+            acc += (double)len * (same ? 1.0 : ga * gb);
+            tau += len;
+            pos += len;
+            if (tau >= Tk1) break;
+            if (tau == ea) {
+                sa = ea;
+                green_interval(A, Tk1, F, sa, ea, ga);
+            }
+            if (pos == eb) {
+                if (eb == C.T[kb + 1]) {
+                    // next slab of site jj; past the last one time wraps at beta
+                    kb++;
+                    if (kb == nt) { kb = 0; pos -= M; }
+                    B.init(P.ev + ev_base(C, kb, dspj, slj), C.nloc, P.cnt[C.cnt_off + unit_su(C, kb, dspj, slj)]);
+                    sb = C.T[kb];
+                } else {
+                    sb = eb;
+                }
+                green_interval(B, C.T[kb + 1], F, sb, eb, gb);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (lane == 0) part[blk] = acc;
+}
+
+// ===========================================================================
 // End of sweep: per chain, sum the domain partials in domain order, append
 // the record to the series ring, advance the sweep counter.
 // ===========================================================================

@@ -19,7 +19,7 @@ PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
 
 EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
-           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times", "pmwa_diag",
+           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times", "pmwa_diag", "pmwa_green",
            "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
 
 
@@ -79,6 +79,7 @@ def lib():
         L.pmwa_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.pmwa_phase_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.pmwa_diag.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
+        L.pmwa_green.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
         L.pmwa_create_slots.argtypes = [P(pmwa_params), C.c_int, P(pmwa_opts), P(C.c_void_p)]
         L.pmwa_slot_load.argtypes = [C.c_void_p, C.c_int, P(pmwa_params), C.c_int64]
         L.pmwa_slot_release.argtypes = [C.c_void_p, C.c_int]
@@ -210,6 +211,16 @@ def pmwa_phase_times(h):
     return ms, n
 
 
+def pmwa_green(h, chain, disps):
+    """Green function G(r, dt) of b + b^+ on the chain's current
+    configuration, one value per displacement (rx, ry) or (rx, ry, dt ticks)."""
+    rows = [tuple(int(v) for v in dd) + (0,) * (3 - len(dd)) for dd in disps]
+    d = np.ascontiguousarray(np.array(rows, dtype=np.int64).reshape(-1, 3), dtype=np.int32)
+    out = np.zeros(len(d))
+    _check(lib().pmwa_green(h, chain, d.ctypes.data, len(d), out.ctypes.data), "pmwa_green")
+    return out
+
+
 def pmwa_diag(h, chain):
     out = np.zeros(4, np.int64)
     _check(lib().pmwa_diag(h, chain, out.ctypes.data, 4), "pmwa_diag")
@@ -286,3 +297,6 @@ class Sim:
 
     def diag(self, chain=0):
         return pmwa_diag(self.h, chain)
+
+    def green(self, disps, chain=0):
+        return pmwa_green(self.h, chain, disps)
