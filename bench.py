@@ -63,8 +63,10 @@ def params_of(P, cfgs):
     return [P.make_params(**c) for c in cfgs]
 
 
-def run_timed(P, cfgs, steps, warmup, use_graph=False, timing=False, scatter_mode=0):
-    """Warm up, then time exactly `steps` sweeps; returns a result dict."""
+def run_timed(P, cfgs, steps, warmup, use_graph=False, timing=0, scatter_mode=0):
+    """Warm up, then time exactly `steps` sweeps; returns a result dict.
+    `timing`: bit p-1 brackets phase p with HIP events inside the timed
+    region (0: none)."""
     with P.Sim(params_of(P, cfgs), use_graph=use_graph, scatter_mode=scatter_mode,
                series_cap=max(4096, steps + warmup + 8)) as sim:
         if warmup:
@@ -74,7 +76,7 @@ def run_timed(P, cfgs, steps, warmup, use_graph=False, timing=False, scatter_mod
         for c in range(len(cfgs)):
             sim.measure(c)
         if timing:
-            sim.set_timing(True)
+            sim.set_timing_phases(int(timing))
         sync()
         t0 = time.perf_counter()
         sim.sweep(steps)
@@ -188,15 +190,23 @@ def main():
     from paper_1307_0328_amd import workloads as W
 
     single = W.single_64()
-    log(f"[bench] headline: 64x64 chain, plain launches with per-kernel events, "
+    # per-kernel breakdown: every phase bracketed by HIP events (not timed
+    # for the headline, since the events add launch work)
+    brk_steps = min(args.steps, 500)
+    log(f"[bench] kernel breakdown: 64x64 chain, every kernel between HIP events, {brk_steps} sweeps")
+    brk = run_timed(P, single, brk_steps, args.warmup, use_graph=False, timing=0x7F)
+    kern_ms = {PHASES[i]: float(brk["ms"][i]) for i in range(7)}
+    kern_n = {PHASES[i]: int(brk["launches"][i]) for i in range(7)}
+    dom = max(kern_ms, key=kern_ms.get)
+    dom_phase = PHASES.index(dom) + 1
+    # headline: plain launches; the dominant kernel between HIP events on its
+    # stream, so its average launch duration comes from the timed region
+    log(f"[bench] headline: 64x64 chain, plain launches, events around {dom}, "
         f"warmup {args.warmup}, steps {args.steps}")
-    head = run_timed(P, single, args.steps, args.warmup, use_graph=False, timing=True)
+    head = run_timed(P, single, args.steps, args.warmup, use_graph=False, timing=1 << (dom_phase - 1))
     ms_step = head["seconds"] * 1e3 / args.steps
     value = head["nv"] / head["seconds"]
-    kern_ms = {PHASES[i]: float(head["ms"][i]) for i in range(7)}
-    kern_n = {PHASES[i]: int(head["launches"][i]) for i in range(7)}
-    dom = max(kern_ms, key=kern_ms.get)
-    avg_launch_ms = kern_ms[dom] / max(kern_n[dom], 1)
+    avg_launch_ms = float(head["ms"][dom_phase - 1]) / max(int(head["launches"][dom_phase - 1]), 1)
     # algorithmic bytes per launch of the scattering kernel: every site event
     # of the chain read once and written once (a vertex has two 8-byte site
     # records: 32 B; a worm one: 16 B)
@@ -283,7 +293,7 @@ def main():
         if args.large_sweeps > 0:
             big = W.large_2048()
             log(f"[bench] 2048x2048 system: warm-up {args.large_warmup}, {args.large_sweeps} sweeps")
-            g2 = run_timed(P, big, args.large_sweeps, args.large_warmup, use_graph=False, timing=True)
+            g2 = run_timed(P, big, args.large_sweeps, args.large_warmup, use_graph=False, timing=0x7F)
             nvb = g2["nv"] / args.large_sweeps
             msb = g2["seconds"] * 1e3 / args.large_sweeps
             kb = {PHASES[i]: float(g2["ms"][i]) / max(int(g2["launches"][i]), 1) for i in range(7)}

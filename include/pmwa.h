@@ -157,6 +157,10 @@ int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out);
    launches[0..6], and resets the accumulators. */
 int pmwa_set_timing(pmwa_t* h, int enable);
 int pmwa_phase_times(pmwa_t* h, double* ms, int64_t* launches);
+/* The same for a subset of the phases: bit p-1 of `mask` brackets phase p
+   (1..7) with events; the others launch without them.  mask = 0 disables
+   timing, 0x7F equals pmwa_set_timing(h, 1).  PMWA_EINVAL for other bits. */
+int pmwa_set_timing_phases(pmwa_t* h, uint32_t mask);
 
 /* Continuous batching.  pmwa_create_slots allocates n_slots chain slots;
    shapes[i] gives slot i's largest chain: a chain fits slot i when none of

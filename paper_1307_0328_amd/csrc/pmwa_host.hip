@@ -92,8 +92,9 @@ struct pmwa_handle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool own_stream = false;
-    // phase timing
+    // phase timing: events around the phases whose bit (phase - 1) is set
     bool timing = false;
+    uint32_t timing_mask = 0;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_phase;          // phase of the pair (2i, 2i+1)
     size_t ev_used = 0;
@@ -320,7 +321,7 @@ static int launch_kernel(pmwa_t* h, int phase);
 
 static int launch_phase(pmwa_t* h, int phase)
 {
-    if (!h->timing) return launch_kernel(h, phase);
+    if (!h->timing || !((h->timing_mask >> (phase - 1)) & 1u)) return launch_kernel(h, phase);
     if (h->ev_used + 2 > h->ev_pool.size()) {
         for (int i = 0; i < 2; i++) {
             hipEvent_t e;
@@ -836,6 +837,15 @@ int pmwa_set_timing(pmwa_t* h, int enable)
 {
     if (!h) return PMWA_EINVAL;
     h->timing = enable != 0;
+    h->timing_mask = enable != 0 ? 0x7Fu : 0u;
+    return PMWA_OK;
+}
+
+int pmwa_set_timing_phases(pmwa_t* h, uint32_t mask)
+{
+    if (!h || (mask & ~0x7Fu)) return PMWA_EINVAL;
+    h->timing = mask != 0;
+    h->timing_mask = mask;
     return PMWA_OK;
 }
 

@@ -19,7 +19,8 @@ PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
 
 EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
-           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_phase_times", "pmwa_diag", "pmwa_green",
+           "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_set_timing_phases", "pmwa_phase_times", "pmwa_diag",
+           "pmwa_green",
            "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
 
 
@@ -77,6 +78,7 @@ def lib():
         L.pmwa_destroy.argtypes = [C.c_void_p]
         L.pmwa_destroy.restype = None
         L.pmwa_set_timing.argtypes = [C.c_void_p, C.c_int]
+        L.pmwa_set_timing_phases.argtypes = [C.c_void_p, C.c_uint32]
         L.pmwa_phase_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.pmwa_diag.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
         L.pmwa_green.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
@@ -204,6 +206,10 @@ def pmwa_set_timing(h, enable):
     _check(lib().pmwa_set_timing(h, 1 if enable else 0), "pmwa_set_timing")
 
 
+def pmwa_set_timing_phases(h, mask):
+    _check(lib().pmwa_set_timing_phases(h, int(mask)), "pmwa_set_timing_phases")
+
+
 def pmwa_phase_times(h):
     ms = np.zeros(7)
     n = np.zeros(7, np.int64)
@@ -291,6 +297,10 @@ class Sim:
 
     def set_timing(self, enable=True):
         pmwa_set_timing(self.h, enable)
+
+    def set_timing_phases(self, mask):
+        """Time only the phases whose bit (phase - 1) is set in `mask`."""
+        pmwa_set_timing_phases(self.h, mask)
 
     def phase_times(self):
         return pmwa_phase_times(self.h)
