@@ -593,6 +593,23 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
     return (uint32_t)(hi >> 32);
 }
 
+// The workgroup of the scattering kernel is one wavefront, and a wavefront's
+// LDS instructions execute in issue order, so with the node store in LDS
+// (16-bit links) a lane reads what another lane wrote or stamped by an
+// earlier instruction without waiting for it; only the compiler must keep
+// the program order of the accesses.  With the node store in HBM the full
+// barrier (and its wait for the memory operations) stays.
+template <typename Idx>
+PMWA_DEV void wave_order()
+{
+    if constexpr (sizeof(Idx) == 2) {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
 // Steps 5-6 over windows of up to 64 consecutive attempts of the serial
 // sequence (cycle-major, worm-list order).  Lane k evaluates attempt s0+k,
 // its whole decision included, on the state at the start of the window.  A
@@ -646,7 +663,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             for (int i = lane; i < NN; i += 64) own[i] = 0u;
             wid = 1;
         }
-        __syncthreads();
+        wave_order<Idx>();
         const bool act = lane < wmax && s0 + lane < total;
         // the attempt's three stream words, read with the first loads of the
         // window (the empty asm below consumes them before the decision, so
@@ -757,7 +774,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             atomicMax(&own[Pn], stamp);
             atomicMax(&own[Nn], stamp);
         }
-        __syncthreads();
+        wave_order<Idx>();
         // stamps of earlier windows are below wid << 8; in this window a
         // stamp exceeds the lane's own value exactly when an earlier lane set it
         bool conflict = !act;
@@ -785,7 +802,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
                 A.prv[Nn] = (Idx)w;
             }
         }
-        __syncthreads();
+        wave_order<Idx>();
         cur += 3u * (uint32_t)kc;
         s0 += kc;
         iw0 += kc < 64 ? __shfl(lm, kc, 64) : m64;   // (iw0 + kc) mod nw
