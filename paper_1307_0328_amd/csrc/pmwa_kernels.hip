@@ -182,7 +182,7 @@ PMWA_DEV int bond_walk_flips(const BondCtx& B, const uint32_t* __restrict__ FA, 
     uint32_t s_a = (uint32_t)B.sa0, s_c = (uint32_t)B.sc0;
     bool clash = false;
     int32_t last = 2 * Tk;                  // positions in half ticks (< 2^31)
-    long long acc = 0;
+    int32_t acc = 0;                        // the slab's integral, below 2^31
     uint32_t ra = na > 0 ? FA[0] : 0u, rc = nc > 0 ? FC[0] : 0u;
     uint32_t rx = np > 0 ? (uint32_t)cand[0] : 0u;
     uint32_t ka = na > 0 ? fkey(ra, mask_a) : INF;
@@ -207,7 +207,7 @@ PMWA_DEV int bond_walk_flips(const BondCtx& B, const uint32_t* __restrict__ FA, 
         // n_a n_c integral up to a flip
         const uint32_t rf = isa ? ra : rc;
         const int32_t pos = 2 * (int32_t)(rf & BV_TICK) + (int32_t)((rf >> 29) & 1u);
-        acc += isx ? 0LL : (long long)(int32_t)(s_a & s_c) * (pos - last);
+        acc += (!isx && (s_a & s_c)) ? pos - last : 0;
         last = isx ? last : pos;
         s_a ^= isa ? 1u : 0u;
         s_c ^= isc ? 1u : 0u;
@@ -228,7 +228,7 @@ PMWA_DEV int bond_walk_flips(const BondCtx& B, const uint32_t* __restrict__ FA, 
         rc = isc ? rn : rc;
         kc = isc ? kn : kc;
     }
-    acc += (long long)(int32_t)(s_a & s_c) * (2 * Tk1 - last);
+    acc += (s_a & s_c) ? 2 * Tk1 - last : 0;
     nn += acc;
     return clash ? -1 : nout;
 }
@@ -401,13 +401,20 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         Stream rs;
         rs.init(C, sweep, RNG_V, unit);
         const double u0 = u53(rs.next());
-        int n = 0;
-        if (k - k_first < 2) {
-            const double* cdf = s_cdf + (k - k_first) * C.cdf_stride;
-            while (!(u0 < cdf[n])) n++;
-        } else {
-            const double* cdf = P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
-            while (!(u0 < cdf[n])) n++;
+        // candidate count: the first n with u0 < cdf[n].  The table does not
+        // decrease and ends in 2.0 entries, so a binary search finds it in a
+        // fixed number of steps
+        int n;
+        {
+            const double* cdf = k - k_first < 2 ? s_cdf + (k - k_first) * C.cdf_stride
+                                                : P.cdf + C.cdf_off + (long long)k * C.cdf_stride;
+            int lo = 0, hi = C.cdf_stride - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (u0 < cdf[mid]) hi = mid;
+                else lo = mid + 1;
+            }
+            n = lo;
         }
         const uint64_t dT = (uint64_t)(Tk1 - Tk);
         // ticks as first drawn; they are the ticks kept unless one repeats
