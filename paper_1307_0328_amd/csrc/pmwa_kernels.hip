@@ -1720,18 +1720,25 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
     }
     const int nv = base;
     __syncthreads();
-    // merged order: (tick, bond id) keys of a site are distinct
+    // merged order: (tick, bond id) keys of a site are distinct.  The four
+    // bonds are ranked once (2 bits each in brk), so an entry's key is the
+    // 32-bit 4 tick + rank of its bond (ticks are below 2^29)
+    uint32_t brk = 0;
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int d2 = 0; d2 < 4; d2++) r += bids[d2] < bids[d] ? 1u : 0u;
+        brk |= r << (2 * d);
+    }
     for (int e = lane; e < nv; e += 64) {
         const uint32_t v = val[e];
-        const int32_t t = (int32_t)(v & BV_TICK);
         const uint32_t dme = vsl[e];
-        const long long b = dme == 0 ? bids[0] : dme == 1 ? bids[1] : dme == 2 ? bids[2] : bids[3];
+        const uint32_t key = ((v & BV_TICK) << 2) | ((brk >> (2 * dme)) & 3u);
         int rank = 0;
         for (int e2 = 0; e2 < nv; e2++) {
-            const int32_t t2 = (int32_t)(val[e2] & BV_TICK);
-            const uint32_t d2 = vsl[e2];
-            const long long b2 = d2 == 0 ? bids[0] : d2 == 1 ? bids[1] : d2 == 2 ? bids[2] : bids[3];
-            rank += (t2 < t || (t2 == t && b2 < b)) ? 1 : 0;
+            const uint32_t key2 = ((val[e2] & BV_TICK) << 2) | ((brk >> (2 * (uint32_t)vsl[e2])) & 3u);
+            rank += key2 < key ? 1 : 0;
         }
         mval[rank] = v;
         msl[rank] = (uint8_t)dme;
