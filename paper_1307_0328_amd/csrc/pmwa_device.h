@@ -129,6 +129,21 @@ PMWA_DEV void philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
     o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
 }
 
+// N rounds of the same generator on a state carried between calls, the round
+// keys advancing with it: ten rounds from (counter, key) equal philox10.
+// Splitting the rounds lets a caller place them between dependent loads.
+template <int N>
+PMWA_DEV void philox_rounds(uint32_t (&x)[4], uint32_t& k0, uint32_t& k1)
+{
+#pragma unroll
+    for (int r = 0; r < N; r++) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x[0], p1 = (uint64_t)0xCD9E8D57u * x[2];
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k0, y2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k1;
+        x[1] = (uint32_t)p1; x[3] = (uint32_t)p0; x[0] = y0; x[2] = y2;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+}
+
 // Word stream of one unit: word 2j = out1:out0, word 2j+1 = out3:out2 of the
 // block with counter (j, unit, sweep, chain_id << 8 | kind).
 struct Stream {

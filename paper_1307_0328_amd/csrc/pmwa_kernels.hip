@@ -648,7 +648,6 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
     const int lane = (int)threadIdx.x;
     const long long total = (long long)C.ncycle * nw;
     if (total > 0x50000000LL) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return 0; }
-    const int wmax = 64;
     // lane k holds attempt s0 + k: worm-list position iw0 + (k mod nw), with
     // k / nw earlier attempts of the same worm in the window
     const int lm = nw > 0 ? lane % nw : 0;
@@ -658,7 +657,8 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
     uint32_t cur = 0, filled = 0, wid = 0;
     int iw0 = 0;                       // worm-list position of attempt s0
     for (long long s0 = 0; s0 < total;) {
-        // words [cur, cur + 192) of the stream sit in the 512-word ring
+        // words [cur, cur + 192) of the stream sit in the 512-word ring (a
+        // catch-up after long windows; the window below normally keeps it full)
         while (filled < cur + 192u) {
             uint32_t o[4];
             philox10((filled >> 1) + (uint32_t)lane, c1, c2, c3, k0, k1, o);
@@ -671,47 +671,58 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             wid = 1;
         }
         wave_order<Idx>();
-        const bool act = lane < wmax && s0 + lane < total;
+        const bool act = s0 + lane < total;
         // the attempt's three stream words, read with the first loads of the
         // window (the empty asm below consumes them before the decision, so
         // that they are not deferred behind the evaluation)
         const uint32_t myc = cur + 3u * (uint32_t)lane;
         const uint64_t wd0 = ring[myc & 511u], wd1 = ring[(myc + 1u) & 511u], wd2 = ring[(myc + 2u) & 511u];
-        // ---- evaluate on the window's starting state
-        uint32_t w = 0, fw = 0, pw = 0, nn_ = 0, x = 0, fx = 0, y = 0, xf = 0, wf = 0;
-        uint32_t fy = 0, yp = 0, yn = 0, f_wf = 0, f_xf = 0, f_yp = 0;
-        int32_t t = 0, t_wf = 0, t_xf = 0, t_yp = 0, t_yn = 0;
-        bool blocked = true, up = false;
-        if (act) {
-            int iw = iw0 + lm;
-            if (iw >= nw) iw -= nw;
-            w = A.wl[iw];
-            fw = (uint32_t)A.fl[w] ^ ((rep & 1) ? F_DIRUP : 0u);
-            pw = A.prv[w];
-            nn_ = A.nxt[w];
-            up = (fw & F_DIRUP) != 0;
-            x = up ? nn_ : pw;
-            wf = up ? pw : nn_;
-            // x and wf are nodes (sentinels included), so their fields are
-            // read in one round; y and xf exist only past a vertex end
-            fx = A.fl[x];
-            t = A.tick[x];
-            y = A.aux[x];
-            xf = up ? A.nxt[x] : A.prv[x];
-            t_wf = A.tick[wf];
-            f_wf = A.fl[wf];
-            blocked = (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) != 0;
-            if (!blocked) {
-                fy = A.fl[y];
-                yp = A.prv[y];
-                yn = A.nxt[y];
-                t_xf = A.tick[xf];
-                f_xf = A.fl[xf];
-                t_yp = A.tick[yp];
-                f_yp = A.fl[yp];
-                t_yn = A.tick[yn];
-            }
-        }
+        // ---- evaluate on the window's starting state.  Every lane evaluates,
+        //      so that the reads form one straight chain; an inactive lane
+        //      still names a worm of the list, and a blocked attempt reads
+        //      nothing past x (its x- and y-side nodes fall back to the worm),
+        //      so every index is a node of the domain.
+        int iw = iw0 + lm;
+        if (iw >= nw) iw -= nw;
+        const uint32_t w = A.wl[iw];
+        // the next 128 stream words, computed two rounds at a time while the
+        // window's dependent reads are in flight (each pair is tied to the
+        // values of one level of reads) and stored at the end if the ring has
+        // room for them
+        uint32_t po[4] = {(filled >> 1) + (uint32_t)lane, c1, c2, c3};
+        uint32_t pk0 = k0, pk1 = k1;
+        philox_rounds<2>(po, pk0, pk1);
+        asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(w));
+        const uint32_t fw = (uint32_t)A.fl[w] ^ ((rep & 1) ? F_DIRUP : 0u);
+        const uint32_t pw = A.prv[w];
+        const uint32_t nn_ = A.nxt[w];
+        philox_rounds<2>(po, pk0, pk1);
+        asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fw), "v"(pw), "v"(nn_));
+        const bool up = (fw & F_DIRUP) != 0;
+        const uint32_t x = up ? nn_ : pw;
+        const uint32_t wf = up ? pw : nn_;
+        const uint32_t fx = A.fl[x];
+        const int32_t t = A.tick[x];
+        const uint32_t ya = A.aux[x];
+        const uint32_t xfa = up ? A.nxt[x] : A.prv[x];
+        const int32_t t_wf = A.tick[wf];
+        const uint32_t f_wf = A.fl[wf];
+        philox_rounds<2>(po, pk0, pk1);
+        asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fx), "v"(ya), "v"(xfa));
+        const bool blocked = (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) != 0;
+        const uint32_t y = blocked ? w : ya;
+        const uint32_t xf = blocked ? w : xfa;
+        const uint32_t fy = A.fl[y];
+        const uint32_t yp = A.prv[y];
+        const uint32_t yn = A.nxt[y];
+        const int32_t t_xf = A.tick[xf];
+        const uint32_t f_xf = A.fl[xf];
+        const int32_t t_yp = A.tick[yp];
+        const uint32_t f_yp = A.fl[yp];
+        const int32_t t_yn = A.tick[yn];
+        philox_rounds<2>(po, pk0, pk1);
+        asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fy), "v"(yp), "v"(yn));
+        philox_rounds<2>(po, pk0, pk1);
         const bool xa = ((fx >> 1) & 3u) < 2u;
         int32_t Lxb, Lxa;
         if (up) { Lxb = t - (t_wf + (int32_t)(f_wf & F_WORM)); Lxa = t_xf - t; }
@@ -725,49 +736,40 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         const int32_t Li = up ? Lxb : Lxa;
         const int i = up ? (xa ? 0 : 1) : (xa ? 2 : 3);
         // ---- the decision on the window's starting state: enter test, exit
-        //      leg and landing slot (stream words 3s, 3s+1, 3s+2)
+        //      leg and landing slot (stream words 3s, 3s+1, 3s+2); computed
+        //      by every lane, kept where the attempt is active and not blocked
         asm volatile("" ::"v"(wd0), "v"(wd1), "v"(wd2));
-        bool moved = false, above = false;
-        uint32_t Pn = 0, Nn = 0, fv = 0, newup = 0, fx_now = fx;
-        int32_t ntick = 0;
-        if (act && !blocked) {
-            const uint32_t r = below32(wd0, (uint32_t)Li);
-            moved = (int32_t)r < Lmin;
-            if (moved) {
-                // vertex roots with the worm in place
-                const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;
-                const uint32_t rxa = (fx >> 3) & 1u;
-                const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
-                const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
-                                 : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
-                const int S0 = S ^ (1 << i);
-                // u53(word) < P  <=>  (word >> 11) < ceil(P 2^53), exactly; the
-                // cumulative thresholds do not decrease, so the exit leg (the
-                // first j with word < row[j]) is the number at or below the word
-                const uint64_t w53 = wd1 >> 11;
-                const uint64_t* row = sthr + S0 * 16 + i * 4;
-                const uint64_t t0 = row[0], t1 = row[1], t2 = row[2];
-                const int j = (int)(w53 >= t0) + (int)(w53 >= t1) + (int)(w53 >= t2);
-                const int32_t Lj = j == 0 ? L0 : j == 1 ? L1 : j == 2 ? L2 : L3;
-                const uint32_t r2 = below32(wd2, (uint32_t)Lj);
-                // leave leg i: above the end on x, that segment takes the worm's state
-                fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
-                const bool on_x = ((j & 1) != 0) != xa;
-                above = j >= 2;
-                if (above) {
-                    Pn = on_x ? x : y;
-                    Nn = on_x ? (up ? xf : wf) : yn;
-                    fv = on_x ? fx_now : fy;
-                    newup = fv & F_UP;
-                } else {
-                    Nn = on_x ? x : y;
-                    Pn = on_x ? (up ? wf : xf) : yp;
-                    const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
-                    newup = (fp & F_UP) ^ F_UP;
-                }
-                ntick = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
-            }
-        }
+        // (and the speculative words here, so that they are not sunk to the
+        // store at the end, where nothing would hide their latency)
+        asm volatile("" ::"v"(po[0]), "v"(po[1]), "v"(po[2]), "v"(po[3]));
+        const uint32_t r = below32(wd0, (uint32_t)Li);
+        const bool moved = act && !blocked && (int32_t)r < Lmin;
+        // vertex roots with the worm in place
+        const uint32_t rxb = up ? (fw >> 3) & 1u : (f_xf >> 3) & 1u;
+        const uint32_t rxa = (fx >> 3) & 1u;
+        const uint32_t ryb = (f_yp >> 3) & 1u, rya = (fy >> 3) & 1u;
+        const int S = xa ? (int)(rxb | (ryb << 1) | (rxa << 2) | (rya << 3))
+                         : (int)(ryb | (rxb << 1) | (rya << 2) | (rxa << 3));
+        const int S0 = S ^ (1 << i);
+        // u53(word) < P  <=>  (word >> 11) < ceil(P 2^53), exactly; the
+        // cumulative thresholds do not decrease, so the exit leg (the first j
+        // with word < row[j]) is the number at or below the word
+        const uint64_t w53 = wd1 >> 11;
+        const uint64_t* row = sthr + S0 * 16 + i * 4;
+        const uint64_t th0 = row[0], th1 = row[1], th2 = row[2];
+        const int j = (int)(w53 >= th0) + (int)(w53 >= th1) + (int)(w53 >= th2);
+        const int32_t Lj = (j & 2) ? ((j & 1) ? L3 : L2) : ((j & 1) ? L1 : L0);
+        const uint32_t r2 = below32(wd2, (uint32_t)Lj);
+        // leave leg i: above the end on x, that segment takes the worm's state
+        const uint32_t fx_now = up ? fx : ((fx & ~F_UP) | (fw & F_UP));
+        const bool on_x = ((j & 1) != 0) != xa;
+        const bool above = j >= 2;
+        const uint32_t Pn = above ? (on_x ? x : y) : (on_x ? (up ? wf : xf) : yp);
+        const uint32_t Nn = above ? (on_x ? (up ? xf : wf) : yn) : (on_x ? x : y);
+        const uint32_t fv = on_x ? fx_now : fy;
+        const uint32_t fp = on_x ? (up ? f_wf : f_xf) : f_yp;
+        const uint32_t newup = above ? (fv & F_UP) : ((fp & F_UP) ^ F_UP);
+        const int32_t ntick = above ? t + (int32_t)r2 : t - 1 - (int32_t)r2;
         // ---- nodes a move writes: the worm's old and new neighbours (the
         //      vertex end it leaves is one of the old ones).  Anything reading
         //      the worm node itself reads one of its old neighbours.  A turn
@@ -783,13 +785,12 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         }
         wave_order<Idx>();
         // stamps of earlier windows are below wid << 8; in this window a
-        // stamp exceeds the lane's own value exactly when an earlier lane set it
-        bool conflict = !act;
-        if (act) {
-            uint32_t v = max(own[w], max(own[pw], own[nn_]));
-            if (!blocked) v = max(v, max(max(own[xf], own[y]), max(own[yp], own[yn])));
-            conflict = v > stamp;
-        }
+        // stamp exceeds the lane's own value exactly when an earlier lane set
+        // it.  A blocked attempt's x- and y-side nodes are the worm and its
+        // neighbours, so it tests the three nodes it reads.
+        const uint32_t v = max(max(max(own[w], own[pw]), max(own[nn_], own[xf])),
+                               max(max(own[y], own[yp]), own[yn]));
+        const bool conflict = !act || v > stamp;
         const unsigned long long cmask = __ballot(conflict);
         const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
         // ---- apply the surviving attempts (disjoint nodes)
@@ -809,10 +810,19 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
                 A.prv[Nn] = (Idx)w;
             }
         }
+        // the speculative words go in when the ring has room: this window
+        // read [cur, cur + 192), and the block [filled, filled + 128) must not
+        // wrap onto words not yet consumed
+        if (filled <= cur + 384u) {
+            ring[(filled + 2u * lane) & 511u] = ((uint64_t)po[1] << 32) | po[0];
+            ring[(filled + 2u * lane + 1u) & 511u] = ((uint64_t)po[3] << 32) | po[2];
+            filled += 128u;
+        }
         wave_order<Idx>();
         cur += 3u * (uint32_t)kc;
         s0 += kc;
-        iw0 += kc < 64 ? __shfl(lm, kc, 64) : m64;   // (iw0 + kc) mod nw
+        // (iw0 + kc) mod nw: lane kc's position offset, read from its register
+        iw0 += kc < 64 ? __builtin_amdgcn_readlane(lm, kc & 63) : m64;
         if (iw0 >= nw) iw0 -= nw;
         windows++;
     }
