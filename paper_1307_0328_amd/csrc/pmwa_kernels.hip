@@ -1989,16 +1989,31 @@ __global__ void __launch_bounds__(256) k_finish(Pools P)
         const DomPart dp = P.dpart[C.dom_off + i];
         a0 += dp.nv; a1 += dp.nkink; a2 += dp.nw; a3 += dp.occ2; q += dp.qimp;
     }
-    __shared__ long long s0[256], s1[256], s2[256], s3[256];
-    __shared__ double sq[256];
-    s0[tid] = a0; s1[tid] = a1; s2[tid] = a2; s3[tid] = a3; sq[tid] = q;
+    // block sum: a butterfly inside each wavefront, then the four wavefront
+    // sums (the integer counts are exact in any order; the estimator sum has
+    // this fixed order for every launch form)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+        a2 += __shfl_xor(a2, o, 64);
+        a3 += __shfl_xor(a3, o, 64);
+        q += __shfl_xor(q, o, 64);
+    }
+    __shared__ long long s0[4], s1[4], s2[4], s3[4];
+    __shared__ double sq[4];
+    if ((tid & 63) == 0) {
+        const int wv = tid >> 6;
+        s0[wv] = a0; s1[wv] = a1; s2[wv] = a2; s3[wv] = a3; sq[wv] = q;
+    }
     __syncthreads();
     if (tid == 0) {
         pmwa_obs o;
-        o.nv = 0; o.nkink = 0; o.nw = 0; o.occ2 = 0; o.qimp = 0.0;
-        for (int i = 0; i < 256; i++) {
-            o.nv += s0[i]; o.nkink += s1[i]; o.nw += s2[i]; o.occ2 += s3[i]; o.qimp += sq[i];
-        }
+        o.nv = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+        o.nkink = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+        o.nw = (s2[0] + s2[1]) + (s2[2] + s2[3]);
+        o.occ2 = (s3[0] + s3[1]) + (s3[2] + s3[3]);
+        o.qimp = (sq[0] + sq[1]) + (sq[2] + sq[3]);
         o.nn2 = (long long)P.nnacc[chain];
         P.nnacc[chain] = 0ULL;
         const unsigned long long sw = P.sweep[chain];
