@@ -314,34 +314,41 @@ PMWA_DEV int vertex_exact(const ChainDev& C, const BondCtx& B, const Lst& LA, co
     return nout;
 }
 
-// occupation-changing objects of a site list -> LDS column (at most `rows`);
-// returns their number (which may exceed rows)
-PMWA_DEV int stage_flips(const uint2* E, int n, int st, int s0, uint32_t* F, int rows)
+// occupation-changing objects (kinks and worms) of both ends of a bond ->
+// their LDS columns (at most `rows` each).  Branch-free body: every event is
+// written at the next free row and kept only if it changes the occupation.
+// Each batch issues the loads of up to 16 events of each end together, from
+// positions clamped to the list (a list with no events reads its first slot,
+// which is allocated), so that one round trip to memory serves the batch;
+// only the events inside the lists count.  Returns the two counts (which may
+// exceed rows).
+PMWA_DEV int2 stage_flips2(const uint2* EA, int na, int sa0, uint32_t* FA,
+                           const uint2* EC, int nc, int sc0, uint32_t* FC, int st, int rows)
 {
-    // branch-free body: every event is written at the next free row and
-    // kept only if it changes the occupation, so the loads can be batched
-    int nf = 0, s = s0;
-    int j = 0;
-    for (; j + 8 <= n; j += 8) {
-        uint2 e[8];
+    constexpr int SB = 16;
+    int fa = 0, fc = 0, s_a = sa0, s_c = sc0;
+    const int nmax = na > nc ? na : nc;
+    const int la = na > 0 ? na - 1 : 0, lc = nc > 0 ? nc - 1 : 0;
+    for (int j = 0; j < nmax; j += SB) {
+        uint2 ea[SB], ec[SB];
 #pragma unroll
-        for (int q = 0; q < 8; q++) e[q] = E[(long long)(j + q) * st];
+        for (int q = 0; q < SB; q++) {
+            ea[q] = EA[(long long)(j + q < la ? j + q : la) * st];
+            ec[q] = EC[(long long)(j + q < lc ? j + q : lc) * st];
+        }
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int up = (int)ev_up(e[q].y);
-            F[(nf < rows ? nf : rows - 1) * VL] = e[q].x | ((e[q].y & 1u) << 29) | (((e[q].y >> 1) & 3u) << 30);
-            nf += up != s ? 1 : 0;
-            s = up;
+        for (int q = 0; q < SB; q++) {
+            const bool va = j + q < na, vc = j + q < nc;
+            const int ua = (int)ev_up(ea[q].y), uc = (int)ev_up(ec[q].y);
+            FA[(fa < rows ? fa : rows - 1) * VL] = ea[q].x | ((ea[q].y & 1u) << 29) | (((ea[q].y >> 1) & 3u) << 30);
+            FC[(fc < rows ? fc : rows - 1) * VL] = ec[q].x | ((ec[q].y & 1u) << 29) | (((ec[q].y >> 1) & 3u) << 30);
+            fa += (va && ua != s_a) ? 1 : 0;
+            fc += (vc && uc != s_c) ? 1 : 0;
+            s_a = va ? ua : s_a;
+            s_c = vc ? uc : s_c;
         }
     }
-    for (; j < n; j++) {
-        const uint2 e = E[(long long)j * st];
-        const int up = (int)ev_up(e.y);
-        F[(nf < rows ? nf : rows - 1) * VL] = e.x | ((e.y & 1u) << 29) | (((e.y >> 1) & 3u) << 30);
-        nf += up != s ? 1 : 0;
-        s = up;
-    }
-    return nf;
+    return make_int2(fa, fc);
 }
 
 // dynamic LDS: Poisson tables of the first two slabs of the block (2 * vs
@@ -386,9 +393,12 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         B.sc0 = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
         const uint2* Ea = P.ev + ev_base(C, k, dsp, sl);
         const uint2* Ec = P.ev + ev_base(C, k, dspc, slc);
-        const int nfa = stage_flips(Ea, na, B.st, B.sa0, FA, rows);
-        const int nfc = stage_flips(Ec, nc, B.st, B.sc0, FC, rows);
-        const bool staged = nfa <= rows && nfc <= rows;
+        const int2 nf2 = stage_flips2(Ea, na, B.sa0, FA, Ec, nc, B.sc0, FC, B.st, rows);
+        const int nfa = nf2.x, nfc = nf2.y;
+        // a column is used only with a row to spare: once a count reaches
+        // `rows`, later events land on the last row, which then no longer
+        // holds the last flip
+        const bool staged = nfa < rows && nfc < rows;
         const FlipList fla{FA, nfa, B.sa0, d}, flc{FC, nfc, B.sc0, -1};
         const FullList gla{Ea, na, B.st, d}, glc{Ec, nc, B.st, -1};
 
