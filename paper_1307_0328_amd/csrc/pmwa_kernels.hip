@@ -436,24 +436,20 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         AR.init(C);
         bool rep;
         if (n <= 32) {
+            // the draws stay rolled loops through the LDS column (unrolled,
+            // each inlined generator call would multiply the code size)
+            for (int i = 0; i < n; i++) cand[i * VL] = Tk + (int32_t)below(rs.next(), dT);
             int32_t c[32];
 #pragma unroll
-            for (int i = 0; i < 32; i++) c[i] = 0x7FFFFFFF;
-#pragma unroll
-            for (int i = 0; i < 32; i++)
-                if (i < n) c[i] = Tk + (int32_t)below(rs.next(), dT);
+            for (int i = 0; i < 32; i++) c[i] = i < n ? cand[i * VL] : 0x7FFFFFFF;
             sort32(c);
             rep = false;
 #pragma unroll
             for (int i = 0; i + 1 < 32; i++) rep |= (i + 1 < n) && c[i] == c[i + 1];
-            if (!rep) {
-#pragma unroll
-                for (int i = 0; i < 32; i++)
-                    if (i < n) c[i] = (int32_t)((uint32_t)c[i] | (AR.rank(rs.next()) << 29));
-            }
 #pragma unroll
             for (int i = 0; i < 32; i++)
                 if (i < n) cand[i * VL] = c[i];
+            if (!rep) tag_ranks(cand, n, rs, AR);
         } else {
             for (int i = 0; i < n; i++) cand[i * VL] = Tk + (int32_t)below(rs.next(), dT);
             rep = sort_col<VL>(cand, n);
