@@ -173,53 +173,60 @@ PMWA_DEV int bond_walk_flips(const BondCtx& B, const uint32_t* __restrict__ FA, 
                              uint32_t* out, int capb, long long& nn)
 {
     const uint32_t INF = 0xFFFFFFFFu;
+    // class of a flip record: 3 for a worm, else 0 or 2 by the mask bit of
+    // its direction (a 2-bit table indexed by worm << 1 | mask bit)
     auto fkey = [](uint32_t r, uint32_t mask) -> uint32_t {
-        const uint32_t w = (r >> 29) & 1u, dir = r >> 30;
-        const uint32_t cls = w ? 3u : (((mask >> dir) & 1u) ? 0u : 2u);
-        return ((r & BV_TICK) << 2) | cls;
+        const uint32_t w = (r >> 29) & 1u, m = (mask >> (r >> 30)) & 1u;
+        return ((r & BV_TICK) << 2) | ((0xF2u >> ((w << 2) | (m << 1))) & 3u);
     };
-    int ia = 0, ic = 0, i = 0, nout = 0;
+    int ia = 0, ic = 0, i = 0, nout = 0, oidx = 0;
     uint32_t s_a = (uint32_t)B.sa0, s_c = (uint32_t)B.sc0;
     bool clash = false;
     int32_t last = 2 * Tk;                  // positions in half ticks (< 2^31)
     int32_t acc = 0;                        // the slab's integral, below 2^31
+    const uint32_t kink_tag = d << 1;       // bits 29.. of a vertex of this bond
     uint32_t ra = na > 0 ? FA[0] : 0u, rc = nc > 0 ? FC[0] : 0u;
     uint32_t rx = np > 0 ? (uint32_t)cand[0] : 0u;
     uint32_t ka = na > 0 ? fkey(ra, mask_a) : INF;
     uint32_t kc = nc > 0 ? fkey(rc, mask_c) : INF;
     uint32_t kx = np > 0 ? (((rx & BV_TICK) << 2) | 1u) : INF;
     while ((ka & kc & kx) != INF) {
-        // which stream comes next; every update below is a select, so the
-        // lanes of a wavefront stay together whatever stream each takes
-        const bool isx = kx < ka && kx < kc;
-        const bool isa = !isx && ka <= kc;
-        const bool isc = !isx && !isa;
+        // which stream comes next (keys of different streams differ, but
+        // for equal flip keys, where end a goes first); every update below
+        // is a select, so the lanes of a wavefront stay together
+        const uint32_t km = min(min(ka, kc), kx);
+        const bool isx = kx == km;
+        const bool isa = !isx & (ka == km);
+        const bool isc = !isx & !isa;
         const uint32_t tau = rx & BV_TICK, rank = rx >> 29;
-        const bool a_kink = ((ra >> 29) & 1u) == 0u && (ra >> 30) == d;   // a vertex of this bond
+        const bool a_kink = (ra >> 29) == kink_tag;   // a vertex of this bond
         // a candidate on the tick of the next kink of this bond on end a
-        const bool cl = isx && a_kink && ka == ((tau << 2) | 2u);
+        const bool cl = isx & a_kink & (ka == ((tau << 2) | 2u));
         const uint32_t need = (acc_cnt >> (3u * (s_a | (s_c << 1)))) & 7u;
-        const bool wr = (isx && !cl && rank < need) || (isa && !clash && a_kink);
+        // (bitwise operators throughout: no short-circuit branches)
+        const bool wr = (isx & !cl & (rank < need)) | (isa & !clash & a_kink);
         const uint32_t val = isx ? (tau | (s_a << 30) | (s_c << 31))
                                  : ((ra & BV_TICK) | BV_KINK | (s_a << 30) | ((s_a ^ 1u) << 31));
-        if (wr && nout < capb) out[(long long)nout * B.st] = val;
+        if (wr & (nout < capb)) out[oidx] = val;
         nout += wr ? 1 : 0;
+        oidx += wr ? B.st : 0;
         // n_a n_c integral up to a flip
         const uint32_t rf = isa ? ra : rc;
         const int32_t pos = 2 * (int32_t)(rf & BV_TICK) + (int32_t)((rf >> 29) & 1u);
-        acc += (!isx && (s_a & s_c)) ? pos - last : 0;
+        acc += (!isx & ((s_a & s_c) != 0u)) ? pos - last : 0;
         last = isx ? last : pos;
         s_a ^= isa ? 1u : 0u;
         s_c ^= isc ? 1u : 0u;
         clash |= cl;
-        i += (isx && !cl) ? 1 : 0;
+        i += (isx & !cl) ? 1 : 0;
         ia += isa ? 1 : 0;
         ic += isc ? 1 : 0;
-        // next record of the stream that advanced (one LDS read)
+        // next record of the stream that advanced: one LDS read, from row 0
+        // past the end of the list (every column has a row 0)
         const int nx = isx ? i : isa ? ia : ic;
         const int lim = isx ? np : isa ? na : nc;
         const uint32_t* src = isx ? reinterpret_cast<const uint32_t*>(cand) : isa ? FA : FC;
-        const uint32_t rn = nx < lim ? src[nx * VL] : 0u;
+        const uint32_t rn = src[(nx < lim ? nx : 0) * VL];
         const uint32_t kn = nx < lim ? (isx ? (((rn & BV_TICK) << 2) | 1u) : fkey(rn, isa ? mask_a : mask_c)) : INF;
         rx = isx ? rn : rx;
         kx = isx ? (cl ? INF : kn) : kx;
