@@ -374,6 +374,7 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
     uint32_t* FA = reinterpret_cast<uint32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + (size_t)vs * VL + lane;
     uint32_t* FC = FA + (size_t)rows * VL;
     const int k_first = bt.y / (2 * C.N);
+#pragma unroll 4
     for (int i = lane; i < 2 * C.cdf_stride; i += VL) {
         const int kk = k_first + i / C.cdf_stride;
         s_cdf[i] = kk < C.ntau ? P.cdf[C.cdf_off + (long long)kk * C.cdf_stride + i % C.cdf_stride] : 2.0;
@@ -496,7 +497,9 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     const int u = bt.y + (int)threadIdx.x;
     __shared__ double sE[1024];
     __shared__ int32_t s_off[NWL * 64];
-    for (int i = (int)threadIdx.x; i < 1024; i += 64) sE[i] = C.F[i];
+    // (unrolled, so that the loads are in flight together)
+#pragma unroll
+    for (int q = 0; q < 16; q++) sE[q * 64 + (int)threadIdx.x] = C.F[q * 64 + (int)threadIdx.x];
     __syncthreads();
     if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
@@ -1132,8 +1135,11 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     int* cnt = off + (nloc + 1);
     // exit-leg thresholds ceil(P 2^53) of the cumulative scattering table
     // (exact: a power-of-two scaling, then an integral value below 2^55)
-    for (int i = lane; i < 256; i += 64) sthr[i] = (uint64_t)ceil(C.scat[i] * 0x1.0p53);
-    for (int i = lane; i < 1024; i += 64) sE[i] = C.F[i];
+    // (both copies unrolled, so that their loads are in flight together)
+#pragma unroll
+    for (int q = 0; q < 4; q++) sthr[q * 64 + lane] = (uint64_t)ceil(C.scat[q * 64 + lane] * 0x1.0p53);
+#pragma unroll
+    for (int q = 0; q < 16; q++) sE[q * 64 + lane] = C.F[q * 64 + lane];
     for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
     __syncthreads();
     // exclusive scan of the per-site counts
@@ -1223,7 +1229,10 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
     const int u = bt.y + (int)threadIdx.x;
     __shared__ double sE[1024];
     __shared__ int32_t s_off[2 * NWL * VL];
-    for (int i = (int)threadIdx.x; i < 1024; i += VL) sE[i] = C.F[i];
+    // (unrolled, so that the loads are in flight together)
+    static_assert(1024 % VL == 0, "table copy");
+#pragma unroll
+    for (int q = 0; q < 1024 / VL; q++) sE[q * VL + (int)threadIdx.x] = C.F[q * VL + (int)threadIdx.x];
     __syncthreads();
     if (u >= C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
