@@ -1195,13 +1195,34 @@ struct SiteArr {
     PMWA_DEV uint2 get(int j) const { return e[(long long)j * st]; }
     PMWA_DEV void put(int j, uint2 v) { e[(long long)j * st] = v; }
     // resize the range [lo, hi) to m entries (contents of the new range
-    // undefined), moving the events above it
+    // undefined), moving the events above it.  They move 16 at a time: a
+    // chunk's loads (from positions clamped to the events that move) are all
+    // issued before its stores, so one round trip to memory serves the chunk,
+    // and no chunk stores over an event that a later chunk still loads.
     PMWA_DEV bool resize(int lo, int hi, int m)
     {
+        constexpr int MB = 16;
         const int delta = m - (hi - lo);
         if (n + delta > cap) return false;
-        if (delta > 0) for (int j = n - 1; j >= hi; j--) put(j + delta, get(j));
-        else if (delta < 0) for (int j = hi; j < n; j++) put(j + delta, get(j));
+        if (delta > 0) {
+            for (int top = n - 1; top >= hi; top -= MB) {
+                uint2 v[MB];
+#pragma unroll
+                for (int q = 0; q < MB; q++) v[q] = get(top - q >= hi ? top - q : hi);
+#pragma unroll
+                for (int q = 0; q < MB; q++)
+                    if (top - q >= hi) put(top - q + delta, v[q]);
+            }
+        } else if (delta < 0) {
+            for (int b = hi; b < n; b += MB) {
+                uint2 v[MB];
+#pragma unroll
+                for (int q = 0; q < MB; q++) v[q] = get(b + q < n ? b + q : n - 1);
+#pragma unroll
+                for (int q = 0; q < MB; q++)
+                    if (b + q < n) put(b + q + delta, v[q]);
+            }
+        }
         n += delta;
         return true;
     }
