@@ -154,6 +154,13 @@ struct Stream {
         k0 = C.key0; k1 = C.key1; c1 = unit; c2 = sweep; c3 = (C.chain_id << 8) | kind;
         w = 0; blk = 0;
     }
+    // the same, from the chain's keys and id held by the caller
+    PMWA_DEV void init_keys(uint32_t key0, uint32_t key1, uint32_t chain_id, uint32_t sweep, uint32_t kind,
+                            uint32_t unit)
+    {
+        k0 = key0; k1 = key1; c1 = unit; c2 = sweep; c3 = (chain_id << 8) | kind;
+        w = 0; blk = 0;
+    }
     PMWA_DEV uint64_t next()
     {
         uint32_t j = w >> 1;

@@ -536,6 +536,9 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     Stream rs;
     rs.init(C, (uint32_t)P.sweep[bt.x], RNG_R, (uint32_t)((long long)i * C.ntau + k));
     int32_t lo = C.T[k];
+    // read before the loop's event stores, which could alias fields of C
+    const int32_t Tk1 = C.T[k + 1];
+    const int capu = C.cap;
     int p = s_lo;
     int out = 0;
     uint32_t ri = 0;                // interval index: vertices passed so far
@@ -562,7 +565,7 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
         }
         int32_t hi;
         int q, above = 0;
-        if (best < 0) { hi = C.T[k + 1]; q = s_hi; }
+        if (best < 0) { hi = Tk1; q = s_hi; }
         else {
             hi = btk;
             q = (int)((best < 2 ? v >> 30 : v >> 31) & 1u);
@@ -573,7 +576,7 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
         rs.blk = 0;
         const int n = sample_worms(sE, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
         if (n < 0) return;
-        if (out + n + (best >= 0 ? 1 : 0) > C.cap) { atomicOr(flag, FL_OVERFLOW); return; }
+        if (out + n + (best >= 0 ? 1 : 0) > capu) { atomicOr(flag, FL_OVERFLOW); return; }
         ri++;
         int s = p;
         for (int w = 0; w < n; w++) {
@@ -1033,11 +1036,12 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     // chain fields in registers: the loop's global stores could otherwise
     // alias them and force reloads
     const int capc = C.cap;
-    const long long cnt_base = C.cnt_off;
+    const long long cnt_base = C.cnt_off + unit_su(C, k, dsp, 0);
+    const long long ev_base0 = ev_base(C, k, dsp, 0);
     long long nv = 0, nkink = 0, nwc = 0, occ = 0;
     bool bad = false;
     for (int s = lane; s < nloc; s += 64) {
-        const long long ebase = ev_base(C, k, dsp, s);
+        const long long ebase = ev_base0 + s;
         uint32_t* qi = qint + off[s] + s;
         const int qmax = cnt[s] + 1;
         int nq = 0;
@@ -1085,7 +1089,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         nkink += nks;
         nwc += nws;
         if (j > capc) bad = true;
-        P.cnt[cnt_base + unit_su(C, k, dsp, s)] = j > capc ? capc : j;
+        P.cnt[cnt_base + s] = j > capc ? capc : j;
     }
     if (bad) atomicOr(&P.flags[chain], FL_OVERFLOW);
     __syncthreads();
@@ -1254,8 +1258,19 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
     static_assert(1024 % VL == 0, "table copy");
 #pragma unroll
     for (int q = 0; q < 1024 / VL; q++) sE[q * VL + (int)threadIdx.x] = C.F[q * VL + (int)threadIdx.x];
+    // the boundary ticks in LDS and the chain fields the loop reads in
+    // registers: the loop's event stores could alias fields of C, which
+    // would then be read again, after waiting for the stores, at every use
+    __shared__ int32_t sT[NT_MAX + 1];
+    for (int i = (int)threadIdx.x; i <= C.ntau; i += VL) sT[i] = C.T[i];
     __syncthreads();
     if (u >= C.N || !live(P, C, bt.x)) return;
+    const int nloc = C.nloc, cap = C.cap, ndsp = C.ndsp;
+    const int32_t Mt = C.M;
+    const uint32_t key0 = C.key0, key1 = C.key1, cid = C.chain_id;
+    const long long ev_off = C.ev_off, cnt_off = C.cnt_off, bs_off = C.bs_off;
+    auto usu = [&](int kk, int dd, int ss) { return (long long)(kk * ndsp + dd) * nloc + ss; };
+    auto evb = [&](int kk, int dd, int ss) { return ev_off + (long long)(kk * ndsp + dd) * cap * nloc + ss; };
     unsigned int* flag = &P.flags[bt.x];
     const double lambda = C.lambda;
     const int dsp = u / C.nloc, sl = u % C.nloc;
@@ -1266,10 +1281,10 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
     int32_t* o2 = s_off + NWL * VL + threadIdx.x;
     for (int k = 0; k < nt; k++) {
         Stream rs;
-        rs.init(C, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
-        const long long cuk = C.cnt_off + unit_su(C, k, dsp, sl);
-        SiteArr Ak{P.ev + ev_base(C, k, dsp, sl), C.nloc, P.cnt[cuk], C.cap};
-        uint8_t* sk = &P.bs[C.bs_off + unit_su(C, k, dsp, sl)];
+        rs.init_keys(key0, key1, cid, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
+        const long long cuk = cnt_off + usu(k, dsp, sl);
+        SiteArr Ak{P.ev + evb(k, dsp, sl), nloc, P.cnt[cuk], cap};
+        uint8_t* sk = &P.bs[bs_off + usu(k, dsp, sl)];
         if (nt == 1) {
             bool hasv = false;
             for (int j = 0; j < Ak.n; j++) hasv |= !ev_worm(Ak.get(j).y);
@@ -1278,7 +1293,7 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
                 const double W[2] = {1.0, 1.0};
                 const int sp = choose(W, u53(rs.next()));
                 uint64_t d1;
-                const int m = sample_worms<VL>(sE, lambda, rs, C.M, 0, o1, d1, flag);
+                const int m = sample_worms<VL>(sE, lambda, rs, Mt, 0, o1, d1, flag);
                 if (m < 0) return;
                 if (!Ak.resize(0, Ak.n, m)) { atomicOr(flag, FL_OVERFLOW); return; }
                 put_worms<VL>(Ak, 0, 0, o1, d1, m, sp);
@@ -1293,19 +1308,19 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
         int32_t t1;
         int q;
         if (jv < Ak.n) { t1 = (int32_t)Ak.get(jv).x; q = jv > 0 ? (int)ev_up(Ak.get(jv - 1).y) : (int)*sk; }
-        else { t1 = C.T[k + 1]; q = P.bs[C.bs_off + unit_su(C, (k + 1) % nt, dsp, sl)]; }
-        const long long l1 = (long long)t1 - C.T[k];
+        else { t1 = sT[k + 1]; q = P.bs[bs_off + usu((k + 1) % nt, dsp, sl)]; }
+        const long long l1 = (long long)t1 - sT[k];
         // I_2: last vertex of slab k-1 up to the boundary
         const int kp = (k + nt - 1) % nt;
-        const long long cukp = C.cnt_off + unit_su(C, kp, dsp, sl);
-        SiteArr Bk{P.ev + ev_base(C, kp, dsp, sl), C.nloc, P.cnt[cukp], C.cap};
+        const long long cukp = cnt_off + usu(kp, dsp, sl);
+        SiteArr Bk{P.ev + evb(kp, dsp, sl), nloc, P.cnt[cukp], cap};
         int jl = Bk.n - 1;
         while (jl >= 0 && ev_worm(Bk.get(jl).y)) jl--;
         int32_t t2;
         int p;
         if (jl >= 0) { t2 = (int32_t)Bk.get(jl).x; p = (int)ev_up(Bk.get(jl).y); }
-        else { t2 = C.T[kp]; p = P.bs[C.bs_off + unit_su(C, kp, dsp, sl)]; }
-        const long long l2 = (long long)C.T[kp + 1] - t2;
+        else { t2 = sT[kp]; p = P.bs[bs_off + usu(kp, dsp, sl)]; }
+        const long long l2 = (long long)sT[kp + 1] - t2;
         double W[2];
         for (int sp = 0; sp < 2; sp++) W[sp] = fleg(sE, sp ^ q, l1) * fleg(sE, p ^ sp, l2);
         const int sp = choose(W, u53(rs.next()));
@@ -1319,11 +1334,11 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
             if (!Ak.resize(jl + 1, Ak.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
             put_worms<VL>(Ak, jl + 1, t2, o2, d2, m2, p);
             if (!Ak.resize(0, jv, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<VL>(Ak, 0, C.T[k], o1, d1, m1, sp);
+            put_worms<VL>(Ak, 0, sT[k], o1, d1, m1, sp);
             P.cnt[cuk] = Ak.n;
         } else {
             if (!Ak.resize(0, jv, m1) || !Bk.resize(jl + 1, Bk.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<VL>(Ak, 0, C.T[k], o1, d1, m1, sp);
+            put_worms<VL>(Ak, 0, sT[k], o1, d1, m1, sp);
             put_worms<VL>(Bk, jl + 1, t2, o2, d2, m2, p);
             P.cnt[cuk] = Ak.n;
             P.cnt[cukp] = Bk.n;
@@ -1711,10 +1726,14 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     }
     __syncthreads();
     {
+        // (the stride in a register: a field of C read between the stores
+        // would be read again after each of them, since an event store might
+        // change it, and that read would wait for the stores to complete)
+        const long long st = C.nloc;
         uint2* OA = P.ev + ev_base(C, k, dspa, sla);
         uint2* OB = P.ev + ev_base(C, k, dspc, slc);
-        for (int j = lane; j < na2; j += 64) OA[(long long)j * C.nloc] = A2[j];
-        for (int j = lane; j < nb2; j += 64) OB[(long long)j * C.nloc] = B2[j];
+        for (int j = lane; j < na2; j += 64) OA[(long long)j * st] = A2[j];
+        for (int j = lane; j < nb2; j += 64) OB[(long long)j * st] = B2[j];
         if (lane == 0) { P.cnt[cua] = na2; P.cnt[cuc] = nb2; }
     }
 }
@@ -1800,6 +1819,9 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
     // intervals r = 0..nv (below vertex r; the last one ends at T_k+1)
     const uint32_t sweep = (uint32_t)P.sweep[bt.x];
     const uint32_t unit = (uint32_t)((long long)i * C.ntau + k);
+    // read before the event stores below, which could alias fields of C
+    const int capw = C.cap;
+    const int32_t Tk0 = C.T[k], Tk1 = C.T[k + 1];
     const double lambda = C.lambda;
     const int nint = nv + 1;
     int carry = 0;
@@ -1820,7 +1842,7 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
                 const int qq = (int)((d < 2 ? v >> 30 : v >> 31) & 1u);
                 p = qq ^ (int)((v >> 29) & 1u);
             } else {
-                lo = C.T[k];
+                lo = Tk0;
                 p = s_lo;
             }
             int q;
@@ -1833,7 +1855,7 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
                 has_v = true;
                 vinfo = (d << 1) | ((uint32_t)above << 3);
             } else {
-                hi = C.T[k + 1];
+                hi = Tk1;
                 q = s_hi;
             }
             rs.init(C, sweep, RNG_R, unit);
@@ -1845,7 +1867,7 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
         const int incl = wave_incl_sum(x);
         const int pos = carry + incl - x;
         carry += __shfl(incl, 63, 64);
-        const bool fits = r < nint && pos + x <= C.cap;
+        const bool fits = r < nint && pos + x <= capw;
         // slots through the pool; the first pending lane always fits
         // (nwr <= NWL < RW_POOL), so every round makes progress
         const int wst = wave_incl_sum(nwr) - nwr;
@@ -1873,7 +1895,7 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
         if (has_v && fits) E[(long long)(pos + nwr) * st] = make_uint2((uint32_t)hi, vinfo);
     }
     if (__ballot(bad)) return;
-    if (carry > C.cap) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
+    if (carry > capw) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
     if (lane == 0) P.cnt[cu] = carry;
 }
 
