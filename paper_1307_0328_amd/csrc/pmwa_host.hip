@@ -594,7 +594,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         const int mode = h->opts.regen_mode;
         h->regen_wave = mode == 2 || (mode == 0 && units <= 65536);
         h->rw_nmax = 4 * maxcapb;
-        h->rw_lds = (size_t)h->rw_nmax * (2 * sizeof(uint32_t) + 2) + (size_t)RW_POOL * sizeof(int32_t);
+        h->rw_lds = (size_t)((h->rw_nmax + 3) & ~3) * sizeof(uint32_t) +
+                    (size_t)h->rw_nmax * (2 * sizeof(uint32_t) + 2) + (size_t)RW_POOL * sizeof(int32_t);
         if (h->rw_lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_assemble_w, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)h->rw_lds);

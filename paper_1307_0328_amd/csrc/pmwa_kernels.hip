@@ -1756,7 +1756,11 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
     const int u = bt.y;
     const int lane = (int)threadIdx.x;
     if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
-    uint32_t* val = reinterpret_cast<uint32_t*>(smem);
+    // merge keys (a multiple of 4 entries, 16-byte aligned), entries,
+    // merged entries, the worm-offset pool, bond slots of both
+    const int nmax4 = (nmax + 3) & ~3;
+    uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* val = keys + nmax4;
     uint32_t* mval = val + nmax;
     int32_t* pool = reinterpret_cast<int32_t*>(mval + nmax);
     uint8_t* vsl = reinterpret_cast<uint8_t*>(pool + RW_POOL);
@@ -1803,17 +1807,22 @@ __global__ void __launch_bounds__(64) k_assemble_w(Pools P, const int2* __restri
         for (int d2 = 0; d2 < 4; d2++) r += bids[d2] < bids[d] ? 1u : 0u;
         brk |= r << (2 * d);
     }
+    // every entry's key once (padding keys above all of them), then each
+    // entry's rank among them, four keys per LDS read
+    const int nv4 = (nv + 3) & ~3;
+    for (int e = lane; e < nv4; e += 64)
+        keys[e] = e < nv ? ((val[e] & BV_TICK) << 2) | ((brk >> (2 * (uint32_t)vsl[e])) & 3u) : 0xFFFFFFFFu;
+    __syncthreads();
+    const uint4* keys4 = reinterpret_cast<const uint4*>(keys);
     for (int e = lane; e < nv; e += 64) {
-        const uint32_t v = val[e];
-        const uint32_t dme = vsl[e];
-        const uint32_t key = ((v & BV_TICK) << 2) | ((brk >> (2 * dme)) & 3u);
+        const uint32_t key = keys[e];
         int rank = 0;
-        for (int e2 = 0; e2 < nv; e2++) {
-            const uint32_t key2 = ((val[e2] & BV_TICK) << 2) | ((brk >> (2 * (uint32_t)vsl[e2])) & 3u);
-            rank += key2 < key ? 1 : 0;
+        for (int e4 = 0; e4 < nv4 / 4; e4++) {
+            const uint4 q = keys4[e4];
+            rank += (q.x < key ? 1 : 0) + (q.y < key ? 1 : 0) + (q.z < key ? 1 : 0) + (q.w < key ? 1 : 0);
         }
-        mval[rank] = v;
-        msl[rank] = (uint8_t)dme;
+        mval[rank] = val[e];
+        msl[rank] = vsl[e];
     }
     __syncthreads();
     // intervals r = 0..nv (below vertex r; the last one ends at T_k+1)
