@@ -1199,13 +1199,15 @@ struct SiteArr {
     PMWA_DEV uint2 get(int j) const { return e[(long long)j * st]; }
     PMWA_DEV void put(int j, uint2 v) { e[(long long)j * st] = v; }
     // resize the range [lo, hi) to m entries (contents of the new range
-    // undefined), moving the events above it.  They move 16 at a time: a
+    // undefined), moving the events above it.  They move 32 at a time: a
     // chunk's loads (from positions clamped to the events that move) are all
     // issued before its stores, so one round trip to memory serves the chunk,
-    // and no chunk stores over an event that a later chunk still loads.
+    // and no chunk stores over an event that a later chunk still loads.  (A
+    // chunk after the first waits for the earlier stores: loads and stores
+    // share one counter of outstanding vector memory operations.)
     PMWA_DEV bool resize(int lo, int hi, int m)
     {
-        constexpr int MB = 16;
+        constexpr int MB = 32;
         const int delta = m - (hi - lo);
         if (n + delta > cap) return false;
         if (delta > 0) {
@@ -1732,6 +1734,9 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
         const long long st = C.nloc;
         uint2* OA = P.ev + ev_base(C, k, dspa, sla);
         uint2* OB = P.ev + ev_base(C, k, dspc, slc);
+        // both addresses before the first store (computed after it, their
+        // loads would wait for the stores to complete)
+        asm volatile("" ::"v"(OA), "v"(OB), "v"(st));
         for (int j = lane; j < na2; j += 64) OA[(long long)j * st] = A2[j];
         for (int j = lane; j < nb2; j += 64) OB[(long long)j * st] = B2[j];
         if (lane == 0) { P.cnt[cua] = na2; P.cnt[cuc] = nb2; }
