@@ -329,7 +329,7 @@ PMWA_DEV int vertex_exact(const ChainDev& C, const BondCtx& B, const Lst& LA, co
 // which is allocated), so that one round trip to memory serves the batch;
 // only the events inside the lists count.  Returns the two counts (which may
 // exceed rows).
-PMWA_DEV int2 stage_flips2(const uint2* EA, int na, int sa0, uint32_t* FA,
+PMWA_DEV int2 stage_flips(const uint2* EA, int na, int sa0, uint32_t* FA,
                            const uint2* EC, int nc, int sc0, uint32_t* FC, int st, int rows)
 {
     constexpr int SB = 16;
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         B.sc0 = P.bs[C.bs_off + unit_su(C, k, dspc, slc)];
         const uint2* Ea = P.ev + ev_base(C, k, dsp, sl);
         const uint2* Ec = P.ev + ev_base(C, k, dspc, slc);
-        const int2 nf2 = stage_flips2(Ea, na, B.sa0, FA, Ec, nc, B.sc0, FC, B.st, rows);
+        const int2 nf2 = stage_flips(Ea, na, B.sa0, FA, Ec, nc, B.sc0, FC, B.st, rows);
         const int nfa = nf2.x, nfc = nf2.y;
         // a column is used only with a row to spare: once a count reaches
         // `rows`, later events land on the last row, which then no longer
