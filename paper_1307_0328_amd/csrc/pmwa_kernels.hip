@@ -1103,7 +1103,10 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         const long long ell = (long long)(q >> 1);
         const double m = em1(sE, ell);
         const double num = m * (2.0 + m), den = 2.0 * (1.0 + m) + m * m;
-        const double term = (double)ell * ((q & 1u) ? den / num : num / den);
+        // the operands selected first: one division, and no branch that
+        // would run both divisions for a mix of parities
+        const bool odd = (q & 1u) != 0u;
+        const double term = (double)ell * ((odd ? den : num) / (odd ? num : den));
         qimp += ell > 0 ? term : 0.0;
     }
     for (int o = 32; o > 0; o >>= 1) {
