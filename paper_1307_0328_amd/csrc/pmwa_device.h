@@ -260,10 +260,12 @@ PMWA_DEV double em1(const double* __restrict__ F, long long ell)
 }
 PMWA_DEV double fleg(const double* __restrict__ E, int sigma, long long ell)
 {
-    double m = em1(E, ell);
-    double d = 2.0 * (1.0 + m);
-    if (sigma) return (m * (2.0 + m)) / d;
-    return 1.0 + (m * m) / d;
+    const double m = em1(E, ell);
+    const double d = 2.0 * (1.0 + m);
+    // the numerator selected first: one division whatever the mix of sigma
+    // over a wavefront (sinh: m (2 + m) / d, cosh: 1 + m m / d)
+    const double r = (sigma ? m * (2.0 + m) : m * m) / d;
+    return sigma ? r : 1.0 + r;
 }
 PMWA_DEV double tanh_ell(const double* __restrict__ E, long long ell)
 {
