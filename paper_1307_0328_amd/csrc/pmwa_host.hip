@@ -25,6 +25,7 @@ __global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows
 __global__ void k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
+template <int LANES>
 __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
 __global__ void k_green(Pools P, int chain, const int4* __restrict__ disp, int nd, int nchunk,
                         double* __restrict__ part);
@@ -83,6 +84,7 @@ struct pmwa_handle {
     size_t rw_lds = 0;
     size_t lds_bytes = 0;
     size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
+    int bt_lanes = 64;       // lanes per workgroup of the temporal-boundary update (64 or 16)
     int vs = 1;              // candidate column length of the vertex kernel
     int v_rows = 1;          // flips per site staged in LDS by the vertex kernel
     size_t v_lds = 0;
@@ -357,7 +359,12 @@ static int launch_kernel(pmwa_t* h, int phase)
         if (h->nblk_s) hipLaunchKernelGGL(k_scatter, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
         break;
     case 4:
-        if (h->nblk_bt) hipLaunchKernelGGL(k_btemporal, dim3(h->nblk_bt), dim3(VL), 0, s, h->P, h->d_blk_bt);
+        if (h->nblk_bt) {
+            if (h->bt_lanes == 16)
+                hipLaunchKernelGGL(k_btemporal<16>, dim3(h->nblk_bt), dim3(16), 0, s, h->P, h->d_blk_bt);
+            else
+                hipLaunchKernelGGL(k_btemporal<64>, dim3(h->nblk_bt), dim3(64), 0, s, h->P, h->d_blk_bt);
+        }
         break;
     case 5:
         if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsx, 0);
@@ -579,7 +586,14 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (!r2) { block_table(h->ch, VL, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
     if (!r2) { block_table(h->ch, 64, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_dom, t); r2 = upload_table(t, &h->d_blk_s, &h->nblk_s); }
-    if (!r2) { block_table(h->ch, VL, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
+    {
+        // the temporal update in 16-lane groups where 64-lane ones would
+        // leave CUs idle (fewer units than 64 per CU)
+        int64_t units = 0;
+        for (auto& hc : h->ch) units += hc.n_bt;
+        h->bt_lanes = units < 64LL * std::max(prop.multiProcessorCount, 1) ? 16 : 64;
+    }
+    if (!r2) { block_table(h->ch, h->bt_lanes, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
     if (!r2) { block_table(h->ch, 1, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
     {

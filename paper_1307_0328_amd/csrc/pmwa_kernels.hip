@@ -1252,22 +1252,28 @@ PMWA_DEV void put_worms(SiteArr& A, int j0, int32_t base, const int32_t* off, ui
 // Step 1, Eq. (Para): one lane per site, temporal boundaries k = 0.. in order;
 // the upper domain's stream (site, k) makes the choice, then the worms of the
 // two legs I_1 (above) and I_2 (below) are regenerated.
-__global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restrict__ blk)
+template <int LANES>
+__global__ void __launch_bounds__(LANES) k_btemporal(Pools P, const int2* __restrict__ blk)
 {
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    __shared__ double sE[1024];
-    __shared__ int32_t s_off[2 * NWL * VL];
-    // (unrolled, so that the loads are in flight together)
-    static_assert(1024 % VL == 0, "table copy");
+    // full wavefronts copy the expm1 table to LDS (unrolled, the loads in
+    // flight together); 16-lane groups, used where 64-lane ones would leave
+    // most CUs idle, read it from L2 (a copy per small group costs more)
+    const double* sE = C.F;
+    if constexpr (LANES == 64) {
+        __shared__ double sEl[1024];
 #pragma unroll
-    for (int q = 0; q < 1024 / VL; q++) sE[q * VL + (int)threadIdx.x] = C.F[q * VL + (int)threadIdx.x];
+        for (int q = 0; q < 16; q++) sEl[q * 64 + (int)threadIdx.x] = C.F[q * 64 + (int)threadIdx.x];
+        sE = sEl;
+    }
+    __shared__ int32_t s_off[2 * NWL * LANES];
     // the boundary ticks in LDS and the chain fields the loop reads in
     // registers: the loop's event stores could alias fields of C, which
     // would then be read again, after waiting for the stores, at every use
     __shared__ int32_t sT[NT_MAX + 1];
-    for (int i = (int)threadIdx.x; i <= C.ntau; i += VL) sT[i] = C.T[i];
+    for (int i = (int)threadIdx.x; i <= C.ntau; i += LANES) sT[i] = C.T[i];
     __syncthreads();
     if (u >= C.N || !live(P, C, bt.x)) return;
     const int nloc = C.nloc, cap = C.cap, ndsp = C.ndsp;
@@ -1283,7 +1289,7 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
     const int nt = C.ntau;
     const uint32_t sweep = (uint32_t)P.sweep[bt.x];
     int32_t* o1 = s_off + threadIdx.x;
-    int32_t* o2 = s_off + NWL * VL + threadIdx.x;
+    int32_t* o2 = s_off + NWL * LANES + threadIdx.x;
     for (int k = 0; k < nt; k++) {
         Stream rs;
         rs.init_keys(key0, key1, cid, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
@@ -1298,10 +1304,10 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
                 const double W[2] = {1.0, 1.0};
                 const int sp = choose(W, u53(rs.next()));
                 uint64_t d1;
-                const int m = sample_worms<VL>(sE, lambda, rs, Mt, 0, o1, d1, flag);
+                const int m = sample_worms<LANES>(sE, lambda, rs, Mt, 0, o1, d1, flag);
                 if (m < 0) return;
                 if (!Ak.resize(0, Ak.n, m)) { atomicOr(flag, FL_OVERFLOW); return; }
-                put_worms<VL>(Ak, 0, 0, o1, d1, m, sp);
+                put_worms<LANES>(Ak, 0, 0, o1, d1, m, sp);
                 P.cnt[cuk] = Ak.n;
                 *sk = (uint8_t)sp;
                 continue;
@@ -1330,27 +1336,29 @@ __global__ void __launch_bounds__(VL) k_btemporal(Pools P, const int2* __restric
         for (int sp = 0; sp < 2; sp++) W[sp] = fleg(sE, sp ^ q, l1) * fleg(sE, p ^ sp, l2);
         const int sp = choose(W, u53(rs.next()));
         uint64_t d1, d2;
-        const int m1 = sample_worms<VL>(sE, lambda, rs, l1, sp ^ q, o1, d1, flag);
+        const int m1 = sample_worms<LANES>(sE, lambda, rs, l1, sp ^ q, o1, d1, flag);
         if (m1 < 0) return;
-        const int m2 = sample_worms<VL>(sE, lambda, rs, l2, p ^ sp, o2, d2, flag);
+        const int m2 = sample_worms<LANES>(sE, lambda, rs, l2, p ^ sp, o2, d2, flag);
         if (m2 < 0) return;
         if (nt == 1) {
             // same array: suffix first, then prefix
             if (!Ak.resize(jl + 1, Ak.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<VL>(Ak, jl + 1, t2, o2, d2, m2, p);
+            put_worms<LANES>(Ak, jl + 1, t2, o2, d2, m2, p);
             if (!Ak.resize(0, jv, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<VL>(Ak, 0, sT[k], o1, d1, m1, sp);
+            put_worms<LANES>(Ak, 0, sT[k], o1, d1, m1, sp);
             P.cnt[cuk] = Ak.n;
         } else {
             if (!Ak.resize(0, jv, m1) || !Bk.resize(jl + 1, Bk.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<VL>(Ak, 0, sT[k], o1, d1, m1, sp);
-            put_worms<VL>(Bk, jl + 1, t2, o2, d2, m2, p);
+            put_worms<LANES>(Ak, 0, sT[k], o1, d1, m1, sp);
+            put_worms<LANES>(Bk, jl + 1, t2, o2, d2, m2, p);
             P.cnt[cuk] = Ak.n;
             P.cnt[cukp] = Bk.n;
         }
         *sk = (uint8_t)sp;
     }
 }
+template __global__ void k_btemporal<64>(Pools, const int2* __restrict__);
+template __global__ void k_btemporal<16>(Pools, const int2* __restrict__);
 
 // Step 2, Eq. (ParaSpace): one wavefront per (bond crossing a spatial domain
 // boundary in direction d, slab); the bond is owned by the left/lower
