@@ -171,7 +171,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the sweep has no multi-GPU path)"}))
         log("bench.py: only --gpus 1 is supported (one GPU per process, no multi-GPU path)")
         sys.exit(2)
 
