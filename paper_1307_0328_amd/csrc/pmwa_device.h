@@ -30,7 +30,8 @@ namespace pmwa {
 constexpr int NT_MAX = 64;      // temporal domains
 constexpr int KMAXC = 256;      // Poisson table entries = max candidates per bond-slab
 constexpr int NWL = 48;         // worms drawn on one interval
-constexpr int RW_POOL = 256;    // worm-offset pool of the wavefront re-generation
+constexpr int RW_POOL = 64;     // worm-offset pool of the wavefront re-generation and the
+                                // spatial update (above NWL: the first pending lane always fits)
 // lanes per workgroup of the lane-per-unit kernels (vertex phase, temporal
 // boundaries).  Full wavefronts: with fewer lanes the same work takes more
 // memory and LDS instructions per CU, which measured slower than leaving
