@@ -56,46 +56,64 @@ OBS_DTYPE = np.dtype([("nv", "<i8"), ("nkink", "<i8"), ("nw", "<i8"),
 _lib = None
 
 
+def bind(path: str):
+    """Load an oracle library built from pmwa_oracle.c and declare its
+    signatures (lib() uses this for the in-tree build)."""
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.orc_create.argtypes = [P(Params), P(C.c_void_p)]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_sweep.argtypes = [C.c_void_p, C.c_int64]
+    L.orc_phase.argtypes = [C.c_void_p, C.c_int]
+    L.orc_series.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+    L.orc_series.restype = C.c_int64
+    L.orc_flags.argtypes = [C.c_void_p]
+    L.orc_state_events.argtypes = [C.c_void_p]
+    L.orc_state_events.restype = C.c_int64
+    L.orc_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_int64, P(C.c_uint64)]
+    L.orc_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_int64, C.c_uint64]
+    L.orc_check.argtypes = [C.c_void_p]
+    L.orc_get_derived.argtypes = [C.c_void_p, P(Derived)]
+    L.orc_get_scatter_table.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_vertex_weight.argtypes = [C.c_void_p, C.c_int]
+    L.orc_vertex_weight.restype = C.c_double
+    L.orc_fleg.argtypes = [C.c_void_p, C.c_int, C.c_int64]
+    L.orc_fleg.restype = C.c_double
+    L.orc_tanh_ell.argtypes = [C.c_void_p, C.c_int64]
+    L.orc_tanh_ell.restype = C.c_double
+    L.orc_poisson_table.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
+    L.orc_test_worms.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int32, C.c_int,
+                                 C.c_void_p, C.c_void_p, C.c_int]
+    L.orc_test_choose.argtypes = [C.c_void_p, C.c_int, C.c_double]
+    L.orc_test_temporal_p0.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int64]
+    L.orc_test_temporal_p0.restype = C.c_double
+    L.orc_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_stream_word.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint64]
+    L.orc_stream_word.restype = C.c_uint64
+    L.orc_green.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB_PATH)
-        P = C.POINTER
-        L.orc_create.argtypes = [P(Params), P(C.c_void_p)]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_sweep.argtypes = [C.c_void_p, C.c_int64]
-        L.orc_phase.argtypes = [C.c_void_p, C.c_int]
-        L.orc_series.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
-        L.orc_series.restype = C.c_int64
-        L.orc_flags.argtypes = [C.c_void_p]
-        L.orc_state_events.argtypes = [C.c_void_p]
-        L.orc_state_events.restype = C.c_int64
-        L.orc_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, C.c_int64, P(C.c_uint64)]
-        L.orc_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, C.c_int64, C.c_uint64]
-        L.orc_check.argtypes = [C.c_void_p]
-        L.orc_get_derived.argtypes = [C.c_void_p, P(Derived)]
-        L.orc_get_scatter_table.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_vertex_weight.argtypes = [C.c_void_p, C.c_int]
-        L.orc_vertex_weight.restype = C.c_double
-        L.orc_fleg.argtypes = [C.c_void_p, C.c_int, C.c_int64]
-        L.orc_fleg.restype = C.c_double
-        L.orc_tanh_ell.argtypes = [C.c_void_p, C.c_int64]
-        L.orc_tanh_ell.restype = C.c_double
-        L.orc_poisson_table.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
-        L.orc_test_worms.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int32, C.c_int,
-                                     C.c_void_p, C.c_void_p, C.c_int]
-        L.orc_test_choose.argtypes = [C.c_void_p, C.c_int, C.c_double]
-        L.orc_test_temporal_p0.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int64]
-        L.orc_test_temporal_p0.restype = C.c_double
-        L.orc_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_stream_word.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint64]
-        L.orc_stream_word.restype = C.c_uint64
-        L.orc_green.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
-        _lib = L
+        _lib = bind(LIB_PATH)
     return _lib
+
+
+def compile_variant(src_text: str, out_path: str) -> str:
+    """Compile a (modified) copy of the oracle source to `out_path`, with the
+    flags of build(); tests use it to check that a pin catches a planted
+    mistake."""
+    c_path = out_path[:-3] + ".c" if out_path.endswith(".so") else out_path + ".c"
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-w",
+                           "-I", HERE, "-o", out_path, c_path, "-lm"])
+    return out_path
 
 
 def make_params(**kw) -> Params:
@@ -122,10 +140,11 @@ def philox(ctr, key):
 class Chain:
     """One oracle chain; mirrors the C-ABI calls of the GPU library."""
 
-    def __init__(self, params: Params | None = None, **kw):
+    def __init__(self, params: Params | None = None, library=None, **kw):
         self.params = params if params is not None else make_params(**kw)
+        self._L = library if library is not None else lib()
         h = C.c_void_p()
-        rc = lib().orc_create(C.byref(self.params), C.byref(h))
+        rc = self._L.orc_create(C.byref(self.params), C.byref(h))
         if rc != 0:
             raise ValueError(f"orc_create failed ({rc})")
         self.h = h
@@ -134,7 +153,7 @@ class Chain:
 
     def close(self):
         if self.h:
-            lib().orc_destroy(self.h)
+            self._L.orc_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -144,20 +163,20 @@ class Chain:
             pass
 
     def sweep(self, n=1):
-        rc = lib().orc_sweep(self.h, n)
+        rc = self._L.orc_sweep(self.h, n)
         if rc != 0:
             raise RuntimeError(f"orc_sweep failed ({rc}), flags={self.flags()}")
 
     def phase(self, ph):
-        rc = lib().orc_phase(self.h, ph)
+        rc = self._L.orc_phase(self.h, ph)
         if rc != 0:
             raise RuntimeError(f"orc_phase({ph}) failed ({rc}), flags={self.flags()}")
 
     def flags(self):
-        return lib().orc_flags(self.h)
+        return self._L.orc_flags(self.h)
 
     def check(self):
-        return lib().orc_check(self.h)
+        return self._L.orc_check(self.h)
 
     def series(self, max_rows=1 << 30):
         n_total = max_rows
@@ -165,7 +184,7 @@ class Chain:
         chunks = []
         while n_total > 0:
             buf = np.zeros(min(n_total, 1 << 16), dtype=OBS_DTYPE)
-            n = lib().orc_series(self.h, buf.ctypes.data, len(buf))
+            n = self._L.orc_series(self.h, buf.ctypes.data, len(buf))
             if n <= 0:
                 break
             chunks.append(buf[:n])
@@ -175,13 +194,13 @@ class Chain:
         return np.concatenate(chunks) if chunks else out
 
     def get_state(self):
-        ne = lib().orc_state_events(self.h)
+        ne = self._L.orc_state_events(self.h)
         bstate = np.zeros(self.N * self.ntau, np.uint8)
         counts = np.zeros(self.N * self.ntau, np.int32)
         ticks = np.zeros(max(ne, 1), np.int32)
         infos = np.zeros(max(ne, 1), np.uint32)
         sw = C.c_uint64()
-        rc = lib().orc_get_state(self.h, bstate.ctypes.data, counts.ctypes.data,
+        rc = self._L.orc_get_state(self.h, bstate.ctypes.data, counts.ctypes.data,
                                  ticks.ctypes.data, infos.ctypes.data, ne, C.byref(sw))
         if rc != 0:
             raise RuntimeError("orc_get_state failed")
@@ -193,7 +212,7 @@ class Chain:
         counts = np.ascontiguousarray(st["counts"], np.int32)
         ticks = np.ascontiguousarray(st["ticks"], np.int32)
         infos = np.ascontiguousarray(st["infos"], np.uint32)
-        rc = lib().orc_set_state(self.h, bstate.ctypes.data, counts.ctypes.data,
+        rc = self._L.orc_set_state(self.h, bstate.ctypes.data, counts.ctypes.data,
                                  ticks.ctypes.data, infos.ctypes.data, len(ticks),
                                  int(st["sweep"]))
         if rc != 0:
@@ -201,38 +220,38 @@ class Chain:
 
     def derived(self):
         d = Derived()
-        lib().orc_get_derived(self.h, C.byref(d))
+        self._L.orc_get_derived(self.h, C.byref(d))
         return d
 
     def scatter_table(self):
         tab = np.zeros((16, 4, 4))
         pair = np.zeros((16, 4, 4))
-        lib().orc_get_scatter_table(self.h, tab.ctypes.data, pair.ctypes.data)
+        self._L.orc_get_scatter_table(self.h, tab.ctypes.data, pair.ctypes.data)
         return tab, pair
 
     def vertex_weight(self, S):
-        return lib().orc_vertex_weight(self.h, S)
+        return self._L.orc_vertex_weight(self.h, S)
 
     def fleg(self, sigma, ell):
-        return lib().orc_fleg(self.h, sigma, ell)
+        return self._L.orc_fleg(self.h, sigma, ell)
 
     def tanh_ell(self, ell):
-        return lib().orc_tanh_ell(self.h, ell)
+        return self._L.orc_tanh_ell(self.h, ell)
 
     def poisson_table(self, k=0):
         buf = np.zeros(1024)
-        n = lib().orc_poisson_table(self.h, k, buf.ctypes.data, 1024)
+        n = self._L.orc_poisson_table(self.h, k, buf.ctypes.data, 1024)
         return buf[:n]
 
     def sample_worms(self, unit, ell, sigma, phase=RNG_R):
         off = np.zeros(4096, np.int32)
         dirs = np.zeros(4096, np.uint8)
-        n = lib().orc_test_worms(self.h, phase, unit, ell, sigma, off.ctypes.data,
+        n = self._L.orc_test_worms(self.h, phase, unit, ell, sigma, off.ctypes.data,
                                  dirs.ctypes.data, 4096)
         return off[:n].copy(), dirs[:n].copy()
 
     def temporal_p0(self, p, q, l1, l2):
-        return lib().orc_test_temporal_p0(self.h, p, q, l1, l2)
+        return self._L.orc_test_temporal_p0(self.h, p, q, l1, l2)
 
     def green(self, disps):
         """Green function G(r, dt) of b + b^+ on the current configuration,
@@ -240,12 +259,12 @@ class Chain:
         rows = [tuple(int(v) for v in dd) + (0,) * (3 - len(dd)) for dd in disps]
         d = np.ascontiguousarray(np.array(rows, dtype=np.int64).reshape(-1, 3), dtype=np.int32)
         out = np.zeros(len(d))
-        if lib().orc_green(self.h, d.ctypes.data, len(d), out.ctypes.data) != 0:
+        if self._L.orc_green(self.h, d.ctypes.data, len(d), out.ctypes.data) != 0:
             raise RuntimeError("orc_green failed")
         return out
 
     def stream_word(self, phase, unit, w):
-        return int(lib().orc_stream_word(self.h, phase, unit, w))
+        return int(self._L.orc_stream_word(self.h, phase, unit, w))
 
 
 def choose(weights, u):
