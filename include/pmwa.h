@@ -54,7 +54,17 @@ enum {
     PMWA_ESTATE = -5      /* inconsistent state (set_state input, sampler) */
 };
 
-/* One chain (one Markov chain of one lattice).  Copied at create. */
+/* One chain (one Markov chain of one lattice).  Copied at create.
+   Besides the per-field limits below, pmwa_create and pmwa_slot_load return
+   PMWA_EINVAL for a chain outside the limits of this implementation:
+     eta * beta <= 8 (the worms drawn on one interval fit the sampler);
+     the Poisson table of candidate counts per bond and slab has at most 256
+       entries (mean rho_max * beta / dom_tau up to about 200);
+     N = Lx*Ly < 2^28; C > max E_b (every diagonal weight positive);
+     n_cycle (given or default) in 1..10^7;
+     events per (site, slab) <= 32767 (opts.event_cap, or the default from
+       the expected density), and the spatial-boundary kernel's LDS for that
+       capacity <= 160 KB. */
 typedef struct pmwa_params {
     int32_t  Lx, Ly;          /* periodic Lx x Ly square lattice, each >= 3       */
     double   beta;            /* inverse temperature (beta*t with t = 1)          */
@@ -95,6 +105,37 @@ typedef struct pmwa_obs {
                         g_1 = coth: the improved worm-density estimator (S-I) */
 } pmwa_obs;
 
+/* Sums over the accumulated sweeps of one chain (see pmwa_observables). */
+typedef struct pmwa_obs_acc {
+    int64_t sweeps;                        /* sweeps accumulated                */
+    int64_t nv, nkink, nw, occ2, nn2;      /* sums of the pmwa_obs fields       */
+    double  qimp;
+    double  nv_sq, nkink_sq, nw_sq, occ2_sq, nn2_sq, qimp_sq;  /* sums of squares,
+                                              each term (double)x * (double)x  */
+} pmwa_obs_acc;
+
+/* Thermal averages per site from the accumulated sums (the estimators of
+   the expansion of Tr exp(-beta H_eta) with non-negative weights, and the
+   improved worm-density estimator of Supplemental S-I).  With S = sweeps,
+   N = Lx*Ly sites, N_b = 2N bonds, M = 2^ticks_log2, <x> = sum_x / S:
+     E        = C N_b / N - <nv> / (beta N)             energy of H per site
+     E_alt    = (V <nn2> - mu <occ2>) / (2 M N) - <nkink> / (beta N)
+                                                        (same mean, from the
+                                                        diagonal and kink terms)
+     E_eta    = E - <nw> / (beta N)                     <H_eta> per site
+     density  = <occ2> / (2 M N)                        <n_i>
+     Q        = <nw> / (beta eta N)                     <b_i + b_i^+> (worm count)
+     Q_imp    = <qimp> / (M N)                          the same, improved estimator
+     b        = Q_imp / 2                               <b_i>
+   The err_* fields are standard errors of the means computed from the sums
+   of squares as if the sweeps were independent (no autocorrelation
+   correction; bin the pmwa_measure records for that). */
+typedef struct pmwa_summary {
+    pmwa_obs_acc acc;
+    double E, E_alt, E_eta, density, Q, Q_imp, b;
+    double err_E, err_density, err_Q, err_Q_imp;
+} pmwa_summary;
+
 /* Derived constants of one chain. */
 typedef struct pmwa_info {
     double  C, rho_max, delta, lambda;    /* Delta = beta/M, lambda = eta Delta */
@@ -129,6 +170,33 @@ int pmwa_measure(pmwa_t* h, int chain, pmwa_obs* out, int64_t max_rows,
 
 /* Synchronise; return 0 or the first error raised on the device. */
 int pmwa_status(pmwa_t* h);
+
+/* Synchronise; return 0 or the error raised on the device for `chain` only
+   (PMWA_EOVERFLOW, PMWA_ESTATE).  A flagged chain stops advancing; the other
+   chains of the handle are unaffected. */
+int pmwa_chain_status(pmwa_t* h, int chain);
+
+/* Accumulated observables of `chain` (synchronises).  Every sweep's record
+   is added on the device at the end of the sweep (k_finish), in sweep order;
+   pmwa_reset_observables restarts the accumulation of every chain of the
+   handle with the next sweep enqueued (stream ordered; use it after the
+   thermalisation sweeps).  A slot load restarts that slot's accumulation.
+   out->acc.sweeps = 0 gives NaN averages.  PMWA_EOVERFLOW / PMWA_ESTATE if
+   the chain is flagged (out is still filled). */
+int pmwa_observables(pmwa_t* h, int chain, pmwa_summary* out);
+int pmwa_reset_observables(pmwa_t* h);
+
+/* 64-bit hash of the canonical state of `chain` (synchronises; computed on
+   the device).  With mix(z) the SplitMix64 finaliser (z ^= z >> 30;
+   z *= 0xbf58476d1ce4e5b9; z ^= z >> 27; z *= 0x94d049bb133111eb;
+   z ^= z >> 31) and u = k*N + site (slab k, site index y*Lx + x):
+     hash = sum over (k, site) of mix((u << 20) ^ (count << 1) ^ bstate)
+          + sum over its events j of
+                mix(mix((u << 15) | j) ^ ((uint64_t)tick << 4 | info))
+   modulo 2^64 (an order-free sum, so a parallel reduction computes it
+   exactly).  count, tick and info are those of pmwa_get_state; the sweep
+   counter is not part of it. */
+int pmwa_state_hash(pmwa_t* h, int chain, uint64_t* out);
 
 /* Canonical state of one chain (synchronises).  Layout:
      bstate[k*N + site]   occupation just above temporal boundary k (uint8)
@@ -179,6 +247,9 @@ int pmwa_create_slots(const pmwa_params* shapes, int n_slots, const pmwa_opts* o
 int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_sweeps);
 int pmwa_slot_release(pmwa_t* h, int slot);
 int pmwa_slot_progress(pmwa_t* h, int slot, int64_t* sweeps_done);
+/* 0 if the chain `p` fits slot `slot` (the check of pmwa_slot_load, without
+   loading), PMWA_EINVAL otherwise. */
+int pmwa_slot_fits(pmwa_t* h, int slot, const pmwa_params* p);
 
 /* Scattering-phase diagnostics of the last sweep of `chain` (synchronises):
    out[0] evaluation windows summed over domains, out[1] the most windows in

@@ -50,6 +50,13 @@ class Derived(C.Structure):
                 ("T", C.c_int32 * 65)]
 
 
+class Summary(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("sweeps", "nv", "nkink", "nw", "occ2", "nn2")] + \
+               [(n, C.c_double) for n in ("qimp", "nv_sq", "nkink_sq", "nw_sq", "occ2_sq", "nn2_sq",
+                                          "qimp_sq", "E", "E_alt", "E_eta", "density", "Q", "Q_imp",
+                                          "b", "err_E", "err_density", "err_Q", "err_Q_imp")]
+
+
 OBS_DTYPE = np.dtype([("nv", "<i8"), ("nkink", "<i8"), ("nw", "<i8"),
                       ("occ2", "<i8"), ("nn2", "<i8"), ("qimp", "<f8")])
 
@@ -93,6 +100,11 @@ def bind(path: str):
     L.orc_stream_word.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint64]
     L.orc_stream_word.restype = C.c_uint64
     L.orc_green.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    L.orc_observables.argtypes = [C.c_void_p, P(Summary)]
+    L.orc_reset_observables.argtypes = [C.c_void_p]
+    L.orc_reset_observables.restype = None
+    L.orc_state_hash.argtypes = [C.c_void_p]
+    L.orc_state_hash.restype = C.c_uint64
     return L
 
 
@@ -262,6 +274,18 @@ class Chain:
         if self._L.orc_green(self.h, d.ctypes.data, len(d), out.ctypes.data) != 0:
             raise RuntimeError("orc_green failed")
         return out
+
+    def observables(self):
+        """Accumulated sums and the per-site thermal averages (dict)."""
+        out = Summary()
+        self._L.orc_observables(self.h, C.byref(out))
+        return {n: getattr(out, n) for n, _ in Summary._fields_}
+
+    def reset_observables(self):
+        self._L.orc_reset_observables(self.h)
+
+    def state_hash(self):
+        return int(self._L.orc_state_hash(self.h))
 
     def stream_word(self, phase, unit, w):
         return int(self._L.orc_stream_word(self.h, phase, unit, w))

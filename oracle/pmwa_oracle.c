@@ -85,6 +85,7 @@ struct orc_chain {
 
     orc_obs cur;               /* measurement of the sweep in progress */
     orc_obs* series; int64_t nseries, capseries;
+    orc_summary sums;          /* sums and squares of the recorded sweeps */
 };
 
 #define KMAX 1024
@@ -1229,7 +1230,54 @@ static void record(orc_chain* c)
         c->series = s; c->capseries = cap;
     }
     c->series[c->nseries++] = c->cur;
+    /* running sums and sums of squares, in sweep order */
+    orc_summary* a = &c->sums;
+    const orc_obs* o = &c->cur;
+    a->sweeps += 1;
+    a->nv += o->nv; a->nkink += o->nkink; a->nw += o->nw; a->occ2 += o->occ2; a->nn2 += o->nn2;
+    a->qimp = a->qimp + o->qimp;
+    a->nv_sq = a->nv_sq + (double)o->nv * (double)o->nv;
+    a->nkink_sq = a->nkink_sq + (double)o->nkink * (double)o->nkink;
+    a->nw_sq = a->nw_sq + (double)o->nw * (double)o->nw;
+    a->occ2_sq = a->occ2_sq + (double)o->occ2 * (double)o->occ2;
+    a->nn2_sq = a->nn2_sq + (double)o->nn2 * (double)o->nn2;
+    a->qimp_sq = a->qimp_sq + o->qimp * o->qimp;
     memset(&c->cur, 0, sizeof(c->cur));
+}
+
+void orc_reset_observables(orc_chain* c) { memset(&c->sums, 0, sizeof(c->sums)); }
+
+static double sem(double sum, double sq, double S)
+{
+    if (!(S > 1.0)) return NAN;
+    double m = sum / S;
+    double var = sq / S - m * m;
+    return sqrt((var > 0.0 ? var : 0.0) / (S - 1.0));
+}
+
+/* the estimators of the expansion of Tr exp(-beta H_eta) (C N_b - <number
+   of operators>/beta for H_eta, <N_w>/beta for eta Q) and the improved
+   worm-density estimator of Supplemental S-I */
+int orc_observables(const orc_chain* c, orc_summary* out)
+{
+    *out = c->sums;
+    double S = (double)c->sums.sweeps, N = (double)c->N, M = (double)c->M;
+    double beta = c->p.beta, eta = c->p.eta, V = c->p.V, mu = c->p.mu;
+    double m_nv = (double)c->sums.nv / S, m_nk = (double)c->sums.nkink / S;
+    double m_nw = (double)c->sums.nw / S, m_occ = (double)c->sums.occ2 / S;
+    double m_nn = (double)c->sums.nn2 / S, m_q = c->sums.qimp / S;
+    out->E = 2.0 * c->C - m_nv / (beta * N);
+    out->E_alt = (V * m_nn - mu * m_occ) / (2.0 * M * N) - m_nk / (beta * N);
+    out->E_eta = out->E - m_nw / (beta * N);
+    out->density = m_occ / (2.0 * M * N);
+    out->Q = m_nw / (beta * eta * N);
+    out->Q_imp = m_q / (M * N);
+    out->b = 0.5 * out->Q_imp;
+    out->err_E = sem((double)c->sums.nv, c->sums.nv_sq, S) / (beta * N);
+    out->err_density = sem((double)c->sums.occ2, c->sums.occ2_sq, S) / (2.0 * M * N);
+    out->err_Q = sem((double)c->sums.nw, c->sums.nw_sq, S) / (beta * eta * N);
+    out->err_Q_imp = sem(c->sums.qimp, c->sums.qimp_sq, S) / (M * N);
+    return c->flags ? ORC_ESTATE : ORC_OK;
 }
 
 int orc_phase(orc_chain* c, int phase)
@@ -1323,6 +1371,7 @@ int orc_set_state(orc_chain* c, const uint8_t* bstate, const int32_t* counts,
         }
     c->sweep = sweep;
     memset(&c->cur, 0, sizeof(c->cur));
+    memset(&c->sums, 0, sizeof(c->sums));
     return ORC_OK;
 }
 
@@ -1369,6 +1418,32 @@ int orc_check(const orc_chain* c)
         }
     }
     return bad;
+}
+
+static uint64_t splitmix_final(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_state_hash(const orc_chain* c)
+{
+    uint64_t h = 0;
+    for (int k = 0; k < c->ntau; k++)
+        for (int i = 0; i < c->N; i++) {
+            int lo, hi;
+            slab_range(c, i, k, &lo, &hi);
+            uint64_t u = (uint64_t)k * (uint64_t)c->N + (uint64_t)i;
+            h += splitmix_final((u << 20) ^ ((uint64_t)(hi - lo) << 1) ^ (uint64_t)c->bstate[(size_t)k * c->N + i]);
+            for (int j = lo; j < hi; j++) {
+                const ev_t* e = &c->site[i].e[j];
+                uint64_t info = (uint64_t)e->worm | ((uint64_t)e->dir << 1) | ((uint64_t)e->up << 3);
+                h += splitmix_final(splitmix_final((u << 15) | (uint64_t)(j - lo))
+                                    ^ (((uint64_t)(uint32_t)e->tick << 4) | info));
+            }
+        }
+    return h;
 }
 
 int orc_get_derived(const orc_chain* c, orc_derived* d)

@@ -64,6 +64,23 @@ typedef struct orc_obs {
     double  qimp;    /* sum over intervals of l * g_sigma(eta*Delta*l) */
 } orc_obs;
 
+/* Sums over the accumulated sweeps (every sweep since create, set_state or
+   orc_reset_observables), and the thermal averages per site built from them
+   (the same estimators as the library's pmwa_observables):
+     E       = 2 C - <nv> / (beta N)
+     E_alt   = (V <nn2> - mu <occ2>) / (2 M N) - <nkink> / (beta N)
+     E_eta   = E - <nw> / (beta N)
+     density = <occ2> / (2 M N)
+     Q       = <nw> / (beta eta N),   Q_imp = <qimp> / (M N),   b = Q_imp / 2
+   err_*: standard errors of the means as if the sweeps were independent. */
+typedef struct orc_summary {
+    int64_t sweeps, nv, nkink, nw, occ2, nn2;
+    double  qimp;
+    double  nv_sq, nkink_sq, nw_sq, occ2_sq, nn2_sq, qimp_sq;
+    double  E, E_alt, E_eta, density, Q, Q_imp, b;
+    double  err_E, err_density, err_Q, err_Q_imp;
+} orc_summary;
+
 typedef struct orc_chain orc_chain;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESTATE = -3 };
@@ -88,6 +105,13 @@ int  orc_set_state(orc_chain* c, const uint8_t* bstate, const int32_t* counts,
                    const int32_t* ticks, const uint32_t* infos, int64_t n_events,
                    uint64_t sweep);
 int  orc_check(const orc_chain* c);            /* worldline invariants */
+int  orc_observables(const orc_chain* c, orc_summary* out);
+void orc_reset_observables(orc_chain* c);
+/* 64-bit hash of the canonical state: with mix() the SplitMix64 finaliser
+   and u = k*N + site, the sum modulo 2^64 over (k, site) of
+   mix((u << 20) ^ (count << 1) ^ bstate) plus, over the site's events j,
+   mix(mix((u << 15) | j) ^ (tick << 4 | info)). */
+uint64_t orc_state_hash(const orc_chain* c);
 
 /* derived quantities and tables (for pins) */
 typedef struct orc_derived {

@@ -32,6 +32,8 @@ constexpr int KMAXC = 256;      // Poisson table entries = max candidates per bo
 constexpr int NWL = 48;         // worms drawn on one interval
 constexpr int RW_POOL = 64;     // worm-offset pool of the wavefront re-generation and the
                                 // spatial update (above NWL: the first pending lane always fits)
+static_assert(NWL <= RW_POOL, "the worm-offset pool must hold the worms of one interval, "
+                              "or the pool rounds of k_assemble_w and k_bspatial make no progress");
 // lanes per workgroup of the lane-per-unit kernels (vertex phase, temporal
 // boundaries).  Full wavefronts: with fewer lanes the same work takes more
 // memory and LDS instructions per CU, which measured slower than leaving
@@ -87,6 +89,7 @@ struct Pools {
     unsigned long long* sweep;   // per chain
     unsigned int* flags;         // per chain
     unsigned long long* nnacc;   // per chain
+    pmwa_obs_acc* acc;           // per chain: sums and squares of the records
     // scattering-phase node scratch in HBM
     int32_t* s_tick;
     uint32_t* s_nxt;
@@ -198,6 +201,14 @@ struct WaveStream {
         return ((uint64_t)hi << 32) | lo;
     }
 };
+
+// SplitMix64 finaliser (the mixing function of the state hash)
+PMWA_DEV uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
 
 PMWA_DEV double u53(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
 PMWA_DEV uint64_t below(uint64_t w, uint64_t n) { return __umul64hi(w, n); }

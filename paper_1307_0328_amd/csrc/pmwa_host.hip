@@ -31,6 +31,8 @@ __global__ void k_green(Pools P, int chain, const int4* __restrict__ disp, int n
                         double* __restrict__ part);
 __global__ void k_bspatial(Pools P, const int2* __restrict__ blk, int d);
 __global__ void k_finish(Pools P);
+__global__ void k_reset_acc(Pools P, int n);
+__global__ void k_hash(Pools P, int chain, unsigned long long* out);
 }  // namespace pmwa
 
 using namespace pmwa;
@@ -104,6 +106,7 @@ struct pmwa_handle {
     int4* d_gdisp = nullptr;
     double* d_gpart = nullptr;
     size_t gpart_cap = 0;
+    unsigned long long* d_hash = nullptr;   // result of the state-hash reduction
 };
 
 // ---------------------------------------------------------------------------
@@ -307,6 +310,17 @@ static void block_table(const std::vector<HostChain>& ch, int per_block, int64_t
         if ((x) != hipSuccess) return PMWA_EDEVICE; \
     } while (0)
 
+// Allow `bytes` of dynamic LDS for kernel `f`: PMWA_EINVAL beyond the CU's
+// LDS, PMWA_EDEVICE if the runtime refuses.
+static int set_lds(const void* f, size_t bytes, size_t lds_max)
+{
+    if (bytes > lds_max) return PMWA_EINVAL;
+    if (bytes > 64 * 1024 &&
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        return PMWA_EDEVICE;
+    return PMWA_OK;
+}
+
 static int upload_table(const std::vector<int2>& t, int2** dst, int* n)
 {
     *n = (int)t.size();
@@ -445,7 +459,8 @@ void pmwa_destroy(pmwa_t* h)
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
                     h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->d_blk_v, h->d_blk_r,
-                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw, h->d_gdisp, h->d_gpart};
+                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw, h->d_gdisp, h->d_gpart,
+                    h->P.acc, h->d_hash};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete h;
@@ -531,9 +546,10 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     }
     h->P.lds_nodes = (int32_t)lds_nodes;
     h->lds_bytes = fixed_al + lds_nodes * per_node + 16;
-    if (h->lds_bytes > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)h->lds_bytes);
+    if (int e = set_lds((const void*)k_scatter, h->lds_bytes, lds_max)) {
+        pmwa_destroy(h);
+        return e;
+    }
     // HBM node scratch for domains beyond the LDS capacity
     for (auto& hc : h->ch) {
         ChainDev& d = hc.d;
@@ -558,6 +574,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     h->P.sweep = dalloc<unsigned long long>(n_chains, &rc);
     h->P.flags = dalloc<unsigned int>(n_chains, &rc);
     h->P.nnacc = dalloc<unsigned long long>(n_chains, &rc);
+    h->P.acc = dalloc<pmwa_obs_acc>(n_chains, &rc);
+    h->d_hash = dalloc<unsigned long long>(1, &rc);
     h->P.s_tick = dalloc<int32_t>(scr, &rc);
     h->P.s_nxt = dalloc<uint32_t>(scr, &rc);
     h->P.s_prv = dalloc<uint32_t>(scr, &rc);
@@ -610,9 +628,12 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         h->rw_nmax = 4 * maxcapb;
         h->rw_lds = (size_t)((h->rw_nmax + 3) & ~3) * sizeof(uint32_t) +
                     (size_t)h->rw_nmax * (2 * sizeof(uint32_t) + 2) + (size_t)RW_POOL * sizeof(int32_t);
-        if (h->rw_lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_assemble_w, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)h->rw_lds);
+        if (h->regen_wave) {
+            const int e = set_lds((const void*)k_assemble_w, h->rw_lds, lds_max);
+            // the lane form needs no LDS: take it when the wavefront form does not fit
+            if (e == PMWA_EINVAL && mode == 0) h->regen_wave = false;
+            else if (e && !r2) r2 = e;
+        }
         if (!r2 && h->regen_wave) {
             block_table(h->ch, 1, &HostChain::n_units_r, t);
             r2 = upload_table(t, &h->d_blk_rw, &h->nblk_rw);
@@ -624,9 +645,11 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         // A, B, A2, B2; 10 int arrays; the per-vertex records; the worm-offset pool
         h->bs_lds = (size_t)maxcap * (4 * sizeof(uint2) + 10 * sizeof(int) + sizeof(BsVert)) +
                     (size_t)RW_POOL * sizeof(int32_t);
-        if (h->bs_lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_bspatial, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)h->bs_lds);
+        // the spatial update holds a cross bond's two site lists in LDS: a
+        // chain with spatial domains needs its event capacity to fit
+        bool any_spatial = false;
+        for (auto& hc : h->ch) any_spatial |= hc.n_bsx > 0 || hc.n_bsy > 0 || slots;
+        if (any_spatial && !r2) r2 = set_lds((const void*)k_bspatial, h->bs_lds, lds_max);
         int vs = 1;
         for (auto& hc : h->ch) vs = std::max(vs, hc.d.cdf_stride);
         h->vs = vs;
@@ -635,9 +658,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + VL * sizeof(int32_t));
         h->v_rows = std::max(8, std::min(std::max(maxcap, 8), 64));
         h->v_lds = v_fixed + (size_t)h->v_rows * 2 * VL * sizeof(uint32_t);
-        if (h->v_lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_vertex, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)h->v_lds);
+        if (!r2) r2 = set_lds((const void*)k_vertex, h->v_lds, lds_max);
     }
     if (r2) { pmwa_destroy(h); return r2; }
     // the empty configuration
@@ -646,6 +667,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         hipMemsetAsync(h->P.sweep, 0, n_chains * sizeof(unsigned long long), h->stream) != hipSuccess ||
         hipMemsetAsync(h->P.flags, 0, n_chains * sizeof(unsigned int), h->stream) != hipSuccess ||
         hipMemsetAsync(h->P.nnacc, 0, n_chains * sizeof(unsigned long long), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->P.acc, 0, n_chains * sizeof(pmwa_obs_acc), h->stream) != hipSuccess ||
         hipMemsetAsync(h->P.bvc, 0, std::max<int64_t>(bvc, 1) * sizeof(int32_t), h->stream) != hipSuccess ||
         hipMemsetAsync(h->P.dpart, 0, std::max<int64_t>(dom, 1) * sizeof(DomPart), h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess) {
@@ -681,15 +703,14 @@ static void advance_enq(pmwa_t* h)
         if (hc.active && hc.enq_sweeps < hc.target) hc.enq_sweeps++;
 }
 
-int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_sweeps)
+// Build the chain `p` with the event capacity of slot `slot` and check that it
+// fits the slot's regions and launch tables.
+static int slot_fit(pmwa_t* h, int slot, const pmwa_params* p, HostChain& job)
 {
-    if (!h || !p || !h->slots || slot < 0 || slot >= (int)h->ch.size() || target_sweeps < 0) return PMWA_EINVAL;
-    HostChain& hc = h->ch[slot];
-    HostChain job;
+    const HostChain& hc = h->ch[slot];
     int rc = build_chain(*p, (uint32_t)hc.cap_event, job);
     if (rc) return rc;
-    ChainDev& d = job.d;
-    // the job must fit the slot's regions and launch tables
+    const ChainDev& d = job.d;
     const int64_t ev = (int64_t)d.ntau * d.N * d.cap, su = (int64_t)d.ntau * d.N;
     const int64_t bv = 2LL * d.ntau * d.N * d.capb;
     if (ev > hc.cap_ev || su > hc.cap_su || bv > hc.cap_bv || job.n_dom > hc.cap_dom ||
@@ -698,6 +719,25 @@ int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_swe
         job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc || d.cdf_stride > h->vs ||
         (h->regen_wave && 4 * d.capb > h->rw_nmax))
         return PMWA_EINVAL;
+    return PMWA_OK;
+}
+
+int pmwa_slot_fits(pmwa_t* h, int slot, const pmwa_params* p)
+{
+    if (!h || !p || !h->slots || slot < 0 || slot >= (int)h->ch.size()) return PMWA_EINVAL;
+    HostChain job;
+    return slot_fit(h, slot, p, job);
+}
+
+int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_sweeps)
+{
+    if (!h || !p || !h->slots || slot < 0 || slot >= (int)h->ch.size() || target_sweeps < 0) return PMWA_EINVAL;
+    HostChain& hc = h->ch[slot];
+    HostChain job;
+    int rc = slot_fit(h, slot, p, job);
+    if (rc) return rc;
+    ChainDev& d = job.d;
+    const int64_t su = (int64_t)d.ntau * d.N;
     const ChainDev& s = hc.d;
     d.ev_off = s.ev_off; d.cnt_off = s.cnt_off; d.bs_off = s.bs_off; d.bv_off = s.bv_off;
     d.bvc_off = s.bvc_off; d.dom_off = s.dom_off; d.ser_off = s.ser_off; d.cdf_off = s.cdf_off;
@@ -722,6 +762,7 @@ int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_swe
     HIPCHK(hipMemsetAsync(h->P.sweep + slot, 0, sizeof(unsigned long long), st));
     HIPCHK(hipMemsetAsync(h->P.flags + slot, 0, sizeof(unsigned int), st));
     HIPCHK(hipMemsetAsync(h->P.nnacc + slot, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(h->P.acc + slot, 0, sizeof(pmwa_obs_acc), st));
     // host view: keep the slot's capacities, take the job's parameters
     hc.p = job.p;
     hc.d = d;
@@ -954,6 +995,77 @@ int pmwa_green(pmwa_t* h, int chain, const int32_t* disp, int n, double* out)
     return PMWA_OK;
 }
 
+int pmwa_chain_status(pmwa_t* h, int chain)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size()) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    unsigned int fl = 0;
+    HIPCHK(hipMemcpy(&fl, h->P.flags + chain, sizeof(fl), hipMemcpyDeviceToHost));
+    return flag_code(fl);
+}
+
+// standard error of the mean of S samples from their sum and sum of squares
+static double sem(double sum, double sq, double S)
+{
+    if (!(S > 1.0)) return NAN;
+    const double m = sum / S;
+    const double var = sq / S - m * m;
+    return std::sqrt((var > 0.0 ? var : 0.0) / (S - 1.0));
+}
+
+int pmwa_observables(pmwa_t* h, int chain, pmwa_summary* out)
+{
+    if (!h || !out || chain < 0 || chain >= (int)h->ch.size()) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const HostChain& hc = h->ch[chain];
+    pmwa_obs_acc a;
+    HIPCHK(hipMemcpy(&a, h->P.acc + chain, sizeof(a), hipMemcpyDeviceToHost));
+    unsigned int fl = 0;
+    HIPCHK(hipMemcpy(&fl, h->P.flags + chain, sizeof(fl), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->acc = a;
+    // the estimators, in this operation order
+    const double S = (double)a.sweeps, N = (double)hc.d.N, M = (double)hc.d.M;
+    const double beta = hc.p.beta, eta = hc.p.eta, V = hc.p.V, mu = hc.p.mu, C = hc.C;
+    const double m_nv = (double)a.nv / S, m_nk = (double)a.nkink / S, m_nw = (double)a.nw / S;
+    const double m_occ = (double)a.occ2 / S, m_nn = (double)a.nn2 / S, m_q = a.qimp / S;
+    out->E = 2.0 * C - m_nv / (beta * N);
+    out->E_alt = (V * m_nn - mu * m_occ) / (2.0 * M * N) - m_nk / (beta * N);
+    out->E_eta = out->E - m_nw / (beta * N);
+    out->density = m_occ / (2.0 * M * N);
+    out->Q = m_nw / (beta * eta * N);
+    out->Q_imp = m_q / (M * N);
+    out->b = 0.5 * out->Q_imp;
+    out->err_E = sem((double)a.nv, a.nv_sq, S) / (beta * N);
+    out->err_density = sem((double)a.occ2, a.occ2_sq, S) / (2.0 * M * N);
+    out->err_Q = sem((double)a.nw, a.nw_sq, S) / (beta * eta * N);
+    out->err_Q_imp = sem(a.qimp, a.qimp_sq, S) / (M * N);
+    return flag_code(fl);
+}
+
+int pmwa_reset_observables(pmwa_t* h)
+{
+    if (!h) return PMWA_EINVAL;
+    const int n = (int)h->ch.size();
+    hipLaunchKernelGGL(k_reset_acc, dim3((unsigned)std::min((n + 63) / 64, 1024)), dim3(64), 0, h->stream, h->P, n);
+    return hipGetLastError() == hipSuccess ? PMWA_OK : PMWA_EDEVICE;
+}
+
+int pmwa_state_hash(pmwa_t* h, int chain, uint64_t* out)
+{
+    if (!h || !out || chain < 0 || chain >= (int)h->ch.size()) return PMWA_EINVAL;
+    const ChainDev& d = h->ch[chain].d;
+    const long long units = (long long)d.ntau * d.N;
+    HIPCHK(hipMemsetAsync(h->d_hash, 0, sizeof(unsigned long long), h->stream));
+    hipLaunchKernelGGL(k_hash, dim3((unsigned)((units + 63) / 64)), dim3(64), 0, h->stream, h->P, chain, h->d_hash);
+    HIPCHK(hipGetLastError());
+    unsigned long long v = 0;
+    HIPCHK(hipMemcpyAsync(&v, h->d_hash, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *out = (uint64_t)v;
+    return PMWA_OK;
+}
+
 int pmwa_chain_info(pmwa_t* h, int chain, pmwa_info* out)
 {
     if (!h || !out || chain < 0 || chain >= (int)h->ch.size()) return PMWA_EINVAL;
@@ -1051,6 +1163,8 @@ int pmwa_set_state(pmwa_t* h, int chain, const uint8_t* bstate, const int32_t* c
     HIPCHK(hipMemcpy(h->P.sweep + chain, &sw, sizeof(sw), hipMemcpyHostToDevice));
     const unsigned long long z = 0;
     HIPCHK(hipMemcpy(h->P.nnacc + chain, &z, sizeof(z), hipMemcpyHostToDevice));
+    const pmwa_obs_acc za{};
+    HIPCHK(hipMemcpy(h->P.acc + chain, &za, sizeof(za), hipMemcpyHostToDevice));
     HostChain& hc = h->ch[chain];
     hc.enq_sweeps = hc.read_sweeps = sweep;
     hc.host_rows.clear();

@@ -2109,7 +2109,60 @@ __global__ void __launch_bounds__(256) k_finish(Pools P)
         const unsigned long long sw = P.sweep[chain];
         P.ser[C.ser_off + (long long)(sw % (unsigned long long)P.series_cap)] = o;
         P.sweep[chain] = sw + 1ULL;
+        // running sums and sums of squares, in sweep order
+        pmwa_obs_acc a = P.acc[chain];
+        a.sweeps += 1;
+        a.nv += o.nv; a.nkink += o.nkink; a.nw += o.nw; a.occ2 += o.occ2; a.nn2 += o.nn2;
+        a.qimp = a.qimp + o.qimp;
+        a.nv_sq = a.nv_sq + (double)o.nv * (double)o.nv;
+        a.nkink_sq = a.nkink_sq + (double)o.nkink * (double)o.nkink;
+        a.nw_sq = a.nw_sq + (double)o.nw * (double)o.nw;
+        a.occ2_sq = a.occ2_sq + (double)o.occ2 * (double)o.occ2;
+        a.nn2_sq = a.nn2_sq + (double)o.nn2 * (double)o.nn2;
+        a.qimp_sq = a.qimp_sq + o.qimp * o.qimp;
+        P.acc[chain] = a;
     }
+}
+
+// Restart the accumulated observables of chains [0, n).
+__global__ void __launch_bounds__(64) k_reset_acc(Pools P, int n)
+{
+    for (int c = (int)(blockIdx.x * 64 + threadIdx.x); c < n; c += (int)(gridDim.x * 64)) {
+        pmwa_obs_acc z;
+        z.sweeps = 0; z.nv = 0; z.nkink = 0; z.nw = 0; z.occ2 = 0; z.nn2 = 0;
+        z.qimp = 0.0; z.nv_sq = 0.0; z.nkink_sq = 0.0; z.nw_sq = 0.0; z.occ2_sq = 0.0;
+        z.nn2_sq = 0.0; z.qimp_sq = 0.0;
+        P.acc[c] = z;
+    }
+}
+
+// State hash of one chain: one lane per (slab, site), the terms of its
+// boundary state, count and events (each site's events are adjacent rows of
+// its domain block), summed modulo 2^64 over a wavefront and added to *out.
+__global__ void __launch_bounds__(64) k_hash(Pools P, int chain, unsigned long long* __restrict__ out)
+{
+    const ChainDev& C = P.cd[chain];
+    const long long nunits = (long long)C.ntau * C.N;
+    const long long u = (long long)blockIdx.x * 64 + threadIdx.x;
+    unsigned long long acc = 0ULL;
+    if (u < nunits) {
+        const int per = C.ndsp * C.nloc;
+        const int k = (int)(u / per), rem = (int)(u - (long long)k * per);
+        const int dsp = rem / C.nloc, sl = rem - dsp * C.nloc;
+        const int site = site_join(C, dsp, sl);
+        const uint64_t uc = (uint64_t)k * (uint64_t)C.N + (uint64_t)site;
+        const long long su = unit_su(C, k, dsp, sl);
+        const int n = P.cnt[C.cnt_off + su];
+        const uint32_t b = P.bs[C.bs_off + su];
+        acc = mix64((uc << 20) ^ ((uint64_t)n << 1) ^ (uint64_t)b);
+        const uint2* E = P.ev + ev_base(C, k, dsp, sl);
+        for (int j = 0; j < n; j++) {
+            const uint2 e = E[(long long)j * C.nloc];
+            acc += mix64(mix64((uc << 15) | (uint64_t)j) ^ (((uint64_t)e.x << 4) | (uint64_t)e.y));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (threadIdx.x == 0) atomicAdd(out, acc);
 }
 
 }  // namespace pmwa

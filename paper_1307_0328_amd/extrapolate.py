@@ -7,13 +7,13 @@ vanishes in a finite system whenever Q measures a broken symmetry. The
 solid phase is therefore fitted as a + c eta^2. In the superfluid phase the
 paper fits a line at low temperature.
 
-Per-sweep estimators (per site), from the records of pmwa_measure:
-  E = 2 C - N_v / (beta N)    energy of the physical H in the eta ensemble
-                              (every operator of the expansion but the worms
-                              is a vertex of H; the shift C is per bond)
-  Q = N_w / (beta eta N)      order parameter (b + b^dagger per site)
-  n = occ2 / (2 M N)          density
-Errors come from a binning analysis. The fits are weighted least squares.
+The estimators (per site) are the library's (pmwa_observables): the energy
+of the physical H in the eta ensemble E = 2 C - <N_v>/(beta N), the order
+parameter Q = <N_w>/(beta eta N) (and its improved form), the density
+<occ2>/(2 M N).  The library accumulates them on the device; this module
+reads one average per block of sweeps and does the statistics: a binning
+analysis of the block averages for the errors, then weighted least-squares
+fits.
 
 The runs are batched: all (mu, eta) chains advance in the same launches.
 
@@ -85,16 +85,6 @@ FITS = {"quad": (0, 2), "lin": (0, 1), "quad+lin": (0, 1, 2), "quad+quartic": (0
 
 
 # ---------------------------------------------------------------------------
-# per-sweep estimators
-# ---------------------------------------------------------------------------
-def estimators(rows, C: float, beta: float, N: int, eta: float, M: int):
-    nv = rows["nv"].astype(np.float64)
-    nw = rows["nw"].astype(np.float64)
-    occ = rows["occ2"].astype(np.float64)
-    return {"E": 2.0 * C - nv / (beta * N), "Q": nw / (beta * eta * N), "n": occ / (2.0 * M * N)}
-
-
-# ---------------------------------------------------------------------------
 # batched eta scan on the device
 # ---------------------------------------------------------------------------
 def checkerboard_state(Lx: int, Ly: int, ntau: int, parity: int = 0) -> dict:
@@ -106,49 +96,59 @@ def checkerboard_state(Lx: int, Ly: int, ntau: int, parity: int = 0) -> dict:
                 ticks=np.zeros(0, np.int32), infos=np.zeros(0, np.uint32), sweep=0)
 
 
-def run_scan(chains: list[dict], therm: int, sweeps: int, chunk: int = 500, progress=None,
-             use_graph: bool = True, init_states=None):
+def run_scan(chains: list[dict], therm: int, sweeps: int, block: int = 100, progress=None,
+             use_graph: bool = True, init_states=None, chunk: int | None = None):
     """Run every chain of `chains` (parameter dicts) in one handle: `therm`
-    sweeps, then `sweeps` measured sweeps. `init_states` (optional, one
-    canonical state or None per chain) replaces the empty start. Returns
-    per chain a dict of per-sweep estimator arrays and the derived
-    constants."""
+    sweeps, then `sweeps` measured sweeps in blocks of `block`.  After each
+    block the library's accumulated observables give the block averages,
+    and the accumulation restarts.  `init_states` (optional, one canonical
+    state or None per chain) replaces the empty start.  Returns per chain
+    the block averages of each estimator and the derived constants.
+    (`chunk` is the older name of `block`.)"""
     from . import pmwa as P
+    if chunk is not None:
+        block = chunk
     ps = [P.make_params(**c) for c in chains]
-    out = []
-    with P.Sim(ps, use_graph=use_graph, series_cap=max(4096, 2 * chunk)) as sim:
+    keys = ("E", "E_alt", "E_eta", "density", "Q", "Q_imp", "b")
+    est = [{k: [] for k in keys} for _ in ps]
+    with P.Sim(ps, use_graph=use_graph, series_cap=max(4096, 2 * block)) as sim:
         infos = [sim.info(i) for i in range(len(ps))]
         if init_states is not None:
             for i, st in enumerate(init_states):
                 if st is not None:
                     sim.set_state(st, i)
-        done = 0
         t0 = time.time()
+        done = 0
         while done < therm:
-            n = min(chunk, therm - done)
+            n = min(max(block, 500), therm - done)
             sim.sweep(n)
             for i in range(len(ps)):
-                sim.measure(i)
+                sim.measure(i)          # the per-sweep records are not needed
             done += n
             if progress:
                 progress(f"thermalise {done}/{therm} sweeps, {time.time() - t0:.0f} s")
-        rows = [[] for _ in ps]
         done = 0
+        last = time.time()
         while done < sweeps:
-            n = min(chunk, sweeps - done)
+            n = min(block, sweeps - done)
+            sim.reset_observables()
             sim.sweep(n)
             for i in range(len(ps)):
-                rows[i].append(sim.measure(i))
+                o = sim.observables(i)
+                for k in keys:
+                    est[i][k].append(o[k])
+                sim.measure(i)
             done += n
-            if progress:
+            if progress and (time.time() - last > 10.0 or done == sweeps):
+                last = time.time()
                 progress(f"measure {done}/{sweeps} sweeps, {time.time() - t0:.0f} s")
         if sim.status() != 0:
             raise RuntimeError(f"device error {sim.status()}")
+    out = []
     for i, c in enumerate(chains):
-        r = np.concatenate(rows[i])
-        N = c.get("Lx", c.get("L")) * c.get("Ly", c.get("L"))
-        est = estimators(r, infos[i].C, c["beta"], N, c["eta"], infos[i].M)
-        out.append(dict(params=c, C=infos[i].C, est=est))
+        e = {k: np.array(v) for k, v in est[i].items()}
+        e["n"] = e["density"]
+        out.append(dict(params=c, C=infos[i].C, est=e, block=block))
     return out
 
 
@@ -176,7 +176,7 @@ def main(argv=None):
     ap.add_argument("--grid", default="16,16,2", help="domains dom_x,dom_y,dom_tau")
     ap.add_argument("--therm", type=int, default=2000)
     ap.add_argument("--sweeps", type=int, default=20000)
-    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--block", type=int, default=100, help="sweeps per block average")
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--start", default="empty", choices=["empty", "checkerboard"],
                     help="initial configuration (an ordered solid for the CS phase)")
@@ -188,7 +188,7 @@ def main(argv=None):
     init = None
     if a.start == "checkerboard":
         init = [checkerboard_state(a.L, a.L, gt) for _ in chains]
-    res = run_scan(chains, a.therm, a.sweeps, a.chunk, progress=lambda s: print(s, flush=True), init_states=init)
+    res = run_scan(chains, a.therm, a.sweeps, a.block, progress=lambda s: print(s, flush=True), init_states=init)
     summ = {k: summarize(res, a.fit if k == "E" else "lin", k) for k in ("E", "n", "Q")}
     summ["config"] = vars(a)
     text = json.dumps(summ, indent=1)

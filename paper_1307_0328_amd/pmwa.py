@@ -20,7 +20,8 @@ PH_V, PH_R, PH_S, PH_BT, PH_BSX, PH_BSY, PH_END = 1, 2, 3, 4, 5, 6, 7
 EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_status",
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
            "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_set_timing_phases", "pmwa_phase_times", "pmwa_diag",
-           "pmwa_green",
+           "pmwa_green", "pmwa_chain_status", "pmwa_observables", "pmwa_reset_observables",
+           "pmwa_state_hash", "pmwa_slot_fits",
            "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
 
 
@@ -41,6 +42,13 @@ class pmwa_opts(C.Structure):
 class pmwa_obs(C.Structure):
     _fields_ = [("nv", C.c_int64), ("nkink", C.c_int64), ("nw", C.c_int64),
                 ("occ2", C.c_int64), ("nn2", C.c_int64), ("qimp", C.c_double)]
+
+
+class pmwa_summary(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("sweeps", "nv", "nkink", "nw", "occ2", "nn2")] + \
+               [(n, C.c_double) for n in ("qimp", "nv_sq", "nkink_sq", "nw_sq", "occ2_sq", "nn2_sq",
+                                          "qimp_sq", "E", "E_alt", "E_eta", "density", "Q", "Q_imp",
+                                          "b", "err_E", "err_density", "err_Q", "err_Q_imp")]
 
 
 class pmwa_info(C.Structure):
@@ -86,6 +94,11 @@ def lib():
         L.pmwa_slot_load.argtypes = [C.c_void_p, C.c_int, P(pmwa_params), C.c_int64]
         L.pmwa_slot_release.argtypes = [C.c_void_p, C.c_int]
         L.pmwa_slot_progress.argtypes = [C.c_void_p, C.c_int, P(C.c_int64)]
+        L.pmwa_chain_status.argtypes = [C.c_void_p, C.c_int]
+        L.pmwa_observables.argtypes = [C.c_void_p, C.c_int, P(pmwa_summary)]
+        L.pmwa_reset_observables.argtypes = [C.c_void_p]
+        L.pmwa_state_hash.argtypes = [C.c_void_p, C.c_int, P(C.c_uint64)]
+        L.pmwa_slot_fits.argtypes = [C.c_void_p, C.c_int, P(pmwa_params)]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -227,6 +240,33 @@ def pmwa_green(h, chain, disps):
     return out
 
 
+def pmwa_chain_status(h, chain):
+    return lib().pmwa_chain_status(h, chain)
+
+
+def pmwa_observables(h, chain, allow_flagged=False):
+    """Accumulated sums and per-site thermal averages of one chain (dict)."""
+    out = pmwa_summary()
+    rc = lib().pmwa_observables(h, chain, C.byref(out))
+    if not allow_flagged:
+        _check(rc, "pmwa_observables")
+    return {n: getattr(out, n) for n, _ in pmwa_summary._fields_}
+
+
+def pmwa_reset_observables(h):
+    _check(lib().pmwa_reset_observables(h), "pmwa_reset_observables")
+
+
+def pmwa_state_hash(h, chain):
+    v = C.c_uint64()
+    _check(lib().pmwa_state_hash(h, chain, C.byref(v)), "pmwa_state_hash")
+    return int(v.value)
+
+
+def pmwa_slot_fits(h, slot, p):
+    return lib().pmwa_slot_fits(h, slot, C.byref(p)) == 0
+
+
 def pmwa_diag(h, chain):
     out = np.zeros(4, np.int64)
     _check(lib().pmwa_diag(h, chain, out.ctypes.data, 4), "pmwa_diag")
@@ -310,3 +350,15 @@ class Sim:
 
     def green(self, disps, chain=0):
         return pmwa_green(self.h, chain, disps)
+
+    def observables(self, chain=0):
+        return pmwa_observables(self.h, chain)
+
+    def reset_observables(self):
+        pmwa_reset_observables(self.h)
+
+    def state_hash(self, chain=0):
+        return pmwa_state_hash(self.h, chain)
+
+    def chain_status(self, chain=0):
+        return pmwa_chain_status(self.h, chain)

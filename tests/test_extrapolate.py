@@ -49,17 +49,6 @@ def test_fit_error_of_a_two_point_line():
     assert abs(dv - s * math.sqrt(1 + 9) / 2.0) < 1e-12
 
 
-def test_estimators_from_records():
-    rows = np.zeros(2, dtype=[("nv", "<i8"), ("nw", "<i8"), ("occ2", "<i8")])
-    rows["nv"] = [100, 140]
-    rows["nw"] = [4, 6]
-    rows["occ2"] = [2 ** 10 * 9, 2 ** 11 * 9]
-    est = X.estimators(rows, C=1.25, beta=2.0, N=9, eta=0.1, M=2 ** 10)
-    np.testing.assert_allclose(est["E"], [2.5 - 100 / 18, 2.5 - 140 / 18])
-    np.testing.assert_allclose(est["Q"], [4 / 1.8, 6 / 1.8])
-    np.testing.assert_allclose(est["n"], [0.5, 1.0])
-
-
 def test_checkerboard_start_is_a_valid_configuration():
     from oracle import oracle as O
     st = X.checkerboard_state(6, 4, 2, parity=1)

@@ -20,7 +20,7 @@ def test_energy_extrapolates_to_the_eta0_ground_truth():
     base = dict(Lx=3, Ly=3, beta=2.0, t=1.0, V=1.0, mu=0.5, seed=21)
     chains = [dict(base, eta=e, chain_id=i) for i, e in enumerate(etas)]
     print("[extrapolate] 3x3, five eta, 400000 sweeps", flush=True)
-    res = X.run_scan(chains, therm=2000, sweeps=400000, chunk=20000,
+    res = X.run_scan(chains, therm=2000, sweeps=400000, block=2000,
                      progress=lambda s: (print(s, flush=True), sys.stdout.flush()))
     s = X.summarize(res, "quad")
     exact = [ed.thermal_dense(3, 3, 2.0, 1.0, 1.0, 0.5, e)["E"] for e in etas]
