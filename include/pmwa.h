@@ -91,7 +91,12 @@ typedef struct pmwa_opts {
     int32_t regen_mode;       /* worm re-generation: 0 auto, 1 a lane per (site,
                                  slab), 2 a wavefront per (site, slab); the
                                  result is the same                           */
-    int32_t reserved[3];
+    int32_t vertex_mode;      /* vertex phase, for tests (the result is the same):
+                                 0 auto; bit0: walk the site lists in HBM even
+                                 where the occupation changes fit in LDS; bit1:
+                                 sort the candidates in an LDS column even
+                                 where 32 registers hold them               */
+    int32_t reserved[2];
 } pmwa_opts;
 
 /* Raw per-sweep record of one chain (all sums over the whole lattice). */
@@ -275,6 +280,22 @@ int pmwa_diag(pmwa_t* h, int chain, int64_t* out, int n);
    PMWA_EOVERFLOW if the chain is flagged. */
 #define PMWA_GREEN_MAX 64
 int pmwa_green(pmwa_t* h, int chain, const int32_t* disp, int n, double* out);
+
+/* pmwa_green without any allocation, for callers that cannot allocate
+   device memory (code under graph capture set-up, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, results and errors as
+   pmwa_green (equal to it: the same kernel, the partials summed in the same
+   order on the device).  Its workspace (displacements, per-block partials,
+   results; 4 MB + 2 KB) is one static device array per GPU, set up by
+   pmwa_create; the call makes no hipMalloc/hipFree.  Limit: dom_tau *
+   (distinct non-zero displacements) * ceil(Lx*Ly / 64) <=
+   PMWA_GREEN_STATIC_PARTIALS, else PMWA_EINVAL (e.g. a 2048 x 2048 lattice
+   with 4 slabs takes at most 2 displacements per call).  Every call on a GPU
+   uses that GPU's one array: calls that overlap in time on the same GPU
+   (from several threads or handles) race and must be serialised by the
+   caller.  Synchronises the handle's stream. */
+#define PMWA_GREEN_STATIC_PARTIALS (1 << 19)
+int pmwa_green_static(pmwa_t* h, int chain, const int32_t* disp, int n, double* out);
 
 /* Events per (site, slab) a chain would be given by default. */
 int pmwa_default_event_cap(const pmwa_params* p);

@@ -16,12 +16,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "pmwa_device.h"
 
 namespace pmwa {
-__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows);
+__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows, int vmode);
 __global__ void k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
@@ -33,9 +34,47 @@ __global__ void k_bspatial(Pools P, const int2* __restrict__ blk, int d);
 __global__ void k_finish(Pools P);
 __global__ void k_reset_acc(Pools P, int n);
 __global__ void k_hash(Pools P, int chain, unsigned long long* out);
+__global__ void k_green_sum(const double* part, int ntau, int nd, int nchunk, double norm, double* out);
 }  // namespace pmwa
 
 using namespace pmwa;
+
+// ---------------------------------------------------------------------------
+// Static device scratch of pmwa_green_static, the entry point that allocates
+// nothing: the displacements, the per-displacement results and the per-block
+// partials of the Green-function kernels.  Each GPU holds its own copy for
+// the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (kept per device below).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t SCR_DISP = 0;                              // int4[PMWA_GREEN_MAX]
+constexpr size_t SCR_OUT = 1024;                            // double[PMWA_GREEN_MAX]
+constexpr size_t SCR_PART = 2048;                           // double[PMWA_GREEN_STATIC_PARTIALS]
+constexpr size_t SCR_BYTES = SCR_PART + (size_t)PMWA_GREEN_STATIC_PARTIALS * sizeof(double);
+static_assert(SCR_OUT >= PMWA_GREEN_MAX * sizeof(int4) && SCR_PART - SCR_OUT >= PMWA_GREEN_MAX * sizeof(double),
+              "scratch regions overlap");
+constexpr int SCR_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCR_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
+// Device address of `scratch` on device `dev` (which must be current),
+// looked up once per device.
+static int scratch_address(int dev, void** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= SCR_MAX_DEVICES) return PMWA_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return PMWA_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PMWA_OK;
+}
 
 namespace {
 
@@ -107,6 +146,7 @@ struct pmwa_handle {
     double* d_gpart = nullptr;
     size_t gpart_cap = 0;
     unsigned long long* d_hash = nullptr;   // result of the state-hash reduction
+    void* scratch = nullptr;                // this device's static scratch (pmwa_green_static)
 };
 
 // ---------------------------------------------------------------------------
@@ -360,7 +400,8 @@ static int launch_kernel(pmwa_t* h, int phase)
     hipStream_t s = h->stream;
     switch (phase) {
     case 1:
-        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(VL), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows);
+        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(VL), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows,
+                               h->opts.vertex_mode);
         break;
     case 2:
         if (h->regen_wave) {
@@ -477,7 +518,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (opts) h->opts = *opts;
     if (h->opts.series_cap <= 0) h->opts.series_cap = 4096;
     if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0 ||
-        h->opts.event_cap > 32767 || h->opts.regen_mode < 0 || h->opts.regen_mode > 2) { delete h; return PMWA_EINVAL; }
+        h->opts.event_cap > 32767 || h->opts.regen_mode < 0 || h->opts.regen_mode > 2 ||
+        h->opts.vertex_mode < 0 || h->opts.vertex_mode > 3) { delete h; return PMWA_EINVAL; }
     h->stream = (hipStream_t)h->opts.stream;
     if (!h->stream) {
         // work goes to a stream of the handle (default priority)
@@ -524,6 +566,10 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
         pmwa_destroy(h);
         return PMWA_EDEVICE;
+    }
+    if (int e = scratch_address(dev, &h->scratch)) {
+        pmwa_destroy(h);
+        return e;
     }
     size_t lds_max = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds_max) lds_max = prop.maxSharedMemoryPerMultiProcessor;
@@ -1063,6 +1109,51 @@ int pmwa_state_hash(pmwa_t* h, int chain, uint64_t* out)
     HIPCHK(hipMemcpyAsync(&v, h->d_hash, sizeof(v), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     *out = (uint64_t)v;
+    return PMWA_OK;
+}
+
+int pmwa_green_static(pmwa_t* h, int chain, const int32_t* disp, int n, double* out)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size() || n < 1 || n > PMWA_GREEN_MAX || !disp || !out)
+        return PMWA_EINVAL;
+    if (!h->scratch) return PMWA_EDEVICE;
+    const ChainDev& d = h->ch[chain].d;
+    // the partials of one call must fit the static scratch
+    int4 dv[PMWA_GREEN_MAX];
+    int slot[PMWA_GREEN_MAX];
+    int nd = 0;
+    for (int q = 0; q < n; q++) {
+        const int rx = ((disp[3 * q] % d.Lx) + d.Lx) % d.Lx, ry = ((disp[3 * q + 1] % d.Ly) + d.Ly) % d.Ly;
+        const int dt = (int)((((int64_t)disp[3 * q + 2] % d.M) + d.M) % d.M);
+        slot[q] = -1;
+        if (rx == 0 && ry == 0 && dt == 0) continue;
+        slot[q] = nd;
+        dv[nd++] = make_int4(rx, ry, dt, 0);
+    }
+    const int nchunk = (d.N + 63) / 64;
+    const long long nblk = (long long)d.ntau * nd * nchunk;
+    if (nblk > PMWA_GREEN_STATIC_PARTIALS) return PMWA_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    unsigned int fl = 0;
+    HIPCHK(hipMemcpy(&fl, h->P.flags + chain, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl) return (fl & 1u) ? PMWA_EOVERFLOW : PMWA_ESTATE;
+    double res[PMWA_GREEN_MAX];
+    if (nd > 0) {
+        unsigned char* base = static_cast<unsigned char*>(h->scratch);
+        int4* s_disp = reinterpret_cast<int4*>(base + SCR_DISP);
+        double* s_out = reinterpret_cast<double*>(base + SCR_OUT);
+        double* s_part = reinterpret_cast<double*>(base + SCR_PART);
+        HIPCHK(hipMemcpyAsync(s_disp, dv, nd * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(k_green, dim3((unsigned)nblk), dim3(64), 0, h->stream, h->P, chain, s_disp, nd, nchunk,
+                           s_part);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_green_sum, dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, h->stream, s_part, d.ntau,
+                           nd, nchunk, (double)d.M * (double)d.N, s_out);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(res, s_out, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    for (int q = 0; q < n; q++) out[q] = slot[q] < 0 ? 1.0 : res[slot[q]];
     return PMWA_OK;
 }
 

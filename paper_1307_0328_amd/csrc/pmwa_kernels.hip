@@ -362,7 +362,7 @@ PMWA_DEV int2 stage_flips(const uint2* EA, int na, int sa0, uint32_t* FA,
 // doubles), the candidate ticks (one column of vs entries per lane), and the
 // occupation-changing objects of both ends of each lane's bond (two columns
 // of `rows` entries per lane)
-__global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows)
+__global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows, int vmode)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         // a column is used only with a row to spare: once a count reaches
         // `rows`, later events land on the last row, which then no longer
         // holds the last flip
-        const bool staged = nfa < rows && nfc < rows;
+        const bool staged = nfa < rows && nfc < rows && !(vmode & 1);
         const FlipList fla{FA, nfa, B.sa0, d}, flc{FC, nfc, B.sc0, -1};
         const FullList gla{Ea, na, B.st, d}, glc{Ec, nc, B.st, -1};
 
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         AccRank AR;
         AR.init(C);
         bool rep;
-        if (n <= 32) {
+        if (n <= 32 && !(vmode & 2)) {
             // the draws stay rolled loops through the LDS column (unrolled,
             // each inlined generator call would multiply the code size)
             for (int i = 0; i < n; i++) cand[i * VL] = Tk + (int32_t)below(rs.next(), dT);
@@ -2059,6 +2059,20 @@ __global__ void __launch_bounds__(64) k_green(Pools P, int chain, const int4* __
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     if (lane == 0) part[blk] = acc;
+}
+
+// The per-block partials of k_green summed per displacement on the device,
+// in the order the host sums them for pmwa_green (slab, then block of
+// sites), then divided by M N: out[d] = G of displacement d.
+__global__ void __launch_bounds__(64) k_green_sum(const double* __restrict__ part, int ntau, int nd, int nchunk,
+                                                  double norm, double* __restrict__ out)
+{
+    const int d = (int)(blockIdx.x * 64 + threadIdx.x);
+    if (d >= nd) return;
+    double sum = 0.0;
+    for (int k = 0; k < ntau; k++)
+        for (int c = 0; c < nchunk; c++) sum += part[((long long)k * nd + d) * nchunk + c];
+    out[d] = sum / norm;
 }
 
 // ===========================================================================

@@ -21,7 +21,7 @@ EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_stat
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
            "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_set_timing_phases", "pmwa_phase_times", "pmwa_diag",
            "pmwa_green", "pmwa_chain_status", "pmwa_observables", "pmwa_reset_observables",
-           "pmwa_state_hash", "pmwa_slot_fits",
+           "pmwa_state_hash", "pmwa_slot_fits", "pmwa_green_static",
            "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
 
 
@@ -36,7 +36,7 @@ class pmwa_params(C.Structure):
 class pmwa_opts(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("scatter_mode", C.c_int32), ("series_cap", C.c_int32),
                 ("event_cap", C.c_int32), ("use_graph", C.c_int32), ("regen_mode", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("vertex_mode", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class pmwa_obs(C.Structure):
@@ -99,6 +99,7 @@ def lib():
         L.pmwa_reset_observables.argtypes = [C.c_void_p]
         L.pmwa_state_hash.argtypes = [C.c_void_p, C.c_int, P(C.c_uint64)]
         L.pmwa_slot_fits.argtypes = [C.c_void_p, C.c_int, P(pmwa_params)]
+        L.pmwa_green_static.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -267,6 +268,15 @@ def pmwa_slot_fits(h, slot, p):
     return lib().pmwa_slot_fits(h, slot, C.byref(p)) == 0
 
 
+def pmwa_green_static(h, chain, disps):
+    """pmwa_green through the entry point that allocates nothing."""
+    rows = [tuple(int(v) for v in dd) + (0,) * (3 - len(dd)) for dd in disps]
+    d = np.ascontiguousarray(np.array(rows, dtype=np.int64).reshape(-1, 3), dtype=np.int32)
+    out = np.zeros(len(d))
+    _check(lib().pmwa_green_static(h, chain, d.ctypes.data, len(d), out.ctypes.data), "pmwa_green_static")
+    return out
+
+
 def pmwa_diag(h, chain):
     out = np.zeros(4, np.int64)
     _check(lib().pmwa_diag(h, chain, out.ctypes.data, 4), "pmwa_diag")
@@ -283,7 +293,7 @@ class Sim:
     """A handle of one or more chains (convenience around the calls above)."""
 
     def __init__(self, chains, stream=None, scatter_mode=0, series_cap=4096, event_cap=0,
-                 use_graph=False, regen_mode=0):
+                 use_graph=False, regen_mode=0, vertex_mode=0):
         if isinstance(chains, pmwa_params):
             chains = [chains]
         self.chains = list(chains)
@@ -294,6 +304,7 @@ class Sim:
         o.event_cap = event_cap
         o.use_graph = 1 if use_graph else 0
         o.regen_mode = regen_mode
+        o.vertex_mode = vertex_mode
         self.h = pmwa_create(self.chains, o)
 
     def close(self):
