@@ -115,6 +115,58 @@ def green_dense(Lx, Ly, beta, t, V, mu, eta, disps):
     return np.array(out)
 
 
+OPS = {"Q": 0, "b": 1, "bd": 2}      # b + b^+, b (annihilation), b^+ (creation)
+
+
+def correlator_dense(Lx, Ly, beta, t, V, mu, eta, points):
+    """Imaginary-time ordered n-point function of H_eta,
+
+        (1/N) sum_i < T prod_k O_k(i + r_k, tau_k) >,
+
+    for points (rx, ry, tau, op) with op in OPS (a name or its code) and tau
+    in [0, beta]: the points are ordered by decreasing tau (equal times keep
+    their listed order, the first to the left) and the trace is
+    Tr(e^{-(beta - tau_1) H} O_1 e^{-(tau_1 - tau_2) H} O_2 ... O_n
+    e^{-tau_n H}) / Z."""
+    N = Lx * Ly
+    H, _, _, _, _ = hamiltonian_dense(Lx, Ly, t, V, mu, eta)
+    evals, evecs = np.linalg.eigh(H)
+    e = evals - evals.min()
+    Z = np.exp(-beta * e).sum()
+    states = np.arange(1 << N, dtype=np.int64)
+
+    def op_matrix(code, i):
+        code = OPS.get(code, code)
+        m = np.zeros((1 << N, 1 << N))
+        occ = (states >> i) & 1
+        if code in (0, 1):                   # b: |..1_i..> -> |..0_i..>
+            src = states[occ == 1]
+            m[src ^ (1 << i), src] = 1.0
+        if code in (0, 2):                   # b^+: |..0_i..> -> |..1_i..>
+            src = states[occ == 0]
+            m[src ^ (1 << i), src] = 1.0
+        return evecs.T @ m @ evecs
+
+    cache = {}
+    order = sorted(range(len(points)), key=lambda k: (-float(points[k][2]), k))
+    taus = [float(points[k][2]) for k in order]
+    acc = 0.0
+    for i in range(N):
+        x, y = i % Lx, i // Lx
+        prod = np.diag(np.exp(-(beta - taus[0]) * e))
+        for n, k in enumerate(order):
+            rx, ry, _, op = points[k]
+            j = ((y + ry) % Ly) * Lx + (x + rx) % Lx
+            key = (OPS.get(op, op), j)
+            if key not in cache:
+                cache[key] = op_matrix(op, j)
+            prod = prod @ cache[key]
+            dtau = taus[n] - (taus[n + 1] if n + 1 < len(order) else 0.0)
+            prod = prod * np.exp(-dtau * e)[None, :]
+        acc += float(np.trace(prod)) / Z
+    return acc / N
+
+
 def _finish(r, N, V, mu, eta):
     E_eta = r["E_eta_total"] / N
     Q = r["Q"] / N

@@ -100,6 +100,7 @@ def bind(path: str):
     L.orc_stream_word.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint64]
     L.orc_stream_word.restype = C.c_uint64
     L.orc_green.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    L.orc_correlator.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
     L.orc_observables.argtypes = [C.c_void_p, P(Summary)]
     L.orc_reset_observables.argtypes = [C.c_void_p]
     L.orc_reset_observables.restype = None
@@ -273,6 +274,18 @@ class Chain:
         out = np.zeros(len(d))
         if self._L.orc_green(self.h, d.ctypes.data, len(d), out.ctypes.data) != 0:
             raise RuntimeError("orc_green failed")
+        return out
+
+    def correlator(self, corrs, nbase=8):
+        """n-point functions on the current configuration: `corrs` is a list
+        of correlators, each a list of points (rx, ry, dt ticks, op) with op
+        0 = b + b^+, 1 = b, 2 = b^+ (all correlators with the same number of
+        points); one value per correlator."""
+        arr = np.ascontiguousarray(np.array(corrs, dtype=np.int64), dtype=np.int32)
+        ncorr, npt = arr.shape[0], arr.shape[1]
+        out = np.zeros(ncorr)
+        if self._L.orc_correlator(self.h, npt, arr.ctypes.data, ncorr, nbase, out.ctypes.data) != 0:
+            raise RuntimeError("orc_correlator failed")
         return out
 
     def observables(self):

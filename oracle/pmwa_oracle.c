@@ -960,6 +960,129 @@ int orc_green(const orc_chain* c, const int32_t* disp, int n, double* out)
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------ */
+/* n-point functions of b, b^+ and Q (Supplemental S-I, general n)     */
+/* ------------------------------------------------------------------ */
+/* The configuration's weight is a product over intervals (delimited by
+   vertices and temporal domain boundaries) of <q| exp(l eta Delta Q) |p>,
+   p and q the occupations just above its lower and just below its upper
+   end: the worms inside an interval are summed over.  An operator inserted
+   at a point of an interval multiplies that factor by
+     <q| E(l_top) O_m E(..) ... O_1 E(l_bottom) |p> / <q| E(l) |p>,
+   E(l) = exp(l eta Delta Q), the operators in time order; points on
+   different intervals give the product of their intervals' factors.  A
+   point at tick t sits at t + 1/4: between a vertex at t and the worm slot
+   t + 1/2, so l_bottom = t - lo slots lie below it and hi - t above. */
+enum { ORC_OP_Q = 0, ORC_OP_B = 1, ORC_OP_BD = 2 };
+
+typedef struct { int site; int32_t t; int op, idx; int32_t lo, hi; int p, q, grp; } cpt_t;
+
+/* interval of `site` holding time t + 1/4: its ends lo <= t < hi, the
+   occupation p just above lo and q just below hi */
+static void point_interval(const orc_chain* c, int site, int32_t t, int32_t* lo, int32_t* hi, int* p, int* q)
+{
+    int k = slab_of(c, t);
+    const elist* l = &c->site[site];
+    int a, b;
+    slab_range(c, site, k, &a, &b);
+    *lo = c->T[k];
+    *p = c->bstate[(size_t)k * c->N + site];
+    *hi = c->T[k + 1];
+    *q = c->bstate[(size_t)((k + 1) % c->ntau) * c->N + site];
+    for (int j = a; j < b; j++) {
+        const ev_t* e = &l->e[j];
+        if (e->worm) continue;
+        if (e->tick <= t) { *lo = e->tick; *p = e->up; }
+        else { *hi = e->tick; *q = state_below(c, site, k, j); break; }
+    }
+}
+
+/* v <- E(ell) v with E = [[cosh, sinh], [sinh, cosh]](lambda ell) */
+static void prop2(const orc_chain* c, int64_t ell, double v[2])
+{
+    double ch = fleg(c, 0, ell), sh = fleg(c, 1, ell);
+    double n0 = ch * v[0] + sh * v[1];
+    double n1 = sh * v[0] + ch * v[1];
+    v[0] = n0; v[1] = n1;
+}
+static void apply_op(int op, double v[2])
+{
+    double a = v[0], b = v[1];
+    if (op == ORC_OP_Q) { v[0] = b; v[1] = a; }
+    else if (op == ORC_OP_B) { v[0] = b; v[1] = 0.0; }     /* b|1> = |0> */
+    else { v[0] = 0.0; v[1] = a; }                        /* b^+|0> = |1> */
+}
+
+/* one sample: points (site_k, t_k) of one base point, in the order listed */
+static double corr_sample(const orc_chain* c, cpt_t* P, int np)
+{
+    for (int k = 0; k < np; k++) {
+        point_interval(c, P[k].site, P[k].t, &P[k].lo, &P[k].hi, &P[k].p, &P[k].q);
+        P[k].grp = -1;
+    }
+    double prod = 1.0;
+    for (int k = 0; k < np; k++) {
+        if (P[k].grp >= 0) continue;
+        /* the group of point k: every point on the same interval */
+        int mem[16], nm = 0;
+        for (int m = k; m < np; m++)
+            if (P[m].site == P[k].site && P[m].lo == P[k].lo && P[m].hi == P[k].hi) {
+                P[m].grp = k;
+                mem[nm++] = m;
+            }
+        /* bottom to top: ascending time; at equal times the later-listed
+           point acts first (the first listed is leftmost) */
+        for (int a = 1; a < nm; a++) {
+            int v = mem[a], b = a - 1;
+            while (b >= 0 && (P[mem[b]].t > P[v].t || (P[mem[b]].t == P[v].t && mem[b] < v))) {
+                mem[b + 1] = mem[b]; b--;
+            }
+            mem[b + 1] = v;
+        }
+        double v[2] = { 0.0, 0.0 };
+        v[P[k].p] = 1.0;
+        int32_t cur = P[k].lo;
+        for (int a = 0; a < nm; a++) {
+            prop2(c, (int64_t)P[mem[a]].t - cur, v);
+            apply_op(P[mem[a]].op, v);
+            cur = P[mem[a]].t;
+        }
+        prop2(c, (int64_t)P[k].hi - cur, v);
+        double den = fleg(c, P[k].p ^ P[k].q, (int64_t)P[k].hi - P[k].lo);
+        prod = prod * (v[P[k].q] / den);
+    }
+    return prod;
+}
+
+int orc_correlator(const orc_chain* c, int npt, const int32_t* pts, int ncorr, int nbase, double* out)
+{
+    if (npt < 1 || npt > 16 || ncorr < 1 || nbase < 1 || !pts || !out) return ORC_EINVAL;
+    for (int i = 0; i < npt * ncorr; i++)
+        if (pts[4 * i + 3] < 0 || pts[4 * i + 3] > 2) return ORC_EINVAL;
+    cpt_t P[16];
+    for (int cc = 0; cc < ncorr; cc++) {
+        const int32_t* q = pts + (size_t)4 * npt * cc;
+        double sum = 0.0;
+        for (int i = 0; i < c->N; i++) {
+            int x = i % c->Lx, y = i / c->Lx;
+            for (int j = 0; j < nbase; j++) {
+                int64_t tau = ((int64_t)j * c->M) / nbase;
+                for (int k = 0; k < npt; k++) {
+                    int rx = ((q[4 * k] % c->Lx) + c->Lx) % c->Lx;
+                    int ry = ((q[4 * k + 1] % c->Ly) + c->Ly) % c->Ly;
+                    P[k].site = ((y + ry) % c->Ly) * c->Lx + (x + rx) % c->Lx;
+                    P[k].t = (int32_t)((((tau + (int64_t)q[4 * k + 2]) % c->M) + c->M) % c->M);
+                    P[k].op = q[4 * k + 3];
+                    P[k].idx = k;
+                }
+                sum += corr_sample(c, P, npt);
+            }
+        }
+        out[cc] = sum / ((double)c->N * (double)nbase);
+    }
+    return ORC_OK;
+}
+
 static void scatter_phase(orc_chain* c)
 {
     int ndsp = c->p.dom_x * c->p.dom_y;

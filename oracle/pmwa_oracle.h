@@ -132,6 +132,13 @@ double orc_tanh_ell(const orc_chain* c, int64_t ell);
    source */
 int  orc_green(const orc_chain* c, const int32_t* disp, int n, double* out);
 int  orc_poisson_table(const orc_chain* c, int k, double* cdf, int cap);
+/* n-point functions on the current configuration (Supplemental S-I):
+   pts holds ncorr correlators of npt points (rx, ry, dt ticks, op), op 0 =
+   b + b^+, 1 = b, 2 = b^+; out[c] = (1/(N nbase)) sum over sites i and base
+   times tau_j = floor(j M / nbase) of the estimator of
+   < T prod_k O_k(i + r_k, tau_j + dt_k) > (a point at tick t sits at
+   t + 1/4; equal times keep the listed order, first leftmost). */
+int  orc_correlator(const orc_chain* c, int npt, const int32_t* pts, int ncorr, int nbase, double* out);
 
 /* samplers driven by a Philox stream (phase, unit) of the current sweep */
 int  orc_test_worms(orc_chain* c, uint32_t phase, uint32_t unit, int32_t ell,
