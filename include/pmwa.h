@@ -83,7 +83,8 @@ typedef struct pmwa_params {
 typedef struct pmwa_opts {
     void*   stream;           /* hipStream_t (borrowed); NULL: the handle creates
                                  one (default priority) and destroys it       */
-    int32_t scatter_mode;     /* 0 auto, 1 domain in LDS, 2 domain in HBM        */
+    int32_t scatter_mode;     /* scattering node store: 0 and 1: LDS where the
+                                 domain fits, else HBM; 2: every domain in HBM */
     int32_t series_cap;       /* per-chain device rows of per-sweep records     */
     int32_t event_cap;        /* events per (site, slab), <= 32767; 0 = from the
                                  density                                      */
@@ -96,7 +97,11 @@ typedef struct pmwa_opts {
                                  where the occupation changes fit in LDS; bit1:
                                  sort the candidates in an LDS column even
                                  where 32 registers hold them               */
-    int32_t reserved[2];
+    int32_t scatter_lds;      /* LDS bytes of the scattering kernel's LDS form (a
+                                 tuning knob: fewer bytes let more domains share a
+                                 CU, larger domains then take the HBM store); 0 =
+                                 sized for the largest expected domain       */
+    int32_t reserved[1];
 } pmwa_opts;
 
 /* Raw per-sweep record of one chain (all sums over the whole lattice). */
@@ -280,6 +285,28 @@ int pmwa_diag(pmwa_t* h, int chain, int64_t* out, int n);
    PMWA_EOVERFLOW if the chain is flagged. */
 #define PMWA_GREEN_MAX 64
 int pmwa_green(pmwa_t* h, int chain, const int32_t* disp, int n, double* out);
+
+/* n-point functions of b, b^+ and Q = b + b^+ (Supplemental S-I, any n up
+   to PMWA_CORR_MAX_POINTS) on the CURRENT configuration of `chain` (one
+   sample; average over sweeps for the thermal value).  pts holds ncorr
+   correlators of npt points each, a point being 4 int32: (rx, ry, dt, op)
+   with op 0 = b + b^+, 1 = b, 2 = b^+ and dt in ticks (all taken modulo the
+   lattice and M).  out[c] = (1/(N nbase)) sum over sites i and base times
+   tau_j = floor(j M / nbase), j < nbase, of the estimator of
+   < T prod_k O_k(i + r_k, tau_j + dt_k) >: the worms of an interval
+   (between vertices and temporal domain boundaries) are summed over, so an
+   interval holding points contributes <q| E .. O .. E |p> / <q| E |p>, E the
+   interval's propagator exp(l eta Delta Q) split at the points, operators in
+   time order (equal times: the first listed leftmost); points on different
+   intervals multiply.  A point at tick t sits at t + 1/4.  Every term is
+   >= 0.  Synchronises the handle's stream; the first call allocates a small
+   device workspace that the handle keeps.  PMWA_EINVAL on bad arguments,
+   PMWA_ESTATE / PMWA_EOVERFLOW if the chain is flagged.  At small
+   eta * (interval length) the odd-parity ratio is large (coth), so the
+   estimator of a product of many points is heavy-tailed. */
+#define PMWA_CORR_MAX_POINTS 8
+#define PMWA_CORR_MAX 64
+int pmwa_correlator(pmwa_t* h, int chain, int npt, const int32_t* pts, int ncorr, int nbase, double* out);
 
 /* pmwa_green without any allocation, for callers that cannot allocate
    device memory (code under graph capture set-up, tight serving loops,

@@ -59,6 +59,7 @@ struct ChainDev {
     double lambda, t;
     int64_t ev_off, cnt_off, bs_off, bv_off, bvc_off, dom_off, ser_off, cdf_off;
     int64_t scr_off;   // node scratch of the HBM scattering path (nodes)
+    int64_t oc_off;    // per-domain rows of site counts and offsets (HBM scattering form)
     int64_t target;    // sweeps after which the chain stops
     int32_t active;    // 0: idle slot, every kernel skips the chain
     int32_t pad1_;
@@ -98,8 +99,9 @@ struct Pools {
     uint8_t* s_fl;
     uint32_t* s_wl;
     uint32_t* s_own;
+    int32_t* s_oc;               // per domain 2 * nloc + 2 ints: site offsets, counts
     int32_t series_cap;
-    int32_t lds_nodes;           // node capacity of the LDS path (0 = off)
+    int32_t lds_bytes;           // dynamic LDS of the scattering kernel's LDS form
 };
 
 // per vertex of a cross bond in the spatial boundary update (in LDS)

@@ -25,6 +25,7 @@ namespace pmwa {
 __global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows, int vmode);
 __global__ void k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
+template <bool HBM_ONLY>
 __global__ void k_scatter(Pools P, const int2* __restrict__ blk);
 template <int LANES>
 __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
@@ -35,6 +36,7 @@ __global__ void k_finish(Pools P);
 __global__ void k_reset_acc(Pools P, int n);
 __global__ void k_hash(Pools P, int chain, unsigned long long* out);
 __global__ void k_green_sum(const double* part, int ntau, int nd, int nchunk, double norm, double* out);
+__global__ void k_corr(Pools P, int chain, const int4* pts, int npt, int nbase, int nchunk, double* part);
 }  // namespace pmwa
 
 using namespace pmwa;
@@ -89,7 +91,7 @@ struct HostChain {
     uint64_t enq_sweeps = 0, read_sweeps = 0;
     std::vector<pmwa_obs> host_rows;   // drained, not yet returned
     // what the chain's regions hold (a slot keeps these for every chain it takes)
-    int64_t cap_ev = 0, cap_su = 0, cap_bv = 0, cap_dom = 0, cap_cdf = 0, cap_scr = 0;
+    int64_t cap_ev = 0, cap_su = 0, cap_bv = 0, cap_dom = 0, cap_cdf = 0, cap_scr = 0, cap_oc = 0;
     int64_t cap_units_v = 0, cap_units_r = 0, cap_bt = 0, cap_bsx = 0, cap_bsy = 0;
     int cap_event = 0;
     bool active = true;
@@ -124,6 +126,7 @@ struct pmwa_handle {
     int rw_nmax = 4;           // bond-buffer entries of a site in a slab, at most
     size_t rw_lds = 0;
     size_t lds_bytes = 0;
+    bool scatter_hbm = false;   // the scattering kernel's HBM form (nodes, counts in device memory)
     size_t bs_lds = 0;       // LDS of the spatial-boundary kernel
     int bt_lanes = 64;       // lanes per workgroup of the temporal-boundary update (64 or 16)
     int vs = 1;              // candidate column length of the vertex kernel
@@ -146,6 +149,7 @@ struct pmwa_handle {
     double* d_gpart = nullptr;
     size_t gpart_cap = 0;
     unsigned long long* d_hash = nullptr;   // result of the state-hash reduction
+    int4* d_cpts = nullptr;                 // correlator points
     void* scratch = nullptr;                // this device's static scratch (pmwa_green_static)
 };
 
@@ -411,7 +415,12 @@ static int launch_kernel(pmwa_t* h, int phase)
         }
         break;
     case 3:
-        if (h->nblk_s) hipLaunchKernelGGL(k_scatter, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
+        if (h->nblk_s) {
+            if (h->scatter_hbm)
+                hipLaunchKernelGGL(k_scatter<true>, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
+            else
+                hipLaunchKernelGGL(k_scatter<false>, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
+        }
         break;
     case 4:
         if (h->nblk_bt) {
@@ -499,9 +508,9 @@ void pmwa_destroy(pmwa_t* h)
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
                     h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
-                    h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->d_blk_v, h->d_blk_r,
+                    h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->P.s_oc, h->d_blk_v, h->d_blk_r,
                     h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw, h->d_gdisp, h->d_gpart,
-                    h->P.acc, h->d_hash};
+                    h->P.acc, h->d_hash, h->d_cpts};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete h;
@@ -519,7 +528,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (h->opts.series_cap <= 0) h->opts.series_cap = 4096;
     if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0 ||
         h->opts.event_cap > 32767 || h->opts.regen_mode < 0 || h->opts.regen_mode > 2 ||
-        h->opts.vertex_mode < 0 || h->opts.vertex_mode > 3) { delete h; return PMWA_EINVAL; }
+        h->opts.vertex_mode < 0 || h->opts.vertex_mode > 3 || h->opts.scatter_lds < 0 ||
+        h->opts.scatter_lds > 160 * 1024) { delete h; return PMWA_EINVAL; }
     h->stream = (hipStream_t)h->opts.stream;
     if (!h->stream) {
         // work goes to a stream of the handle (default priority)
@@ -528,7 +538,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     }
     h->ch.resize(n_chains);
     int rc = PMWA_OK;
-    int64_t ev = 0, su = 0, bv = 0, bvc = 0, dom = 0, cdf = 0, scr = 0;
+    int64_t ev = 0, su = 0, bv = 0, bvc = 0, dom = 0, cdf = 0, scr = 0, oc = 0;
     int max_nloc = 1;
     for (int c = 0; c < n_chains && rc == PMWA_OK; c++) {
         HostChain& hc = h->ch[c];
@@ -574,27 +584,43 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     size_t lds_max = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds_max) lds_max = prop.maxSharedMemoryPerMultiProcessor;
     if (lds_max > 160 * 1024) lds_max = 160 * 1024;
-    const size_t fixed = 1792 * sizeof(double) + (size_t)(2 * max_nloc + 1) * sizeof(int);
+    // LDS form of the scattering kernel: the exit thresholds, the stream ring,
+    // the per-site offsets and counts, then 12 bytes per node (and the worm
+    // list).  Sized for the largest expected domain within the CU's LDS;
+    // larger domains take the HBM store.  opts.scatter_lds (bytes) overrides.
+    const size_t fixed = 768 * sizeof(uint64_t) + (size_t)(2 * max_nloc + 1) * sizeof(int);
     const size_t fixed_al = (fixed + 15) & ~(size_t)15;
-    const size_t per_node = 4 + 4 * 2 + 4 + 1;   // tick, nxt, prv, aux, wl (16-bit), owner stamp, flags
-    // nodes wanted: the largest expected domain with margin
-    double want = 0.0;
+    double want = 0.0;                 // nodes of the largest expected domain, with margin
     for (auto& hc : h->ch) {
         const double m = mean_events(hc.p, hc.rho_max) * 0.75;
         want = std::max(want, hc.d.nloc * (m * 1.3 + 2.0) + 64.0);
     }
-    size_t lds_nodes = 0;
-    if (h->opts.scatter_mode != 2 && fixed_al + 64 * per_node < lds_max) {
-        lds_nodes = (lds_max - fixed_al) / per_node;
-        lds_nodes = std::min<size_t>(lds_nodes, (size_t)std::ceil(want));
-        lds_nodes = std::min<size_t>(lds_nodes, 65520);
-        lds_nodes &= ~(size_t)15;
+    const int smode = h->opts.scatter_mode;
+    size_t lds = 0;
+    if (smode != 2) {
+        lds = h->opts.scatter_lds > 0 ? (size_t)h->opts.scatter_lds
+                                      : fixed_al + (size_t)std::ceil(want * 12.5) + 256;
+        // many domains: at most 80 KB, so that two domains share a CU (the
+        // larger ones take the HBM store); measured best on the 256-chain batch
+        int64_t ndom = 0;
+        for (auto& hc : h->ch) ndom += hc.n_dom;
+        if (h->opts.scatter_lds == 0 && ndom >= 2LL * std::max(prop.multiProcessorCount, 1))
+            lds = std::min<size_t>(lds, 80 * 1024);
+        lds = std::min(lds, lds_max);
+        lds = std::max(lds, fixed_al + 64);
+        lds = (lds + 15) & ~(size_t)15;
+        if (lds > lds_max) lds = 0;        // not even the fixed region fits: HBM form
     }
-    h->P.lds_nodes = (int32_t)lds_nodes;
-    h->lds_bytes = fixed_al + lds_nodes * per_node + 16;
-    if (int e = set_lds((const void*)k_scatter, h->lds_bytes, lds_max)) {
-        pmwa_destroy(h);
-        return e;
+    h->scatter_hbm = lds == 0;
+    h->P.lds_bytes = (int32_t)lds;
+    h->lds_bytes = h->scatter_hbm ? 768 * sizeof(uint64_t) + 16 : lds;
+    {
+        const int e = h->scatter_hbm ? set_lds((const void*)k_scatter<true>, h->lds_bytes, lds_max)
+                                     : set_lds((const void*)k_scatter<false>, h->lds_bytes, lds_max);
+        if (e) {
+            pmwa_destroy(h);
+            return e;
+        }
     }
     // HBM node scratch for domains beyond the LDS capacity
     for (auto& hc : h->ch) {
@@ -606,6 +632,9 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         d.scr_off = scr;
         scr += nodes * hc.n_dom;
         hc.cap_scr = nodes * hc.n_dom;
+        d.oc_off = oc;
+        hc.cap_oc = hc.n_dom * (2LL * d.nloc + 2);
+        oc += hc.cap_oc;
     }
 
     h->ev_total = ev;
@@ -629,6 +658,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     h->P.s_fl = dalloc<uint8_t>(scr, &rc);
     h->P.s_wl = dalloc<uint32_t>(scr, &rc);
     h->P.s_own = dalloc<uint32_t>(scr, &rc);
+    h->P.s_oc = dalloc<int32_t>(oc, &rc);
     h->d_cd = dalloc<ChainDev>(n_chains, &rc);
     h->d_cdf = dalloc<double>(cdf, &rc);
     if (rc) { pmwa_destroy(h); return rc; }
@@ -763,7 +793,7 @@ static int slot_fit(pmwa_t* h, int slot, const pmwa_params* p, HostChain& job)
         (int64_t)job.cdf.size() > hc.cap_cdf || job.n_units_v > hc.cap_units_v ||
         job.n_units_r > hc.cap_units_r || job.n_bt > hc.cap_bt || job.n_bsx > hc.cap_bsx ||
         job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc || d.cdf_stride > h->vs ||
-        (h->regen_wave && 4 * d.capb > h->rw_nmax))
+        (h->regen_wave && 4 * d.capb > h->rw_nmax) || job.n_dom * (2LL * d.nloc + 2) > hc.cap_oc)
         return PMWA_EINVAL;
     return PMWA_OK;
 }
@@ -788,6 +818,7 @@ int pmwa_slot_load(pmwa_t* h, int slot, const pmwa_params* p, int64_t target_swe
     d.ev_off = s.ev_off; d.cnt_off = s.cnt_off; d.bs_off = s.bs_off; d.bv_off = s.bv_off;
     d.bvc_off = s.bvc_off; d.dom_off = s.dom_off; d.ser_off = s.ser_off; d.cdf_off = s.cdf_off;
     d.scr_off = s.scr_off;
+    d.oc_off = s.oc_off;
     d.scr_nodes = (int32_t)std::min<int64_t>(hc.cap_scr / std::max<int64_t>(job.n_dom, 1), 0x7FFFFFFF);
     d.active = 1;
     d.target = target_sweeps;
@@ -1109,6 +1140,55 @@ int pmwa_state_hash(pmwa_t* h, int chain, uint64_t* out)
     HIPCHK(hipMemcpyAsync(&v, h->d_hash, sizeof(v), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     *out = (uint64_t)v;
+    return PMWA_OK;
+}
+
+int pmwa_correlator(pmwa_t* h, int chain, int npt, const int32_t* pts, int ncorr, int nbase, double* out)
+{
+    if (!h || chain < 0 || chain >= (int)h->ch.size() || npt < 1 || npt > PMWA_CORR_MAX_POINTS || ncorr < 1 ||
+        ncorr > PMWA_CORR_MAX || nbase < 1 || nbase > (1 << 20) || !pts || !out)
+        return PMWA_EINVAL;
+    const ChainDev& d = h->ch[chain].d;
+    std::vector<int4> pv((size_t)ncorr * npt);
+    for (int q = 0; q < ncorr * npt; q++) {
+        const int32_t* r = pts + 4 * (size_t)q;
+        if (r[3] < 0 || r[3] > 2) return PMWA_EINVAL;
+        pv[q] = make_int4(((r[0] % d.Lx) + d.Lx) % d.Lx, ((r[1] % d.Ly) + d.Ly) % d.Ly,
+                          (int)((((int64_t)r[2] % d.M) + d.M) % d.M), r[3]);
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    unsigned int fl = 0;
+    HIPCHK(hipMemcpy(&fl, h->P.flags + chain, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl) return (fl & 1u) ? PMWA_EOVERFLOW : PMWA_ESTATE;
+    const long long pairs = (long long)d.N * nbase;
+    const long long nchunk = (pairs + 63) / 64;
+    const long long nblk = nchunk * ncorr;
+    if (nblk > 0x7FFFFFFFLL) return PMWA_EINVAL;
+    if (!h->d_cpts &&
+        hipMalloc(&h->d_cpts, (size_t)PMWA_CORR_MAX * PMWA_CORR_MAX_POINTS * sizeof(int4)) != hipSuccess) {
+        h->d_cpts = nullptr;
+        return PMWA_ENOMEM;
+    }
+    if ((size_t)nblk > h->gpart_cap) {
+        if (h->d_gpart) (void)hipFree(h->d_gpart);
+        h->d_gpart = nullptr;
+        h->gpart_cap = 0;
+        if (hipMalloc(&h->d_gpart, (size_t)nblk * sizeof(double)) != hipSuccess) return PMWA_ENOMEM;
+        h->gpart_cap = (size_t)nblk;
+    }
+    HIPCHK(hipMemcpyAsync(h->d_cpts, pv.data(), pv.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL(k_corr, dim3((unsigned)nblk), dim3(64), 0, h->stream, h->P, chain, h->d_cpts, npt, nbase,
+                       (int)nchunk, h->d_gpart);
+    HIPCHK(hipGetLastError());
+    std::vector<double> part((size_t)nblk);
+    HIPCHK(hipMemcpyAsync(part.data(), h->d_gpart, nblk * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const double norm = (double)d.N * (double)nbase;
+    for (int c = 0; c < ncorr; c++) {
+        double sum = 0.0;
+        for (long long b = 0; b < nchunk; b++) sum += part[(size_t)c * nchunk + b];
+        out[c] = sum / norm;
+    }
     return PMWA_OK;
 }
 

@@ -601,14 +601,63 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
 // sentinels) held in LDS with 16-bit links when they fit, else in an HBM
 // scratch region with 32-bit links.
 // ===========================================================================
-template <typename Idx>
-struct Nodes {
+// A node as the window evaluation reads it: tick and flags
+struct NodeRec {
+    int32_t t;
+    uint32_t f;
+};
+
+// Node store in device memory (the HBM form): 32-bit links, separate tick
+// and flag arrays, one owner stamp per node.
+struct HbmStore {
     int32_t* tick;
-    Idx* nxt;
-    Idx* prv;
-    Idx* aux;        // partner end of a vertex
+    uint32_t* nxt;
+    uint32_t* prv;
+    uint32_t* aux;   // partner end of a vertex
     uint8_t* fl;
-    Idx* wl;         // worm list
+    uint32_t* wl;    // worm list
+    uint32_t* own;   // owner stamps (setup and measurement scratch as well)
+    static constexpr bool in_lds = false;
+    PMWA_DEV NodeRec rec(uint32_t i) const { NodeRec r; r.t = tick[i]; r.f = fl[i]; return r; }
+    // the flags (the tick is not needed by the caller)
+    PMWA_DEV NodeRec rec_f(uint32_t i) const { NodeRec r; r.t = 0; r.f = fl[i]; return r; }
+    PMWA_DEV int32_t tk(uint32_t i) const { return tick[i]; }
+    PMWA_DEV void put(uint32_t i, int32_t t, uint32_t f) { tick[i] = t; fl[i] = (uint8_t)f; }
+    // new flags of a node whose tick t is unchanged
+    PMWA_DEV void put_fl(uint32_t i, int32_t, uint32_t f) { fl[i] = (uint8_t)f; }
+    PMWA_DEV uint32_t* stamp(uint32_t i) { return own + i; }
+    PMWA_DEV static int stamps(int nn) { return nn; }
+};
+
+// Node store in LDS (the LDS form), 12 bytes a node: one 32-bit word
+// (tick - T_k) << 5 | flags, 16-bit links (next, previous, partner end) and
+// an owner stamp shared by the nodes 2m and 2m + 1 (sharing can only end a
+// window early, never let a conflict through).  Flag bits 0-3 are those of
+// the event info; bit 4 (F_SBOT) marks every node a worm bounces off: the
+// sentinels at the slab ends and the vertices of crossing bonds.
+struct LdsStore {
+    uint32_t* w;
+    uint16_t* nxt;
+    uint16_t* prv;
+    uint16_t* aux;
+    uint16_t* wl;
+    uint32_t* own;
+    int32_t base;    // T_k
+    static constexpr bool in_lds = true;
+    PMWA_DEV NodeRec rec(uint32_t i) const
+    {
+        const uint32_t x = w[i];
+        NodeRec r;
+        r.t = base + (int32_t)(x >> 5);
+        r.f = x & 31u;
+        return r;
+    }
+    PMWA_DEV NodeRec rec_f(uint32_t i) const { return rec(i); }
+    PMWA_DEV int32_t tk(uint32_t i) const { return base + (int32_t)(w[i] >> 5); }
+    PMWA_DEV void put(uint32_t i, int32_t t, uint32_t f) { w[i] = ((uint32_t)(t - base) << 5) | f; }
+    PMWA_DEV void put_fl(uint32_t i, int32_t t, uint32_t f) { put(i, t, f); }
+    PMWA_DEV uint32_t* stamp(uint32_t i) { return own + (i >> 1); }
+    PMWA_DEV static int stamps(int nn) { return (nn + 1) >> 1; }
 };
 
 // floor(w * n / 2^64) for n < 2^32, exact
@@ -625,10 +674,10 @@ PMWA_DEV uint32_t below32(uint64_t w, uint32_t n)
 // earlier instruction without waiting for it; only the compiler must keep
 // the program order of the accesses.  With the node store in HBM the full
 // barrier (and its wait for the memory operations) stays.
-template <typename Idx>
+template <class Store>
 PMWA_DEV void wave_order()
 {
-    if constexpr (sizeof(Idx) == 2) {
+    if constexpr (Store::in_lds) {
         asm volatile("" ::: "memory");
         __builtin_amdgcn_wave_barrier();
     } else {
@@ -658,10 +707,10 @@ PMWA_DEV void wave_order()
 // the same before and after, Eq. (DB)), leaves by leg j with probability
 // w_ji/w_i, lands on a uniform free slot of leg j and faces away from the
 // vertex.
-template <typename Idx>
-PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
-                                   int NN, int nw, const ChainDev& C, uint32_t sweep, uint32_t D,
-                                   const uint64_t* __restrict__ sthr, unsigned int* flag)
+template <class Store>
+PMWA_DEV long long scatter_windows(Store& A, uint64_t* __restrict__ ring, int NN, int nw, const ChainDev& C,
+                                   uint32_t sweep, uint32_t D, const uint64_t* __restrict__ sthr,
+                                   unsigned int* flag)
 {
     long long windows = 0;
     const int lane = (int)threadIdx.x;
@@ -686,10 +735,10 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             filled += 128u;
         }
         if (++wid == (1u << 23)) {
-            for (int i = lane; i < NN; i += 64) own[i] = 0u;
+            for (int i = lane; i < Store::stamps(NN); i += 64) A.own[i] = 0u;
             wid = 1;
         }
-        wave_order<Idx>();
+        wave_order<Store>();
         const bool act = s0 + lane < total;
         // the attempt's three stream words, read with the first loads of the
         // window (the empty asm below consumes them before the decision, so
@@ -712,7 +761,8 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         uint32_t pk0 = k0, pk1 = k1;
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(w));
-        const uint32_t fw = (uint32_t)A.fl[w] ^ ((rep & 1) ? F_DIRUP : 0u);
+        const NodeRec rw = A.rec_f(w);
+        const uint32_t fw = rw.f ^ ((rep & 1) ? F_DIRUP : 0u);
         const uint32_t pw = A.prv[w];
         const uint32_t nn_ = A.nxt[w];
         philox_rounds<2>(po, pk0, pk1);
@@ -720,25 +770,29 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         const bool up = (fw & F_DIRUP) != 0;
         const uint32_t x = up ? nn_ : pw;
         const uint32_t wf = up ? pw : nn_;
-        const uint32_t fx = A.fl[x];
-        const int32_t t = A.tick[x];
+        const NodeRec rx = A.rec(x);
+        const uint32_t fx = rx.f;
+        const int32_t t = rx.t;
         const uint32_t ya = A.aux[x];
         const uint32_t xfa = up ? A.nxt[x] : A.prv[x];
-        const int32_t t_wf = A.tick[wf];
-        const uint32_t f_wf = A.fl[wf];
+        const NodeRec rwf = A.rec(wf);
+        const int32_t t_wf = rwf.t;
+        const uint32_t f_wf = rwf.f;
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fx), "v"(ya), "v"(xfa));
         const bool blocked = (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) != 0;
         const uint32_t y = blocked ? w : ya;
         const uint32_t xf = blocked ? w : xfa;
-        const uint32_t fy = A.fl[y];
+        const uint32_t fy = A.rec_f(y).f;
         const uint32_t yp = A.prv[y];
         const uint32_t yn = A.nxt[y];
-        const int32_t t_xf = A.tick[xf];
-        const uint32_t f_xf = A.fl[xf];
-        const int32_t t_yp = A.tick[yp];
-        const uint32_t f_yp = A.fl[yp];
-        const int32_t t_yn = A.tick[yn];
+        const NodeRec rxf = A.rec(xf);
+        const int32_t t_xf = rxf.t;
+        const uint32_t f_xf = rxf.f;
+        const NodeRec ryp = A.rec(yp);
+        const int32_t t_yp = ryp.t;
+        const uint32_t f_yp = ryp.f;
+        const int32_t t_yn = A.tk(yn);
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fy), "v"(yp), "v"(yn));
         philox_rounds<2>(po, pk0, pk1);
@@ -797,36 +851,36 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
         //      earlier one writes ends the window.
         const uint32_t stamp = (wid << 8) | (uint32_t)(255 - lane);
         if (moved) {
-            atomicMax(&own[pw], stamp);
-            atomicMax(&own[nn_], stamp);
-            atomicMax(&own[Pn], stamp);
-            atomicMax(&own[Nn], stamp);
+            atomicMax(A.stamp(pw), stamp);
+            atomicMax(A.stamp(nn_), stamp);
+            atomicMax(A.stamp(Pn), stamp);
+            atomicMax(A.stamp(Nn), stamp);
         }
-        wave_order<Idx>();
+        wave_order<Store>();
         // stamps of earlier windows are below wid << 8; in this window a
         // stamp exceeds the lane's own value exactly when an earlier lane set
         // it.  A blocked attempt's x- and y-side nodes are the worm and its
         // neighbours, so it tests the three nodes it reads.
-        const uint32_t v = max(max(max(own[w], own[pw]), max(own[nn_], own[xf])),
-                               max(max(own[y], own[yp]), own[yn]));
+        const uint32_t v = max(max(max(*A.stamp(w), *A.stamp(pw)), max(*A.stamp(nn_), *A.stamp(xf))),
+                               max(max(*A.stamp(y), *A.stamp(yp)), *A.stamp(yn)));
         const bool conflict = !act || v > stamp;
         const unsigned long long cmask = __ballot(conflict);
         const int kc = cmask ? __ffsll((long long)cmask) - 1 : 64;
         // ---- apply the surviving attempts (disjoint nodes)
         if (lane < kc) {
             if (!moved) {
-                if (lane + nw >= kc) A.fl[w] = (uint8_t)(fw ^ F_DIRUP);   // the worm's last attempt here
+                if (lane + nw >= kc) A.put_fl(w, rw.t, fw ^ F_DIRUP);   // the worm's last attempt here
             } else {
-                if (!up) A.fl[x] = (uint8_t)fx_now;
-                A.nxt[pw] = (Idx)nn_;
-                A.prv[nn_] = (Idx)pw;
-                if (above) A.fl[Pn] = (uint8_t)(fv ^ F_UP);
-                A.tick[w] = ntick;
-                A.fl[w] = (uint8_t)(F_WORM | (above ? F_DIRUP : 0u) | newup);
-                A.prv[w] = (Idx)Pn;
-                A.nxt[w] = (Idx)Nn;
-                A.nxt[Pn] = (Idx)w;
-                A.prv[Nn] = (Idx)w;
+                // (x and y are the two ends of one vertex: both at tick t)
+                if (!up) A.put_fl(x, t, fx_now);
+                A.nxt[pw] = nn_;
+                A.prv[nn_] = pw;
+                if (above) A.put_fl(Pn, t, fv ^ F_UP);
+                A.put(w, ntick, F_WORM | (above ? F_DIRUP : 0u) | newup);
+                A.prv[w] = Pn;
+                A.nxt[w] = Nn;
+                A.nxt[Pn] = w;
+                A.prv[Nn] = w;
             }
         }
         // the speculative words go in when the ring has room: this window
@@ -837,7 +891,7 @@ PMWA_DEV long long scatter_windows(Nodes<Idx>& A, uint32_t* __restrict__ own, ui
             ring[(filled + 2u * lane + 1u) & 511u] = ((uint64_t)po[3] << 32) | po[2];
             filled += 128u;
         }
-        wave_order<Idx>();
+        wave_order<Store>();
         cur += 3u * (uint32_t)kc;
         s0 += kc;
         // (iw0 + kc) mod nw: lane kc's position offset, read from its register
@@ -861,9 +915,8 @@ PMWA_DEV int wave_excl_scan(int v, int& total)
     return x - v;
 }
 
-template <typename Idx>
 PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D,
-                             Nodes<Idx> A, uint32_t* __restrict__ own, uint64_t* __restrict__ ring,
+                             HbmStore A, uint64_t* __restrict__ ring,
                              const int* __restrict__ off, const int* __restrict__ cnt,
                              const uint64_t* __restrict__ sthr, const double* __restrict__ sE, int NE)
 {
@@ -871,7 +924,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
     const int nloc = C.nloc, ex = C.ex, ey = C.ey;
     const uint32_t BOT = (uint32_t)NE, TOP = (uint32_t)(NE + nloc);
-    const Idx NIL = (Idx)~(Idx)0;
+    const uint32_t NIL = 0xFFFFFFFFu;
+    uint32_t* own = A.own;
 
     // Steps 1-3 take one lane per site and walk the site's events in order.
     // The vertices of a bond carry the same ticks on its two sites, so the
@@ -882,7 +936,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     // count, then per site (from off[s]) the node of every vertex, grouped by
     // direction.
     uint16_t* vtab = reinterpret_cast<uint16_t*>(own);
-    Idx* vnode = reinterpret_cast<Idx*>(vtab + 4 * nloc);
+    uint32_t* vnode = reinterpret_cast<uint32_t*>(vtab + 4 * nloc);
 
     // 1. nodes from the events (loads of consecutive sites are adjacent in
     //    HBM), the sentinels, and the vertex count per direction; vertices
@@ -912,8 +966,8 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                     const bool v = (f & F_WORM) == 0u;
                     A.tick[idx] = (int32_t)e[u].x;
                     A.fl[idx] = (uint8_t)(f | ((v && ((crm >> vd) & 1u)) ? F_CROSS : 0u));
-                    A.prv[idx] = (Idx)(j > 0 ? idx - 1u : BOT + (uint32_t)s);
-                    A.nxt[idx] = (Idx)(j + 1 < n ? idx + 1u : TOP + (uint32_t)s);
+                    A.prv[idx] = (j > 0 ? idx - 1u : BOT + (uint32_t)s);
+                    A.nxt[idx] = (j + 1 < n ? idx + 1u : TOP + (uint32_t)s);
                     A.aux[idx] = NIL;
                     c0 += v && vd == 0u;
                     c1 += v && vd == 1u;
@@ -929,12 +983,12 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
         A.tick[BOT + s] = Tk;
         A.fl[BOT + s] = (uint8_t)(F_SBOT | (bsv ? F_UP : 0u));
-        A.nxt[BOT + s] = (Idx)(n ? (uint32_t)o : TOP + s);
+        A.nxt[BOT + s] = (n ? (uint32_t)o : TOP + s);
         A.prv[BOT + s] = NIL;
         A.aux[BOT + s] = NIL;
         A.tick[TOP + s] = Tk1;
         A.fl[TOP + s] = (uint8_t)F_STOP;
-        A.prv[TOP + s] = (Idx)(n ? (uint32_t)(o + n - 1) : BOT + s);
+        A.prv[TOP + s] = (n ? (uint32_t)(o + n - 1) : BOT + s);
         A.nxt[TOP + s] = NIL;
         A.aux[TOP + s] = NIL;
     }
@@ -963,10 +1017,10 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                         const uint32_t f = fb[u];
                         const uint32_t vd = (f >> 1) & 3u;
                         if (f & F_WORM) {
-                            A.wl[rw++] = (Idx)idx;
+                            A.wl[rw++] = idx;
                         } else {
                             const int r = vd == 0u ? r0 : vd == 1u ? r1 : vd == 2u ? r2 : r3;
-                            vnode[o + r] = (Idx)idx;
+                            vnode[o + r] = idx;
                             r0 += vd == 0u;
                             r1 += vd == 1u;
                             r2 += vd == 2u;
@@ -1002,14 +1056,14 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             const int nown = st[d + 1] - st[d];
             bad3 |= nown != nb_hi - nb_lo;
             const int m_n = nown < nb_hi - nb_lo ? nown : nb_hi - nb_lo;
-            const Idx* own_v = vnode + o + st[d];
-            const Idx* nb_v = vnode + off[nb] + nb_lo;
+            const uint32_t* own_v = vnode + o + st[d];
+            const uint32_t* nb_v = vnode + off[nb] + nb_lo;
 #pragma unroll 4
             for (int r = 0; r < m_n; r++) {
                 const uint32_t idx = (uint32_t)own_v[r];
                 const uint32_t m = (uint32_t)nb_v[r];
                 bad3 |= A.tick[idx] != A.tick[m];
-                A.aux[idx] = (Idx)m;
+                A.aux[idx] = m;
             }
         }
     }
@@ -1020,7 +1074,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     // 4. N_cycle cycles, worms in list order, evaluated in windows
     for (int i = lane; i < NE + 2 * nloc; i += 64) own[i] = 0u;
     __syncthreads();
-    const long long windows = scatter_windows(A, own, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
+    const long long windows = scatter_windows(A, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
                                               (uint32_t)D, sthr, &P.flags[chain]);
 
     // 5. measurement (Step 6) and write-back.  One lane per site follows the
@@ -1123,8 +1177,297 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     }
 }
 
-// dynamic LDS: [exit thresholds 256 x u64][expm1 table 1024 doubles][ring 512 words][off nloc+1][cnt nloc][nodes: tick 4B, nxt, prv,
-// aux, wl 2B each, fl 1B]
+// The LDS form of one domain (12-byte nodes, see LdsStore).  `mem` is the
+// LDS after the fixed region, `bytes` long.  Returns false, having written
+// nothing outside LDS, when the domain's nodes or its worm list do not fit;
+// the caller then takes the HBM store.
+PMWA_DEV bool scatter_domain_lds(const Pools& P, const ChainDev& C, int chain, int D, unsigned char* mem,
+                                 size_t bytes, uint64_t* __restrict__ ring, const int* __restrict__ off,
+                                 const int* __restrict__ cnt, const uint64_t* __restrict__ sthr, int NE)
+{
+    const int lane = (int)threadIdx.x;
+    const int k = D / C.ndsp, dsp = D - k * C.ndsp;
+    const int nloc = C.nloc, ex = C.ex, ey = C.ey;
+    const int NN = NE + 2 * nloc;
+    const uint32_t BOT = (uint32_t)NE, TOP = (uint32_t)(NE + nloc);
+    const uint16_t NIL = 0xFFFFu;
+    const int32_t Tk = C.T[k], Tk1 = C.T[k + 1];
+    // carve (arrays of an even length, so that each starts 4-byte aligned):
+    // words, stamps, links, partner ends, then the worm list
+    const size_t NNa = (size_t)((NN + 1) & ~1);
+    const size_t nst = NNa / 2;
+    const size_t fixed_b = NNa * 4 + nst * 4 + NNa * 6;
+    if (NN >= 65535 || (long long)(Tk1 - Tk) >= (1LL << 27) || fixed_b + 64 > bytes) return false;
+    const int wl_cap = (int)((bytes - fixed_b) / 2);
+    LdsStore A;
+    unsigned char* q = mem;
+    A.w = reinterpret_cast<uint32_t*>(q); q += NNa * 4;
+    A.own = reinterpret_cast<uint32_t*>(q); q += nst * 4;
+    A.nxt = reinterpret_cast<uint16_t*>(q); q += NNa * 2;
+    A.prv = reinterpret_cast<uint16_t*>(q); q += NNa * 2;
+    A.aux = reinterpret_cast<uint16_t*>(q); q += NNa * 2;
+    A.wl = reinterpret_cast<uint16_t*>(q);
+    A.base = Tk;
+    // Until the windows start, the stamps' memory (2 NN bytes) holds the
+    // rank tables of the partner search: the node of every vertex, per site
+    // (from off[s]) grouped by direction, then per site the vertex counts of
+    // the four directions, 8 bits each.  The partner of the r-th vertex of
+    // direction d on a site is the r-th vertex of direction d ^ 2 on the
+    // neighbouring site (the two ends of a vertex carry the same tick).
+    uint16_t* vnode = reinterpret_cast<uint16_t*>(A.own);
+    uint32_t* dcnt = reinterpret_cast<uint32_t*>(vnode + NE + (NE & 1));
+
+    // 1. nodes from the events (loads of consecutive sites are adjacent in
+    //    HBM), the sentinels, the vertex counts per direction; vertices of
+    //    bonds that leave the domain are marked as nodes a worm bounces off
+    bool big = false;
+    for (int s = lane; s < nloc; s += 64) {
+        const int o = off[s], n = cnt[s];
+        const int lx = s % ex, ly = s / ex;
+        const uint32_t crm = ((C.dom_x > 1 && lx == ex - 1) ? 1u : 0u) | ((C.dom_y > 1 && ly == ey - 1) ? 2u : 0u) |
+                             ((C.dom_x > 1 && lx == 0) ? 4u : 0u) | ((C.dom_y > 1 && ly == 0) ? 8u : 0u);
+        const uint2* E = P.ev + ev_base(C, k, dsp, s);
+        int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (int j0 = 0; j0 < n; j0 += 16) {
+            uint2 e[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++)
+                if (j0 + u < n) e[u] = E[(long long)(j0 + u) * nloc];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int j = j0 + u;
+                if (j < n) {
+                    const uint32_t idx = (uint32_t)(o + j);
+                    const uint32_t f = e[u].y & 15u;
+                    const uint32_t vd = (f >> 1) & 3u;
+                    const bool v = (f & F_WORM) == 0u;
+                    A.w[idx] = ((e[u].x - (uint32_t)Tk) << 5) | f | ((v && ((crm >> vd) & 1u)) ? F_SBOT : 0u);
+                    A.prv[idx] = (uint16_t)(j > 0 ? idx - 1u : BOT + (uint32_t)s);
+                    A.nxt[idx] = (uint16_t)(j + 1 < n ? idx + 1u : TOP + (uint32_t)s);
+                    A.aux[idx] = NIL;
+                    c0 += v && vd == 0u;
+                    c1 += v && vd == 1u;
+                    c2 += v && vd == 2u;
+                    c3 += v && vd == 3u;
+                }
+            }
+        }
+        big |= (c0 | c1 | c2 | c3) > 255;
+        dcnt[s] = (uint32_t)c0 | ((uint32_t)c1 << 8) | ((uint32_t)c2 << 16) | ((uint32_t)c3 << 24);
+        const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
+        A.w[BOT + s] = F_SBOT | (bsv ? F_UP : 0u);
+        A.nxt[BOT + s] = (uint16_t)(n ? (uint32_t)o : TOP + s);
+        A.prv[BOT + s] = NIL;
+        A.aux[BOT + s] = NIL;
+        A.w[TOP + s] = ((uint32_t)(Tk1 - Tk) << 5) | F_SBOT;
+        A.prv[TOP + s] = (uint16_t)(n ? (uint32_t)(o + n - 1) : BOT + s);
+        A.nxt[TOP + s] = NIL;
+        A.aux[TOP + s] = NIL;
+    }
+    if (__any(big)) return false;          // a direction count beyond 8 bits: HBM store
+    __syncthreads();
+    // 2. vertex nodes by (site, direction, rank), and the worm list in
+    //    (site, slot) order = node order
+    int nw = 0;
+    for (int base = 0; base < nloc; base += 64) {
+        const int s = base + lane;
+        uint32_t dc = 0;
+        int ns = 0;
+        if (s < nloc) {
+            dc = dcnt[s];
+            ns = cnt[s] - (int)((dc & 255u) + ((dc >> 8) & 255u) + ((dc >> 16) & 255u) + (dc >> 24));
+        }
+        int tot;
+        int pos = nw + wave_excl_scan(ns, tot);
+        if (s < nloc) {
+            const int o = off[s], n = cnt[s];
+            int r0 = 0, r1 = (int)(dc & 255u), r2 = r1 + (int)((dc >> 8) & 255u), r3 = r2 + (int)((dc >> 16) & 255u);
+            for (int j0 = 0; j0 < n; j0 += 8) {
+                uint32_t wb[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) wb[u] = j0 + u < n ? A.w[o + j0 + u] : 0u;
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    if (j0 + u < n) {
+                        const uint32_t idx = (uint32_t)(o + j0 + u);
+                        const uint32_t vd = (wb[u] >> 1) & 3u;
+                        if (wb[u] & F_WORM) {
+                            if (pos < wl_cap) A.wl[pos] = (uint16_t)idx;
+                            pos++;
+                        } else {
+                            const int r = vd == 0u ? r0 : vd == 1u ? r1 : vd == 2u ? r2 : r3;
+                            vnode[o + r] = (uint16_t)idx;
+                            r0 += vd == 0u;
+                            r1 += vd == 1u;
+                            r2 += vd == 2u;
+                            r3 += vd == 3u;
+                        }
+                    }
+                }
+            }
+        }
+        nw += tot;
+    }
+    if (nw > wl_cap) return false;
+    __syncthreads();
+    // 3. partner ends: per site and direction (bonds inside the domain), the
+    //    r-th vertex of direction d is matched with the r-th vertex of
+    //    direction d ^ 2 on the neighbour (independent iterations)
+    bool bad3 = false;
+    for (int s = lane; s < nloc; s += 64) {
+        const int o = off[s];
+        const int lx = s % ex, ly = s / ex;
+        const uint32_t dc = dcnt[s];
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            const bool cross = d == 0 ? (C.dom_x > 1 && lx == ex - 1) : d == 1 ? (C.dom_y > 1 && ly == ey - 1)
+                             : d == 2 ? (C.dom_x > 1 && lx == 0) : (C.dom_y > 1 && ly == 0);
+            if (cross) continue;
+            const int nb = d == 0 ? (lx == ex - 1 ? s - (ex - 1) : s + 1)
+                         : d == 1 ? (ly == ey - 1 ? s - (ey - 1) * ex : s + ex)
+                         : d == 2 ? (lx == 0 ? s + (ex - 1) : s - 1)
+                                  : (ly == 0 ? s + (ey - 1) * ex : s - ex);
+            const int pd = d ^ 2;
+            const uint32_t dn = dcnt[nb];
+            int st = 0, nst_ = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                st += q < d ? (int)((dc >> (8 * q)) & 255u) : 0;
+                nst_ += q < pd ? (int)((dn >> (8 * q)) & 255u) : 0;
+            }
+            const int nown = (int)((dc >> (8 * d)) & 255u), nnb = (int)((dn >> (8 * pd)) & 255u);
+            bad3 |= nown != nnb;
+            const int m_n = nown < nnb ? nown : nnb;
+            const uint16_t* own_v = vnode + o + st;
+            const uint16_t* nb_v = vnode + off[nb] + nst_;
+#pragma unroll 4
+            for (int r = 0; r < m_n; r++) {
+                const uint32_t idx = own_v[r];
+                const uint32_t m = nb_v[r];
+                bad3 |= (A.w[idx] >> 5) != (A.w[m] >> 5);
+                A.aux[idx] = (uint16_t)m;
+            }
+        }
+    }
+    if (bad3) atomicOr(&P.flags[chain], FL_STATE);
+    __syncthreads();
+    if (__any(P.flags[chain] != 0)) return true;
+
+    // 4. N_cycle cycles, worms in list order, evaluated in windows
+    for (int i = lane; i < (int)nst; i += 64) A.own[i] = 0u;
+    __syncthreads();
+    const long long windows = scatter_windows(A, ring, NN, nw, C, (uint32_t)P.sweep[chain], (uint32_t)D, sthr,
+                                              &P.flags[chain]);
+
+    // 5. measurement (Step 6) and write-back.  One lane per site follows the
+    //    site's node list and writes the events back; the length and worm
+    //    parity of every interval between vertices go to a table (in the
+    //    memory of the previous-node and partner links, 4 NN bytes, which the
+    //    walk does not read; site s has at most cnt[s] + 1 intervals, from
+    //    slot off[s] + s), whose terms of the improved worm-density estimator
+    //    all lanes then evaluate at once.
+    __syncthreads();
+    uint32_t* qint = reinterpret_cast<uint32_t*>(A.prv);
+    for (int i = lane; i < NE + nloc; i += 64) qint[i] = 0u;
+    __syncthreads();
+    const int capc = C.cap;
+    const long long cnt_base = C.cnt_off + unit_su(C, k, dsp, 0);
+    const long long ev_base0 = ev_base(C, k, dsp, 0);
+    long long nv = 0, nkink = 0, nwc = 0, occ = 0;
+    bool bad = false;
+    for (int s = lane; s < nloc; s += 64) {
+        const long long ebase = ev_base0 + s;
+        uint32_t* qi = qint + off[s] + s;
+        const int qmax = cnt[s] + 1;
+        int nq = 0;
+        int stt = (int)((A.w[BOT + s] >> 3) & 1u);
+        int32_t lastp = 2 * Tk;                 // positions in half ticks (< 2^31)
+        int32_t ilo = Tk;
+        uint32_t par = 0;
+        int j = 0;
+        uint32_t node = A.nxt[BOT + s];
+        int guard = 0;
+        int occs = 0, nvs = 0, nks = 0, nws_ = 0;
+        for (;;) {
+            if (node == TOP + (uint32_t)s) {
+                occs += stt * (2 * Tk1 - lastp);
+                if (nq < qmax) qi[nq] = ((uint32_t)(Tk1 - ilo) << 1) | par;
+                else bad = true;
+                break;
+            }
+            if (node >= (uint32_t)NE || ++guard > NE) { bad = true; break; }
+            const NodeRec r = A.rec(node);
+            const uint32_t f = r.f;
+            const int32_t tk = r.t;
+            const uint32_t nx = A.nxt[node];
+            const uint32_t isw = f & F_WORM, isv = isw ^ 1u;
+            const int32_t pos = 2 * tk + (int32_t)isw;
+            occs += stt * (pos - lastp);
+            lastp = pos;
+            // the interval below a vertex ends here; a worm writes the same
+            // slot, which the next vertex or the top of the slab overwrites
+            qi[nq < qmax ? nq : qmax - 1] = ((uint32_t)(tk - ilo) << 1) | par;
+            nq += (int)isv;
+            nws_ += (int)isw;
+            const uint32_t own_v = isv & (((f >> 1) & 3u) < 2u ? 1u : 0u);
+            nvs += (int)own_v;
+            nks += (int)(own_v & ((((f >> 3) & 1u) != (uint32_t)stt) ? 1u : 0u));
+            ilo = isv ? tk : ilo;
+            par = isv ? 0u : (par ^ 1u);
+            stt = (int)((f >> 3) & 1u);
+            if (j < capc) P.ev[ebase + (long long)j * nloc] = make_uint2((uint32_t)tk, f & 15u);
+            j++;
+            node = nx;
+        }
+        occ += occs;
+        nv += nvs;
+        nkink += nks;
+        nwc += nws_;
+        if (j > capc) bad = true;
+        P.cnt[cnt_base + s] = j > capc ? capc : j;
+    }
+    if (bad) atomicOr(&P.flags[chain], FL_OVERFLOW);
+    __syncthreads();
+    // terms of the improved estimator: l tanh(lambda l) for an even number
+    // of worms in the interval, l / tanh(lambda l) for an odd number (empty
+    // slots hold l = 0 and add nothing); the expm1 table is read from L2
+    const double* F = C.F;
+    double qimp = 0.0;
+#pragma unroll 4
+    for (int i = lane; i < NE + nloc; i += 64) {
+        const uint32_t q = qint[i];
+        const long long ell = (long long)(q >> 1);
+        const double m = em1(F, ell);
+        const double num = m * (2.0 + m), den = 2.0 * (1.0 + m) + m * m;
+        const bool odd = (q & 1u) != 0u;
+        const double term = (double)ell * ((odd ? den : num) / (odd ? num : den));
+        qimp += ell > 0 ? term : 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        nv += __shfl_down(nv, o, 64);
+        nkink += __shfl_down(nkink, o, 64);
+        nwc += __shfl_down(nwc, o, 64);
+        occ += __shfl_down(occ, o, 64);
+        qimp += __shfl_down(qimp, o, 64);
+    }
+    if (lane == 0) {
+        DomPart dp;
+        dp.nv = nv; dp.nkink = nkink; dp.nw = nwc; dp.occ2 = occ; dp.qimp = qimp; dp.windows = windows;
+        P.dpart[C.dom_off + D] = dp;
+    }
+    return true;
+}
+
+// Dynamic LDS of the LDS form (HBM_ONLY = false): [exit thresholds 256 x u64]
+// [ring 512 words][expm1 table 1024 doubles][off nloc+1][cnt nloc][nodes:
+// tick 4B, nxt, prv, aux, wl 2B each, owner stamp 4B, fl 1B].  A domain whose
+// nodes do not fit takes the HBM node store.
+// The HBM form (HBM_ONLY = true) keeps only the thresholds and the ring in
+// LDS (6 KB, so that as many wavefronts share a CU as their registers allow):
+// the per-site counts and offsets go to the domain's scratch row in device
+// memory, the expm1 table is read from the chain record (L2), every domain's
+// nodes are in HBM.
+template <bool HBM_ONLY>
 __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict__ blk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1136,17 +1479,16 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
     const int nloc = C.nloc;
     uint64_t* sthr = reinterpret_cast<uint64_t*>(smem);
-    double* sE = reinterpret_cast<double*>(smem) + 256;
-    uint64_t* ring = reinterpret_cast<uint64_t*>(smem + 1280 * sizeof(double));
-    int* off = reinterpret_cast<int*>(smem + 1792 * sizeof(double));
+    uint64_t* ring = reinterpret_cast<uint64_t*>(smem + 256 * sizeof(uint64_t));
+    const double* sE = C.F;
+    int* off;
+    if constexpr (HBM_ONLY) off = P.s_oc + C.oc_off + (long long)D * (2 * nloc + 2);
+    else off = reinterpret_cast<int*>(smem + 768 * sizeof(uint64_t));
     int* cnt = off + (nloc + 1);
     // exit-leg thresholds ceil(P 2^53) of the cumulative scattering table
     // (exact: a power-of-two scaling, then an integral value below 2^55)
-    // (both copies unrolled, so that their loads are in flight together)
 #pragma unroll
     for (int q = 0; q < 4; q++) sthr[q * 64 + lane] = (uint64_t)ceil(C.scat[q * 64 + lane] * 0x1.0p53);
-#pragma unroll
-    for (int q = 0; q < 16; q++) sE[q * 64 + lane] = C.F[q * 64 + lane];
     for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
     __syncthreads();
     // exclusive scan of the per-site counts
@@ -1165,33 +1507,28 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     const int NN = NE + 2 * nloc;
     if (!live(P, C, bt.x)) return;
 
-    const size_t fixed = 1792 * sizeof(double) + (size_t)(2 * nloc + 1) * sizeof(int);
-    const size_t fixed_al = (fixed + 15) & ~(size_t)15;
-    const int cap_l = P.lds_nodes;
-    if (NN <= cap_l && NN < 65535) {
-        unsigned char* p = smem + fixed_al;
-        Nodes<uint16_t> A;
-        A.tick = reinterpret_cast<int32_t*>(p); p += (size_t)cap_l * 4;
-        A.nxt = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
-        A.prv = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
-        A.aux = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
-        A.wl = reinterpret_cast<uint16_t*>(p); p += (size_t)cap_l * 2;
-        uint32_t* own = reinterpret_cast<uint32_t*>(p); p += (size_t)cap_l * 4;
-        A.fl = reinterpret_cast<uint8_t*>(p);
-        scatter_domain(P, C, bt.x, D, A, own, ring, off, cnt, sthr, sE, NE);
-    } else {
-        if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
-        const long long b = C.scr_off + (long long)D * C.scr_nodes;
-        Nodes<uint32_t> A;
-        A.tick = P.s_tick + b;
-        A.nxt = P.s_nxt + b;
-        A.prv = P.s_prv + b;
-        A.aux = P.s_aux + b;
-        A.fl = P.s_fl + b;
-        A.wl = P.s_wl + b;
-        scatter_domain(P, C, bt.x, D, A, P.s_own + b, ring, off, cnt, sthr, sE, NE);
+    if constexpr (!HBM_ONLY) {
+        const size_t fixed = 768 * sizeof(uint64_t) + (size_t)(2 * nloc + 1) * sizeof(int);
+        const size_t fixed_al = (fixed + 15) & ~(size_t)15;
+        if ((size_t)P.lds_bytes > fixed_al &&
+            scatter_domain_lds(P, C, bt.x, D, smem + fixed_al, (size_t)P.lds_bytes - fixed_al, ring, off, cnt, sthr,
+                               NE))
+            return;
     }
+    if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
+    const long long b = C.scr_off + (long long)D * C.scr_nodes;
+    HbmStore A;
+    A.tick = P.s_tick + b;
+    A.nxt = P.s_nxt + b;
+    A.prv = P.s_prv + b;
+    A.aux = P.s_aux + b;
+    A.fl = P.s_fl + b;
+    A.wl = P.s_wl + b;
+    A.own = P.s_own + b;
+    scatter_domain(P, C, bt.x, D, A, ring, off, cnt, sthr, sE, NE);
 }
+template __global__ void k_scatter<false>(Pools, const int2* __restrict__);
+template __global__ void k_scatter<true>(Pools, const int2* __restrict__);
 
 // ===========================================================================
 // Boundary updates on the global arrays
@@ -2056,6 +2393,122 @@ __global__ void __launch_bounds__(64) k_green(Pools P, int chain, const int4* __
                 green_interval(B, C.T[kb + 1], F, sb, eb, gb);
             }
         }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (lane == 0) part[blk] = acc;
+}
+
+// ===========================================================================
+// n-point functions of b, b^+ and Q (Supplemental S-I).  The worms of an
+// interval (delimited by vertices and temporal domain boundaries) are summed
+// over: an operator inserted on it multiplies its propagator element
+// <q| E(l) |p> (E = exp(l eta Delta Q)) by the ratio
+// <q| E .. O_m .. O_1 E |p> / <q| E |p>, operators in time order; points on
+// different intervals give the product of their intervals' ratios.  A point
+// at tick t sits at t + 1/4 (between a vertex at t and the worm slot
+// t + 1/2).  One lane per (site, base time) of one correlator; block
+// c * nchunk + b covers pairs 64 b .. 64 b + 63 of correlator c and writes
+// the wave sum to part[block].
+// ===========================================================================
+constexpr int CORR_NPT = 8;
+
+// the interval of `site` holding time t + 1/4: lo <= t < hi, the occupation
+// p just above lo and q just below hi
+PMWA_DEV void corr_interval(const Pools& P, const ChainDev& C, int site, int32_t t, int32_t& lo, int32_t& hi,
+                            int& p, int& q)
+{
+    int kb = 0;
+    while (C.T[kb + 1] <= t) kb++;
+    int dsp, sl;
+    site_split(C, site, dsp, sl);
+    const long long su = unit_su(C, kb, dsp, sl);
+    const int n = P.cnt[C.cnt_off + su];
+    const uint2* E = P.ev + ev_base(C, kb, dsp, sl);
+    int state = P.bs[C.bs_off + su];
+    lo = C.T[kb];
+    p = state;
+    hi = C.T[kb + 1];
+    q = P.bs[C.bs_off + unit_su(C, kb + 1 == C.ntau ? 0 : kb + 1, dsp, sl)];
+    for (int j = 0; j < n; j++) {
+        const uint2 e = E[(long long)j * C.nloc];
+        const int up = (int)((e.y >> 3) & 1u);
+        if (!(e.y & 1u)) {
+            if ((int32_t)e.x <= t) { lo = (int32_t)e.x; p = up; }
+            else { hi = (int32_t)e.x; q = state; break; }
+        }
+        state = up;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_corr(Pools P, int chain, const int4* __restrict__ pts, int npt, int nbase,
+                                             int nchunk, double* __restrict__ part)
+{
+    const ChainDev& C = P.cd[chain];
+    const int lane = (int)threadIdx.x;
+    const int blk = (int)blockIdx.x;
+    const int c = blk / nchunk, b = blk - c * nchunk;
+    const long long u = (long long)b * 64 + lane;
+    double acc = 0.0;
+    if (u < (long long)C.N * nbase) {
+        const int i = (int)(u / nbase), j = (int)(u - (long long)i * nbase);
+        const int x = i % C.Lx, y = i / C.Lx;
+        const int32_t tau = (int32_t)(((long long)j * C.M) / nbase);
+        int site[CORR_NPT], op[CORR_NPT], pp[CORR_NPT], qq[CORR_NPT], grp[CORR_NPT];
+        int32_t t[CORR_NPT], lo[CORR_NPT], hi[CORR_NPT];
+        for (int k = 0; k < npt; k++) {
+            const int4 r = pts[c * npt + k];        // 0 <= rx < Lx, 0 <= ry < Ly, 0 <= dt < M
+            site[k] = ((y + r.y) % C.Ly) * C.Lx + (x + r.x) % C.Lx;
+            int32_t tk = tau + r.z;
+            if (tk >= C.M) tk -= C.M;
+            t[k] = tk;
+            op[k] = r.w;
+            corr_interval(P, C, site[k], tk, lo[k], hi[k], pp[k], qq[k]);
+            grp[k] = -1;
+        }
+        const double* F = C.F;
+        double prod = 1.0;
+        for (int k = 0; k < npt; k++) {
+            if (grp[k] >= 0) continue;
+            int mem[CORR_NPT], nm = 0;
+            for (int m = k; m < npt; m++)
+                if (site[m] == site[k] && lo[m] == lo[k] && hi[m] == hi[k]) {
+                    grp[m] = k;
+                    mem[nm++] = m;
+                }
+            // bottom to top: ascending time, at equal times the later-listed
+            // point first (the first listed is leftmost)
+            for (int a = 1; a < nm; a++) {
+                const int v = mem[a];
+                int bb = a - 1;
+                while (bb >= 0 && (t[mem[bb]] > t[v] || (t[mem[bb]] == t[v] && mem[bb] < v))) {
+                    mem[bb + 1] = mem[bb];
+                    bb--;
+                }
+                mem[bb + 1] = v;
+            }
+            double v0 = pp[k] ? 0.0 : 1.0, v1 = pp[k] ? 1.0 : 0.0;
+            int32_t cur = lo[k];
+            for (int a = 0; a <= nm; a++) {
+                const int32_t te = a < nm ? t[mem[a]] : hi[k];
+                const long long ell = (long long)(te - cur);
+                const double ch = fleg(F, 0, ell), sh = fleg(F, 1, ell);
+                const double n0 = ch * v0 + sh * v1;
+                const double n1 = sh * v0 + ch * v1;
+                v0 = n0;
+                v1 = n1;
+                if (a < nm) {
+                    const int o = op[mem[a]];
+                    const double w0 = v0, w1 = v1;
+                    if (o == 0) { v0 = w1; v1 = w0; }          // b + b^+
+                    else if (o == 1) { v0 = w1; v1 = 0.0; }    // b:   |1> -> |0>
+                    else { v0 = 0.0; v1 = w0; }                // b^+: |0> -> |1>
+                    cur = te;
+                }
+            }
+            const double den = fleg(F, pp[k] ^ qq[k], (long long)(hi[k] - lo[k]));
+            prod = prod * ((qq[k] ? v1 : v0) / den);
+        }
+        acc = prod;
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     if (lane == 0) part[blk] = acc;

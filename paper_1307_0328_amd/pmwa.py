@@ -21,7 +21,7 @@ EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_stat
            "pmwa_get_state", "pmwa_set_state", "pmwa_chain_info", "pmwa_default_event_cap",
            "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_set_timing_phases", "pmwa_phase_times", "pmwa_diag",
            "pmwa_green", "pmwa_chain_status", "pmwa_observables", "pmwa_reset_observables",
-           "pmwa_state_hash", "pmwa_slot_fits", "pmwa_green_static",
+           "pmwa_state_hash", "pmwa_slot_fits", "pmwa_green_static", "pmwa_correlator",
            "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
 
 
@@ -36,7 +36,7 @@ class pmwa_params(C.Structure):
 class pmwa_opts(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("scatter_mode", C.c_int32), ("series_cap", C.c_int32),
                 ("event_cap", C.c_int32), ("use_graph", C.c_int32), ("regen_mode", C.c_int32),
-                ("vertex_mode", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("vertex_mode", C.c_int32), ("scatter_lds", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class pmwa_obs(C.Structure):
@@ -100,6 +100,7 @@ def lib():
         L.pmwa_state_hash.argtypes = [C.c_void_p, C.c_int, P(C.c_uint64)]
         L.pmwa_slot_fits.argtypes = [C.c_void_p, C.c_int, P(pmwa_params)]
         L.pmwa_green_static.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
+        L.pmwa_correlator.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -277,6 +278,17 @@ def pmwa_green_static(h, chain, disps):
     return out
 
 
+def pmwa_correlator(h, chain, corrs, nbase=8):
+    """n-point functions on the current configuration: `corrs` is a list of
+    correlators, each a list of points (rx, ry, dt ticks, op), op 0 = b + b^+,
+    1 = b, 2 = b^+, all with the same number of points."""
+    arr = np.ascontiguousarray(np.array(corrs, dtype=np.int64), dtype=np.int32)
+    ncorr, npt = arr.shape[0], arr.shape[1]
+    out = np.zeros(ncorr)
+    _check(lib().pmwa_correlator(h, chain, npt, arr.ctypes.data, ncorr, nbase, out.ctypes.data), "pmwa_correlator")
+    return out
+
+
 def pmwa_diag(h, chain):
     out = np.zeros(4, np.int64)
     _check(lib().pmwa_diag(h, chain, out.ctypes.data, 4), "pmwa_diag")
@@ -293,7 +305,7 @@ class Sim:
     """A handle of one or more chains (convenience around the calls above)."""
 
     def __init__(self, chains, stream=None, scatter_mode=0, series_cap=4096, event_cap=0,
-                 use_graph=False, regen_mode=0, vertex_mode=0):
+                 use_graph=False, regen_mode=0, vertex_mode=0, scatter_lds=0):
         if isinstance(chains, pmwa_params):
             chains = [chains]
         self.chains = list(chains)
@@ -305,6 +317,7 @@ class Sim:
         o.use_graph = 1 if use_graph else 0
         o.regen_mode = regen_mode
         o.vertex_mode = vertex_mode
+        o.scatter_lds = scatter_lds
         self.h = pmwa_create(self.chains, o)
 
     def close(self):
@@ -364,6 +377,9 @@ class Sim:
 
     def observables(self, chain=0):
         return pmwa_observables(self.h, chain)
+
+    def correlator(self, corrs, nbase=8, chain=0):
+        return pmwa_correlator(self.h, chain, corrs, nbase)
 
     def reset_observables(self):
         pmwa_reset_observables(self.h)
