@@ -93,11 +93,11 @@ def traffic_from_profile(workload, kernel, hash_now):
 class Timed:
     """A handle of `cfgs`: thermalise, then timed sweeps."""
 
-    def __init__(self, P, cfgs, use_graph=False, scatter_mode=0, series_cap=4096):
+    def __init__(self, P, cfgs, use_graph=False, scatter_mode=0, series_cap=4096, scatter_lds=0):
         self.P = P
         self.cfgs = cfgs
         self.sim = P.Sim(params_of(P, cfgs), use_graph=use_graph, scatter_mode=scatter_mode,
-                         series_cap=series_cap)
+                         series_cap=series_cap, scatter_lds=scatter_lds)
 
     def close(self):
         self.sim.close()
@@ -266,9 +266,10 @@ def main():
         from paper_1307_0328_amd import autotune as T
         log("[bench] autotuning the launch form of the 256-chain batch")
         form, table = T.Tuner(sweeps=10, warmup=10, launch_forms=((0, False), (2, False))).tune_launch(batch)
-        mode = form[0]
-        log(f"[bench] 256 chains batched (scatter_mode {mode}): thermalise {args.therm}, warm-up {args.warmup}")
-        tb = Timed(P, batch, scatter_mode=mode)
+        mode, lds = form[0], form[2]
+        log(f"[bench] 256 chains batched (scatter_mode {mode}, LDS {lds}): thermalise {args.therm}, "
+            f"warm-up {args.warmup}")
+        tb = Timed(P, batch, scatter_mode=mode, scatter_lds=lds)
         try:
             tb.advance(args.therm)
             brk = tb.timed(20, timing=0x7F)            # per-kernel breakdown, not the headline
@@ -282,7 +283,7 @@ def main():
             log(f"[bench] graph replay of the same batch, {args.steps} sweeps")
         finally:
             tb.close()
-        tg = Timed(P, batch, scatter_mode=mode, use_graph=True)
+        tg = Timed(P, batch, scatter_mode=mode, use_graph=True, scatter_lds=lds)
         try:
             for c, st in enumerate(states):
                 tg.sim.set_state(st, c)
@@ -313,14 +314,16 @@ def main():
                                    "beta*t in {4,8,16}, mu on the 16-point grid in [-2,2] (host RNG seed 3), "
                                    "t=1, V=0, eta=0.05, 4x4 spatial domains, M=2^24 ticks",
                        "chains": len(batch), "thermalisation_sweeps": args.therm, "sweeps_timed": args.steps,
-                       "form": f"batched, one launch per phase for all chains (scatter_mode {mode})"},
+                       "form": f"batched, one launch per phase for all chains (scatter_mode {mode}, "
+                               f"scatter_lds {lds})"},
             "roofline": roofline(head, dom, "batched_256", hash_now),
             "plain": {"value": pl["nv"] / pl["seconds"], "ms_per_step": pl["seconds"] * 1e3 / args.steps,
                       "form": "one chain per handle, one launch sequence per phase per sweep, no graph, "
                               "same thermalised states, same sweeps",
                       "batched_over_plain": value / (pl["nv"] / pl["seconds"]), "same_work": same_work},
             "graph_form": {"value": gr["nv"] / gr["seconds"], "ms_per_step": gr["seconds"] * 1e3 / args.steps},
-            "autotune_table": [{"scatter_mode": f[0], "graph": bool(f[1]), "value": v} for f, v in table],
+            "autotune_table": [{"scatter_mode": f[0], "graph": bool(f[1]), "scatter_lds": f[2], "value": v}
+                               for f, v in table],
             "kernel_ms_per_sweep": kern,
             "algorithmic_GBps_per_sweep": 32.0 * nv_per / (ms_step * 1e-3) / 1e9,
             "worm_scatterings_per_s": head["attempts"] / head["seconds"],

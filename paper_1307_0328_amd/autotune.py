@@ -2,7 +2,9 @@
 
 It picks, per problem class, the domain grid and the launch form:
 - the spatial tile edge and the number of temporal slabs;
-- the node store of the scattering kernel (LDS or HBM);
+- the node store of the scattering kernel (LDS or HBM) and the LDS bytes a
+  domain of the LDS form may take (fewer bytes let more domains share a CU;
+  the larger domains then take the HBM store);
 - eager launches or graph replay.
 
 Each candidate is timed on the device (vertex updates per second over a
@@ -86,7 +88,7 @@ def tile_candidates(Lx: int, Ly: int, beta: float, t: float = 1.0, edges=(4, 8, 
 
 
 def measure_rate(chains: list[dict], cand: Candidate | None, sweeps: int = 20, warmup: int = 10,
-                 mode: int = 0, use_graph: bool = False) -> float:
+                 mode: int = 0, use_graph: bool = False, lds: int = 0) -> float:
     """Vertex updates per second of `chains` (parameter dicts) with the grid
     and launch form of `cand` (None: the chains' own grids and the launch
     form given by `mode` and `use_graph`), timed on the device."""
@@ -98,7 +100,7 @@ def measure_rate(chains: list[dict], cand: Candidate | None, sweeps: int = 20, w
         ps.append(P.make_params(**q))
     if cand is not None:
         mode, use_graph = cand.scatter_mode, cand.use_graph
-    with P.Sim(ps, scatter_mode=mode, use_graph=use_graph,
+    with P.Sim(ps, scatter_mode=mode, use_graph=use_graph, scatter_lds=lds,
                series_cap=max(64, sweeps + warmup + 8)) as sim:
         sim.sweep(warmup)
         if sim.status() != 0:
@@ -174,17 +176,23 @@ class Tuner:
         self.save()
         return Result(key, best, rate, table)
 
-    def tune_launch(self, chains: list[dict]):
-        """Launch form (scatter node store, graph replay) for a whole batch:
-        every form is timed on all chains together, grids as given."""
+    def tune_launch(self, chains: list[dict], lds_options=(0, 49152, 65536, 81920, 98304)):
+        """Launch form for a whole batch: every (node store, graph replay, LDS
+        bytes) form is timed on all chains together, grids as given.  Returns
+        the best (scatter_mode, use_graph, scatter_lds) and the table."""
         table = []
+        forms = []
         for mode, graph in self.launch_forms:
+            for lds in (lds_options if mode != 2 else (0,)):
+                forms.append((mode, graph, lds))
+        for mode, graph, lds in forms:
             rate = 0.0
             try:
-                rate = float(self.measure(chains, None, self.sweeps, self.warmup, mode=mode, use_graph=graph))
+                rate = float(self.measure(chains, None, self.sweeps, self.warmup, mode=mode, use_graph=graph,
+                                          lds=lds))
             except P.PmwaError:
                 pass
-            table.append(((mode, graph), rate))
+            table.append(((mode, graph, lds), rate))
         best, rate = max(table, key=lambda fr: fr[1])
         if rate <= 0.0:
             raise RuntimeError("autotune: no launch form ran for the batch")

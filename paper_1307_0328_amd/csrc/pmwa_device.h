@@ -40,6 +40,7 @@ static_assert(NWL <= RW_POOL, "the worm-offset pool must hold the worms of one i
 // SIMDs idle.
 constexpr int VL = 64;
 constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr uint32_t PX_NIL = 0xFFFFFFu;          // no partner end (24-bit link of an HBM node)
 constexpr uint32_t BV_TICK = (1u << 29) - 1u;   // bond-buffer entry: tick bits
 constexpr uint32_t BV_KINK = 1u << 29;          //   kink (occupations flip)
 
@@ -91,12 +92,9 @@ struct Pools {
     unsigned int* flags;         // per chain
     unsigned long long* nnacc;   // per chain
     pmwa_obs_acc* acc;           // per chain: sums and squares of the records
-    // scattering-phase node scratch in HBM
-    int32_t* s_tick;
-    uint32_t* s_nxt;
-    uint32_t* s_prv;
-    uint32_t* s_aux;
-    uint8_t* s_fl;
+    // scattering-phase node scratch in HBM: 16-byte nodes {tick, next,
+    // previous, partner << 8 | flags}, the worm list, the owner stamps
+    uint4* s_nd;
     uint32_t* s_wl;
     uint32_t* s_own;
     int32_t* s_oc;               // per domain 2 * nloc + 2 ints: site offsets, counts

@@ -507,8 +507,7 @@ void pmwa_destroy(pmwa_t* h)
     }
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
-                    h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_tick, h->P.s_nxt,
-                    h->P.s_prv, h->P.s_aux, h->P.s_fl, h->P.s_wl, h->P.s_own, h->P.s_oc, h->d_blk_v, h->d_blk_r,
+                    h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_nd, h->P.s_wl, h->P.s_own, h->P.s_oc, h->d_blk_v, h->d_blk_r,
                     h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw, h->d_gdisp, h->d_gpart,
                     h->P.acc, h->d_hash, h->d_cpts};
     for (void* p : ptrs)
@@ -628,6 +627,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         const double m = mean_events(hc.p, hc.rho_max);
         int64_t nodes = (int64_t)std::ceil(d.nloc * (m + 4.0 * std::sqrt(m) + 8.0)) + 2 * d.nloc + 64;
         nodes = std::min<int64_t>(nodes, (int64_t)d.nloc * (d.cap + 2));
+        nodes = std::min<int64_t>(nodes, (int64_t)PX_NIL - 1);   // partner links are 24-bit
         d.scr_nodes = (int32_t)nodes;
         d.scr_off = scr;
         scr += nodes * hc.n_dom;
@@ -651,11 +651,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     h->P.nnacc = dalloc<unsigned long long>(n_chains, &rc);
     h->P.acc = dalloc<pmwa_obs_acc>(n_chains, &rc);
     h->d_hash = dalloc<unsigned long long>(1, &rc);
-    h->P.s_tick = dalloc<int32_t>(scr, &rc);
-    h->P.s_nxt = dalloc<uint32_t>(scr, &rc);
-    h->P.s_prv = dalloc<uint32_t>(scr, &rc);
-    h->P.s_aux = dalloc<uint32_t>(scr, &rc);
-    h->P.s_fl = dalloc<uint8_t>(scr, &rc);
+    h->P.s_nd = dalloc<uint4>(scr, &rc);
     h->P.s_wl = dalloc<uint32_t>(scr, &rc);
     h->P.s_own = dalloc<uint32_t>(scr, &rc);
     h->P.s_oc = dalloc<int32_t>(oc, &rc);

@@ -601,30 +601,46 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
 // sentinels) held in LDS with 16-bit links when they fit, else in an HBM
 // scratch region with 32-bit links.
 // ===========================================================================
-// A node as the window evaluation reads it: tick and flags
+// A node as the window evaluation reads it: tick and flags; and with its
+// links (next, previous, partner end)
 struct NodeRec {
     int32_t t;
     uint32_t f;
 };
+struct NodeAll {
+    int32_t t;
+    uint32_t f, nx, pv, px;
+};
 
-// Node store in device memory (the HBM form): 32-bit links, separate tick
-// and flag arrays, one owner stamp per node.
+// Node store in device memory (the HBM form): 16-byte nodes {tick, next,
+// previous, partner << 8 | flags}, so that every dependent level of the
+// window evaluation reads one 128-bit word per node; one owner stamp per
+// node (a separate array: also the setup's and the measurement's scratch).
 struct HbmStore {
-    int32_t* tick;
-    uint32_t* nxt;
-    uint32_t* prv;
-    uint32_t* aux;   // partner end of a vertex
-    uint8_t* fl;
+    uint4* nd;
     uint32_t* wl;    // worm list
-    uint32_t* own;   // owner stamps (setup and measurement scratch as well)
+    uint32_t* own;
     static constexpr bool in_lds = false;
-    PMWA_DEV NodeRec rec(uint32_t i) const { NodeRec r; r.t = tick[i]; r.f = fl[i]; return r; }
-    // the flags (the tick is not needed by the caller)
-    PMWA_DEV NodeRec rec_f(uint32_t i) const { NodeRec r; r.t = 0; r.f = fl[i]; return r; }
-    PMWA_DEV int32_t tk(uint32_t i) const { return tick[i]; }
-    PMWA_DEV void put(uint32_t i, int32_t t, uint32_t f) { tick[i] = t; fl[i] = (uint8_t)f; }
-    // new flags of a node whose tick t is unchanged
-    PMWA_DEV void put_fl(uint32_t i, int32_t, uint32_t f) { fl[i] = (uint8_t)f; }
+    PMWA_DEV NodeAll all(uint32_t i) const
+    {
+        const uint4 v = nd[i];
+        NodeAll r;
+        r.t = (int32_t)v.x;
+        r.nx = v.y;
+        r.pv = v.z;
+        r.px = v.w >> 8;
+        r.f = v.w & 255u;
+        return r;
+    }
+    PMWA_DEV void put(uint32_t i, int32_t t, uint32_t f, uint32_t px)
+    {
+        nd[i].x = (uint32_t)t;
+        nd[i].w = (px << 8) | f;
+    }
+    // new flags of a node whose tick is unchanged
+    PMWA_DEV void put_fl(uint32_t i, int32_t, uint32_t f, uint32_t px) { nd[i].w = (px << 8) | f; }
+    PMWA_DEV void set_nx(uint32_t i, uint32_t v) { nd[i].y = v; }
+    PMWA_DEV void set_pv(uint32_t i, uint32_t v) { nd[i].z = v; }
     PMWA_DEV uint32_t* stamp(uint32_t i) { return own + i; }
     PMWA_DEV static int stamps(int nn) { return nn; }
 };
@@ -652,10 +668,22 @@ struct LdsStore {
         r.f = x & 31u;
         return r;
     }
-    PMWA_DEV NodeRec rec_f(uint32_t i) const { return rec(i); }
-    PMWA_DEV int32_t tk(uint32_t i) const { return base + (int32_t)(w[i] >> 5); }
-    PMWA_DEV void put(uint32_t i, int32_t t, uint32_t f) { w[i] = ((uint32_t)(t - base) << 5) | f; }
-    PMWA_DEV void put_fl(uint32_t i, int32_t t, uint32_t f) { put(i, t, f); }
+    // (the fields a caller does not use are never loaded)
+    PMWA_DEV NodeAll all(uint32_t i) const
+    {
+        const NodeRec r = rec(i);
+        NodeAll a;
+        a.t = r.t;
+        a.f = r.f;
+        a.nx = nxt[i];
+        a.pv = prv[i];
+        a.px = aux[i];
+        return a;
+    }
+    PMWA_DEV void put(uint32_t i, int32_t t, uint32_t f, uint32_t) { w[i] = ((uint32_t)(t - base) << 5) | f; }
+    PMWA_DEV void put_fl(uint32_t i, int32_t t, uint32_t f, uint32_t px) { put(i, t, f, px); }
+    PMWA_DEV void set_nx(uint32_t i, uint32_t v) { nxt[i] = (uint16_t)v; }
+    PMWA_DEV void set_pv(uint32_t i, uint32_t v) { prv[i] = (uint16_t)v; }
     PMWA_DEV uint32_t* stamp(uint32_t i) { return own + (i >> 1); }
     PMWA_DEV static int stamps(int nn) { return (nn + 1) >> 1; }
 };
@@ -761,38 +789,39 @@ PMWA_DEV long long scatter_windows(Store& A, uint64_t* __restrict__ ring, int NN
         uint32_t pk0 = k0, pk1 = k1;
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(w));
-        const NodeRec rw = A.rec_f(w);
-        const uint32_t fw = rw.f ^ ((rep & 1) ? F_DIRUP : 0u);
-        const uint32_t pw = A.prv[w];
-        const uint32_t nn_ = A.nxt[w];
+        const NodeAll aw = A.all(w);
+        const uint32_t fw = aw.f ^ ((rep & 1) ? F_DIRUP : 0u);
+        const uint32_t pw = aw.pv;
+        const uint32_t nn_ = aw.nx;
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fw), "v"(pw), "v"(nn_));
         const bool up = (fw & F_DIRUP) != 0;
         const uint32_t x = up ? nn_ : pw;
         const uint32_t wf = up ? pw : nn_;
-        const NodeRec rx = A.rec(x);
-        const uint32_t fx = rx.f;
-        const int32_t t = rx.t;
-        const uint32_t ya = A.aux[x];
-        const uint32_t xfa = up ? A.nxt[x] : A.prv[x];
-        const NodeRec rwf = A.rec(wf);
-        const int32_t t_wf = rwf.t;
-        const uint32_t f_wf = rwf.f;
+        const NodeAll ax = A.all(x);
+        const uint32_t fx = ax.f;
+        const int32_t t = ax.t;
+        const uint32_t ya = ax.px;
+        const uint32_t xfa = up ? ax.nx : ax.pv;
+        const NodeAll awf = A.all(wf);
+        const int32_t t_wf = awf.t;
+        const uint32_t f_wf = awf.f;
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fx), "v"(ya), "v"(xfa));
         const bool blocked = (fx & (F_WORM | F_SBOT | F_STOP | F_CROSS)) != 0;
         const uint32_t y = blocked ? w : ya;
         const uint32_t xf = blocked ? w : xfa;
-        const uint32_t fy = A.rec_f(y).f;
-        const uint32_t yp = A.prv[y];
-        const uint32_t yn = A.nxt[y];
-        const NodeRec rxf = A.rec(xf);
-        const int32_t t_xf = rxf.t;
-        const uint32_t f_xf = rxf.f;
-        const NodeRec ryp = A.rec(yp);
-        const int32_t t_yp = ryp.t;
-        const uint32_t f_yp = ryp.f;
-        const int32_t t_yn = A.tk(yn);
+        const NodeAll ay = A.all(y);
+        const uint32_t fy = ay.f;
+        const uint32_t yp = ay.pv;
+        const uint32_t yn = ay.nx;
+        const NodeAll axf = A.all(xf);
+        const int32_t t_xf = axf.t;
+        const uint32_t f_xf = axf.f;
+        const NodeAll ayp = A.all(yp);
+        const int32_t t_yp = ayp.t;
+        const uint32_t f_yp = ayp.f;
+        const int32_t t_yn = A.all(yn).t;
         philox_rounds<2>(po, pk0, pk1);
         asm("" : "+v"(po[0]), "+v"(po[1]), "+v"(po[2]), "+v"(po[3]) : "v"(fy), "v"(yp), "v"(yn));
         philox_rounds<2>(po, pk0, pk1);
@@ -869,18 +898,19 @@ PMWA_DEV long long scatter_windows(Store& A, uint64_t* __restrict__ ring, int NN
         // ---- apply the surviving attempts (disjoint nodes)
         if (lane < kc) {
             if (!moved) {
-                if (lane + nw >= kc) A.put_fl(w, rw.t, fw ^ F_DIRUP);   // the worm's last attempt here
+                if (lane + nw >= kc) A.put_fl(w, aw.t, fw ^ F_DIRUP, aw.px);   // the worm's last attempt here
             } else {
-                // (x and y are the two ends of one vertex: both at tick t)
-                if (!up) A.put_fl(x, t, fx_now);
-                A.nxt[pw] = nn_;
-                A.prv[nn_] = pw;
-                if (above) A.put_fl(Pn, t, fv ^ F_UP);
-                A.put(w, ntick, F_WORM | (above ? F_DIRUP : 0u) | newup);
-                A.prv[w] = Pn;
-                A.nxt[w] = Nn;
-                A.nxt[Pn] = w;
-                A.prv[Nn] = w;
+                // (x and y are the two ends of one vertex: both at tick t,
+                // each the other's partner)
+                if (!up) A.put_fl(x, t, fx_now, ya);
+                A.set_nx(pw, nn_);
+                A.set_pv(nn_, pw);
+                if (above) A.put_fl(Pn, t, fv ^ F_UP, on_x ? ya : ay.px);
+                A.put(w, ntick, F_WORM | (above ? F_DIRUP : 0u) | newup, aw.px);
+                A.set_pv(w, Pn);
+                A.set_nx(w, Nn);
+                A.set_nx(Pn, w);
+                A.set_pv(Nn, w);
             }
         }
         // the speculative words go in when the ring has room: this window
@@ -964,11 +994,9 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                     const uint32_t f = e[u].y & 15u;
                     const uint32_t vd = (f >> 1) & 3u;
                     const bool v = (f & F_WORM) == 0u;
-                    A.tick[idx] = (int32_t)e[u].x;
-                    A.fl[idx] = (uint8_t)(f | ((v && ((crm >> vd) & 1u)) ? F_CROSS : 0u));
-                    A.prv[idx] = (j > 0 ? idx - 1u : BOT + (uint32_t)s);
-                    A.nxt[idx] = (j + 1 < n ? idx + 1u : TOP + (uint32_t)s);
-                    A.aux[idx] = NIL;
+                    const uint32_t fl = f | ((v && ((crm >> vd) & 1u)) ? F_CROSS : 0u);
+                    A.nd[idx] = make_uint4(e[u].x, j + 1 < n ? idx + 1u : TOP + (uint32_t)s,
+                                           j > 0 ? idx - 1u : BOT + (uint32_t)s, (PX_NIL << 8) | fl);
                     c0 += v && vd == 0u;
                     c1 += v && vd == 1u;
                     c2 += v && vd == 2u;
@@ -981,16 +1009,9 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         vtab[4 * s + 2] = (uint16_t)(c0 + c1 + c2);
         vtab[4 * s + 3] = (uint16_t)(c0 + c1 + c2 + c3);
         const int bsv = P.bs[C.bs_off + unit_su(C, k, dsp, s)];
-        A.tick[BOT + s] = Tk;
-        A.fl[BOT + s] = (uint8_t)(F_SBOT | (bsv ? F_UP : 0u));
-        A.nxt[BOT + s] = (n ? (uint32_t)o : TOP + s);
-        A.prv[BOT + s] = NIL;
-        A.aux[BOT + s] = NIL;
-        A.tick[TOP + s] = Tk1;
-        A.fl[TOP + s] = (uint8_t)F_STOP;
-        A.prv[TOP + s] = (n ? (uint32_t)(o + n - 1) : BOT + s);
-        A.nxt[TOP + s] = NIL;
-        A.aux[TOP + s] = NIL;
+        A.nd[BOT + s] = make_uint4((uint32_t)Tk, n ? (uint32_t)o : TOP + s, NIL,
+                                   (PX_NIL << 8) | F_SBOT | (bsv ? F_UP : 0u));
+        A.nd[TOP + s] = make_uint4((uint32_t)Tk1, NIL, n ? (uint32_t)(o + n - 1) : BOT + s, (PX_NIL << 8) | F_STOP);
     }
     __syncthreads();
     // 2. vertex nodes by (site, direction, rank), and the worm list in
@@ -1009,7 +1030,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             for (int j0 = 0; j0 < n; j0 += 8) {
                 uint32_t fb[8];
 #pragma unroll
-                for (int u = 0; u < 8; u++) fb[u] = j0 + u < n ? (uint32_t)A.fl[o + j0 + u] : 0u;
+                for (int u = 0; u < 8; u++) fb[u] = j0 + u < n ? A.nd[o + j0 + u].w & 255u : 0u;
 #pragma unroll
                 for (int u = 0; u < 8; u++) {
                     if (j0 + u < n) {
@@ -1062,8 +1083,9 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
             for (int r = 0; r < m_n; r++) {
                 const uint32_t idx = (uint32_t)own_v[r];
                 const uint32_t m = (uint32_t)nb_v[r];
-                bad3 |= A.tick[idx] != A.tick[m];
-                A.aux[idx] = m;
+                const uint4 vi = A.nd[idx];
+                bad3 |= vi.x != A.nd[m].x;
+                A.nd[idx].w = (m << 8) | (vi.w & 255u);
             }
         }
     }
@@ -1099,12 +1121,12 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
         uint32_t* qi = qint + off[s] + s;
         const int qmax = cnt[s] + 1;
         int nq = 0;
-        int stt = (A.fl[BOT + s] >> 3) & 1;
+        int stt = (int)((A.nd[BOT + s].w >> 3) & 1u);
         int32_t lastp = 2 * Tk;                 // positions in half ticks (< 2^31)
         int32_t ilo = Tk;
         uint32_t par = 0;
         int j = 0;
-        uint32_t node = A.nxt[BOT + s];
+        uint32_t node = A.nd[BOT + s].y;
         int guard = 0;
         // this site's tallies (the occupation integral is below 2^31)
         int occs = 0, nvs = 0, nks = 0, nws = 0;
@@ -1116,9 +1138,10 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
                 break;
             }
             if (node >= (uint32_t)NE || ++guard > NE) { bad = true; break; }
-            const uint32_t f = A.fl[node];
-            const int32_t tk = A.tick[node];
-            const uint32_t nx = A.nxt[node];
+            const uint4 vn = A.nd[node];
+            const uint32_t f = vn.w & 255u;
+            const int32_t tk = (int32_t)vn.x;
+            const uint32_t nx = vn.y;
             const uint32_t isw = f & F_WORM, isv = isw ^ 1u;
             const int32_t pos = 2 * tk + (int32_t)isw;
             occs += stt * (pos - lastp);
@@ -1518,11 +1541,7 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     if (NN > C.scr_nodes) { if (lane == 0) atomicOr(&P.flags[bt.x], FL_OVERFLOW); return; }
     const long long b = C.scr_off + (long long)D * C.scr_nodes;
     HbmStore A;
-    A.tick = P.s_tick + b;
-    A.nxt = P.s_nxt + b;
-    A.prv = P.s_prv + b;
-    A.aux = P.s_aux + b;
-    A.fl = P.s_fl + b;
+    A.nd = P.s_nd + b;
     A.wl = P.s_wl + b;
     A.own = P.s_own + b;
     scatter_domain(P, C, bt.x, D, A, ring, off, cnt, sthr, sE, NE);

@@ -48,6 +48,7 @@ def test_launch_form_of_a_batch():
     chains = W.batched_256(16)
     say("[autotune] batch launch form, 16 chains")
     tu = T.Tuner(sweeps=4, warmup=2)
-    best, table = tu.tune_launch(chains)
-    assert len(table) == 3 and all(rate > 0.0 for _, rate in table)
+    best, table = tu.tune_launch(chains, lds_options=(0, 49152))
+    # (LDS form, eager) and (LDS form, graph) at two LDS sizes, and the HBM form
+    assert len(table) == 5 and all(rate > 0.0 for _, rate in table)
     assert best in [f for f, _ in table]
