@@ -135,6 +135,7 @@ struct pmwa_handle {
     int64_t ev_total = 0, site_slabs = 0;
     bool slots = false;
     int max_nloc = 1;
+    int max_capb = 1;        // the largest bond-buffer capacity (spatial-update LDS)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool own_stream = false;
@@ -712,11 +713,16 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         }
     }
     {
-        int maxcap = 0;
-        for (auto& hc : h->ch) maxcap = std::max(maxcap, hc.d.cap);
-        // A, B, A2, B2; 10 int arrays; the per-vertex records; the worm-offset pool
-        h->bs_lds = (size_t)maxcap * (4 * sizeof(uint2) + 10 * sizeof(int) + sizeof(BsVert)) +
-                    (size_t)RW_POOL * sizeof(int32_t);
+        int maxcap = 0, maxcapb = 0;
+        for (auto& hc : h->ch) {
+            maxcap = std::max(maxcap, hc.d.cap);
+            maxcapb = std::max(maxcapb, hc.d.capb);
+        }
+        // A, B, A2, B2 and eight 16-bit arrays per event; per bond vertex its
+        // record and two indices; the worm-offset pool
+        h->max_capb = maxcapb;
+        h->bs_lds = (size_t)maxcap * (4 * sizeof(uint2) + 8 * sizeof(int16_t)) +
+                    (size_t)maxcapb * (sizeof(BsVert) + 2 * sizeof(int)) + (size_t)RW_POOL * sizeof(int32_t) + 16;
         // the spatial update holds a cross bond's two site lists in LDS: a
         // chain with spatial domains needs its event capacity to fit
         bool any_spatial = false;
@@ -789,7 +795,8 @@ static int slot_fit(pmwa_t* h, int slot, const pmwa_params* p, HostChain& job)
         (int64_t)job.cdf.size() > hc.cap_cdf || job.n_units_v > hc.cap_units_v ||
         job.n_units_r > hc.cap_units_r || job.n_bt > hc.cap_bt || job.n_bsx > hc.cap_bsx ||
         job.n_bsy > hc.cap_bsy || d.nloc > h->max_nloc || d.cdf_stride > h->vs ||
-        (h->regen_wave && 4 * d.capb > h->rw_nmax) || job.n_dom * (2LL * d.nloc + 2) > hc.cap_oc)
+        (h->regen_wave && 4 * d.capb > h->rw_nmax) || job.n_dom * (2LL * d.nloc + 2) > hc.cap_oc ||
+        d.capb > h->max_capb)
         return PMWA_EINVAL;
     return PMWA_OK;
 }

@@ -1734,7 +1734,7 @@ template __global__ void k_btemporal<16>(Pools, const int2* __restrict__);
 
 // index of the previous / next vertex (worms skipped) for every position of
 // a site array, by wave ballots (chunks of 64 with a carry)
-PMWA_DEV void vertex_links(const uint2* A, int n, int* pv, int* nv)
+PMWA_DEV void vertex_links(const uint2* A, int n, int16_t* pv, int16_t* nv)
 {
     const int lane = (int)threadIdx.x;
     int carry = -1;
@@ -1743,7 +1743,7 @@ PMWA_DEV void vertex_links(const uint2* A, int n, int* pv, int* nv)
         const bool v = j < n && !ev_worm(A[j].y);
         const unsigned long long m = __ballot(v);
         const unsigned long long below_m = m & ((1ULL << lane) - 1ULL);
-        if (j < n) pv[j] = below_m ? base + 63 - __clzll((long long)below_m) : carry;
+        if (j < n) pv[j] = (int16_t)(below_m ? base + 63 - __clzll((long long)below_m) : carry);
         if (m) carry = base + 63 - __clzll((long long)m);
     }
     carry = n;
@@ -1752,7 +1752,7 @@ PMWA_DEV void vertex_links(const uint2* A, int n, int* pv, int* nv)
         const bool v = j < n && !ev_worm(A[j].y);
         const unsigned long long m = __ballot(v);
         const unsigned long long above_m = lane == 63 ? 0ULL : (m & ~((2ULL << lane) - 1ULL));
-        if (j < n) nv[j] = above_m ? top + __ffsll((long long)above_m) - 1 : carry;
+        if (j < n) nv[j] = (int16_t)(above_m ? top + __ffsll((long long)above_m) - 1 : carry);
         if (m) carry = top + __ffsll((long long)m) - 1;
     }
     __builtin_amdgcn_wave_barrier();
@@ -1760,7 +1760,7 @@ PMWA_DEV void vertex_links(const uint2* A, int n, int* pv, int* nv)
 
 // positions of the vertices of direction `dir` in order: V[ord] = j and
 // ord_of[j] = ord; returns their number
-PMWA_DEV int bond_vertices(const uint2* A, int n, uint32_t dir, int* V, int* ord_of)
+PMWA_DEV int bond_vertices(const uint2* A, int n, uint32_t dir, int* V, int16_t* ord_of, int vcap)
 {
     const int lane = (int)threadIdx.x;
     int cnt = 0;
@@ -1774,8 +1774,8 @@ PMWA_DEV int bond_vertices(const uint2* A, int n, uint32_t dir, int* V, int* ord
         const unsigned long long m = __ballot(bv);
         if (bv) {
             const int o = cnt + __popcll(m & ((1ULL << lane) - 1ULL));
-            V[o] = j;
-            ord_of[j] = o;
+            if (o < vcap) V[o] = j;
+            ord_of[j] = (int16_t)o;
         }
         cnt += __popcll(m);
     }
@@ -1799,8 +1799,8 @@ PMWA_DEV int wave_incl_sum(int x)
 // worms of the intervals no bond vertex touches, plus the new worms; the new
 // worms of interval (j, next vertex) start at pos[j] + 1 (or 0 for the
 // interval below the first vertex).  Returns the new length.
-PMWA_DEV int rebuild_positions(const uint2* A, int n, const int* pv, const int* nv, const int* ord_of,
-                               const BsVert* VV, uint32_t dir, int lower_leg, int upper_leg, int* pos)
+PMWA_DEV int rebuild_positions(const uint2* A, int n, const int16_t* pv, const int16_t* nv, const int16_t* ord_of,
+                               const BsVert* VV, uint32_t dir, int lower_leg, int upper_leg, int16_t* pos)
 {
     const int lane = (int)threadIdx.x;
     auto is_bv = [&](int j) { return j >= 0 && j < n && !ev_worm(A[j].y) && ev_dir(A[j].y) == dir; };
@@ -1827,7 +1827,7 @@ PMWA_DEV int rebuild_positions(const uint2* A, int n, const int* pv, const int* 
             }
         }
         const int incl = wave_incl_sum(x);
-        if (j < n) pos[j] = carry + incl - x;
+        if (j < n) pos[j] = (int16_t)(carry + incl - x);
         carry += __shfl(incl, 63, 64);
     }
     __builtin_amdgcn_wave_barrier();
@@ -1836,8 +1836,8 @@ PMWA_DEV int rebuild_positions(const uint2* A, int n, const int* pv, const int* 
 
 // copies the kept objects of A to their positions in A2 (bond vertices get
 // their new occupation above)
-PMWA_DEV void rebuild_copy(const uint2* A, int n, const int* pv, const int* nv, const int* ord_of,
-                           const BsVert* VV, uint32_t dir, int side, const int* pos, uint2* A2)
+PMWA_DEV void rebuild_copy(const uint2* A, int n, const int16_t* pv, const int16_t* nv, const int16_t* ord_of,
+                           const BsVert* VV, uint32_t dir, int side, const int16_t* pos, uint2* A2)
 {
     const int lane = (int)threadIdx.x;
     auto is_bv = [&](int j) { return j >= 0 && j < n && !ev_worm(A[j].y) && ev_dir(A[j].y) == dir; };
@@ -1882,24 +1882,28 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     int dspa, sla, dspc, slc;
     site_split(C, a, dspa, sla);
     site_split(C, c, dspc, slc);
-    const int cap = C.cap;
+    const int cap = C.cap, capb = C.capb;
     const double* sE = C.F;
+    // dynamic LDS: the two site lists and their rebuilt forms (cap events
+    // each), 16-bit links, ranks and new positions per event, then per
+    // vertex of the bond (at most the bond buffer's capacity) its indices
+    // and record, then the worm-offset pool
     uint2* A = reinterpret_cast<uint2*>(smem);
     uint2* B = A + cap;
     uint2* A2 = B + cap;
     uint2* B2 = A2 + cap;
-    int* pvA = reinterpret_cast<int*>(B2 + cap);
-    int* nvA = pvA + cap;
-    int* ordA = nvA + cap;
-    int* posA = ordA + cap;
-    int* pvB = posA + cap;
-    int* nvB = pvB + cap;
-    int* ordB = nvB + cap;
-    int* posB = ordB + cap;
-    int* VA = posB + cap;
-    int* VB = VA + cap;
-    BsVert* VV = reinterpret_cast<BsVert*>(VB + cap);
-    int32_t* pool = reinterpret_cast<int32_t*>(VV + cap);
+    BsVert* VV = reinterpret_cast<BsVert*>(B2 + cap);
+    int* VA = reinterpret_cast<int*>(VV + capb);
+    int* VB = VA + capb;
+    int32_t* pool = VB + capb;
+    int16_t* pvA = reinterpret_cast<int16_t*>(pool + RW_POOL);
+    int16_t* nvA = pvA + cap;
+    int16_t* ordA = nvA + cap;
+    int16_t* posA = ordA + cap;
+    int16_t* pvB = posA + cap;
+    int16_t* nvB = pvB + cap;
+    int16_t* ordB = nvB + cap;
+    int16_t* posB = ordB + cap;
 
     const long long cua = C.cnt_off + unit_su(C, k, dspa, sla);
     const long long cuc = C.cnt_off + unit_su(C, k, dspc, slc);
@@ -1911,9 +1915,10 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
         for (int j = lane; j < nb; j += 64) B[j] = GB[(long long)j * C.nloc];
     }
     __syncthreads();
-    const int nva = bond_vertices(A, na, (uint32_t)d, VA, ordA);
-    const int nvb = bond_vertices(B, nb, (uint32_t)(d + 2), VB, ordB);
+    const int nva = bond_vertices(A, na, (uint32_t)d, VA, ordA, capb);
+    const int nvb = bond_vertices(B, nb, (uint32_t)(d + 2), VB, ordB, capb);
     if (nva != nvb) { if (lane == 0) atomicOr(flag, FL_STATE); return; }
+    if (nva > capb) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
     const int nbv = nva;
     if (nbv == 0) return;
     vertex_links(A, na, pvA, nvA);
