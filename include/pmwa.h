@@ -101,7 +101,13 @@ typedef struct pmwa_opts {
                                  tuning knob: fewer bytes let more domains share a
                                  CU, larger domains then take the HBM store); 0 =
                                  sized for the largest expected domain       */
-    int32_t reserved[1];
+    int32_t groups;           /* 0 or 1: every phase of every chain in one launch;
+                                 G > 1: the chains split into G groups of about
+                                 equal expected work, each on a stream of its
+                                 own (default priority); a sweep forks to them
+                                 and joins, so no group's phase waits for
+                                 another group's (one graph with G branches when
+                                 use_graph).  Results do not depend on it.    */
 } pmwa_opts;
 
 /* Raw per-sweep record of one chain (all sums over the whole lattice). */

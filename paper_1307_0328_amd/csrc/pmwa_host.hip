@@ -32,7 +32,7 @@ __global__ void k_btemporal(Pools P, const int2* __restrict__ blk);
 __global__ void k_green(Pools P, int chain, const int4* __restrict__ disp, int nd, int nchunk,
                         double* __restrict__ part);
 __global__ void k_bspatial(Pools P, const int2* __restrict__ blk, int d);
-__global__ void k_finish(Pools P);
+__global__ void k_finish(Pools P, const int* __restrict__ chains);
 __global__ void k_reset_acc(Pools P, int n);
 __global__ void k_hash(Pools P, int chain, unsigned long long* out);
 __global__ void k_green_sum(const double* part, int ntau, int nd, int nchunk, double norm, double* out);
@@ -112,6 +112,18 @@ T* dalloc(size_t n, int* rc)
 
 }  // namespace
 
+// The block tables of one group of chains and the stream it runs on.
+struct LaunchGroup {
+    std::vector<int> chains;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t done = nullptr;
+    int2 *v = nullptr, *r = nullptr, *s = nullptr, *bt = nullptr, *bsx = nullptr, *bsy = nullptr, *rw = nullptr;
+    int nv = 0, nr = 0, ns = 0, nbt = 0, nbsx = 0, nbsy = 0, nrw = 0;
+    int* fin = nullptr;        // chain indices of k_finish
+    int nfin = 0;
+};
+
 struct pmwa_handle {
     hipStream_t stream = nullptr;
     pmwa_opts opts{};
@@ -119,9 +131,12 @@ struct pmwa_handle {
     Pools P{};
     ChainDev* d_cd = nullptr;
     double* d_cdf = nullptr;
-    int2 *d_blk_v = nullptr, *d_blk_r = nullptr, *d_blk_s = nullptr, *d_blk_bt = nullptr,
-         *d_blk_bsx = nullptr, *d_blk_bsy = nullptr, *d_blk_rw = nullptr;
-    int nblk_v = 0, nblk_r = 0, nblk_s = 0, nblk_bt = 0, nblk_bsx = 0, nblk_bsy = 0, nblk_rw = 0;
+    // launch groups: each holds the block tables of its chains and a stream
+    // (the first group uses the handle's stream); with more than one group a
+    // sweep forks to the group streams and joins back, so a group's phases
+    // never wait for another group's
+    std::vector<LaunchGroup> grp;
+    hipEvent_t fork_ev = nullptr;
     bool regen_wave = false;   // worm re-generation with one wavefront per (site, slab)
     int rw_nmax = 4;           // bond-buffer entries of a site in a slab, at most
     size_t rw_lds = 0;
@@ -340,14 +355,23 @@ static int build_chain(const pmwa_params& p, uint32_t cap_override, HostChain& h
     return PMWA_OK;
 }
 
-static void block_table(const std::vector<HostChain>& ch, int per_block, int64_t HostChain::*units,
-                        std::vector<int2>& out)
+static void block_table(const std::vector<HostChain>& ch, const std::vector<int>& chains, int per_block,
+                        int64_t HostChain::*units, std::vector<int2>& out)
 {
     out.clear();
-    for (size_t c = 0; c < ch.size(); c++) {
+    for (int c : chains) {
         const int64_t n = ch[c].*units;
-        for (int64_t b = 0; b < n; b += per_block) out.push_back(make_int2((int)c, (int)b));
+        for (int64_t b = 0; b < n; b += per_block) out.push_back(make_int2(c, (int)b));
     }
+}
+
+// expected work of one scattering domain of a chain: its expected nodes
+// (4 (rho_max + t) beta per site and slab, the vertex ends) and attempts
+// (N_cycle times the worms, ~ 4 C beta per site and slab)
+static double domain_work(const HostChain& hc)
+{
+    const double db = hc.p.beta / hc.p.dom_tau;
+    return (double)hc.d.nloc * db * (4.0 * (hc.rho_max + hc.p.t) + 4.0 * hc.C);
 }
 
 #define HIPCHK(x)                                  \
@@ -378,11 +402,11 @@ static int upload_table(const std::vector<int2>& t, int2** dst, int* n)
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-static int launch_kernel(pmwa_t* h, int phase);
+static int launch_kernel(pmwa_t* h, int phase, const LaunchGroup& g);
 
-static int launch_phase(pmwa_t* h, int phase)
+static int launch_phase(pmwa_t* h, int phase, const LaunchGroup& g)
 {
-    if (!h->timing || !((h->timing_mask >> (phase - 1)) & 1u)) return launch_kernel(h, phase);
+    if (!h->timing || !((h->timing_mask >> (phase - 1)) & 1u)) return launch_kernel(h, phase, g);
     if (h->ev_used + 2 > h->ev_pool.size()) {
         for (int i = 0; i < 2; i++) {
             hipEvent_t e;
@@ -391,59 +415,85 @@ static int launch_phase(pmwa_t* h, int phase)
         }
     }
     hipEvent_t e0 = h->ev_pool[h->ev_used], e1 = h->ev_pool[h->ev_used + 1];
-    HIPCHK(hipEventRecord(e0, h->stream));
-    int rc = launch_kernel(h, phase);
-    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventRecord(e0, g.stream));
+    int rc = launch_kernel(h, phase, g);
+    HIPCHK(hipEventRecord(e1, g.stream));
     if (h->ev_phase.size() < h->ev_used / 2 + 1) h->ev_phase.resize(h->ev_used / 2 + 1);
     h->ev_phase[h->ev_used / 2] = phase;
     h->ev_used += 2;
     return rc;
 }
 
-static int launch_kernel(pmwa_t* h, int phase)
+static int launch_kernel(pmwa_t* h, int phase, const LaunchGroup& g)
 {
-    hipStream_t s = h->stream;
+    hipStream_t s = g.stream;
     switch (phase) {
     case 1:
-        if (h->nblk_v) hipLaunchKernelGGL(k_vertex, dim3(h->nblk_v), dim3(VL), h->v_lds, s, h->P, h->d_blk_v, h->vs, h->v_rows,
-                               h->opts.vertex_mode);
+        if (g.nv) hipLaunchKernelGGL(k_vertex, dim3(g.nv), dim3(VL), h->v_lds, s, h->P, g.v, h->vs, h->v_rows,
+                                     h->opts.vertex_mode);
         break;
     case 2:
         if (h->regen_wave) {
-            if (h->nblk_rw) hipLaunchKernelGGL(k_assemble_w, dim3(h->nblk_rw), dim3(64), h->rw_lds, s, h->P, h->d_blk_rw, h->rw_nmax);
-        } else if (h->nblk_r) {
-            hipLaunchKernelGGL(k_assemble, dim3(h->nblk_r), dim3(64), 0, s, h->P, h->d_blk_r);
+            if (g.nrw) hipLaunchKernelGGL(k_assemble_w, dim3(g.nrw), dim3(64), h->rw_lds, s, h->P, g.rw, h->rw_nmax);
+        } else if (g.nr) {
+            hipLaunchKernelGGL(k_assemble, dim3(g.nr), dim3(64), 0, s, h->P, g.r);
         }
         break;
     case 3:
-        if (h->nblk_s) {
+        if (g.ns) {
             if (h->scatter_hbm)
-                hipLaunchKernelGGL(k_scatter<true>, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
+                hipLaunchKernelGGL(k_scatter<true>, dim3(g.ns), dim3(64), h->lds_bytes, s, h->P, g.s);
             else
-                hipLaunchKernelGGL(k_scatter<false>, dim3(h->nblk_s), dim3(64), h->lds_bytes, s, h->P, h->d_blk_s);
+                hipLaunchKernelGGL(k_scatter<false>, dim3(g.ns), dim3(64), h->lds_bytes, s, h->P, g.s);
         }
         break;
     case 4:
-        if (h->nblk_bt) {
+        if (g.nbt) {
             if (h->bt_lanes == 16)
-                hipLaunchKernelGGL(k_btemporal<16>, dim3(h->nblk_bt), dim3(16), 0, s, h->P, h->d_blk_bt);
+                hipLaunchKernelGGL(k_btemporal<16>, dim3(g.nbt), dim3(16), 0, s, h->P, g.bt);
             else
-                hipLaunchKernelGGL(k_btemporal<64>, dim3(h->nblk_bt), dim3(64), 0, s, h->P, h->d_blk_bt);
+                hipLaunchKernelGGL(k_btemporal<64>, dim3(g.nbt), dim3(64), 0, s, h->P, g.bt);
         }
         break;
     case 5:
-        if (h->nblk_bsx) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsx), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsx, 0);
+        if (g.nbsx) hipLaunchKernelGGL(k_bspatial, dim3(g.nbsx), dim3(64), h->bs_lds, s, h->P, g.bsx, 0);
         break;
     case 6:
-        if (h->nblk_bsy) hipLaunchKernelGGL(k_bspatial, dim3(h->nblk_bsy), dim3(64), h->bs_lds, s, h->P, h->d_blk_bsy, 1);
+        if (g.nbsy) hipLaunchKernelGGL(k_bspatial, dim3(g.nbsy), dim3(64), h->bs_lds, s, h->P, g.bsy, 1);
         break;
     case 7:
-        hipLaunchKernelGGL(k_finish, dim3((unsigned)h->ch.size()), dim3(256), 0, s, h->P);
+        if (g.nfin) hipLaunchKernelGGL(k_finish, dim3((unsigned)g.nfin), dim3(256), 0, s, h->P, g.fin);
         break;
     default:
         return PMWA_EINVAL;
     }
     return hipGetLastError() == hipSuccess ? PMWA_OK : PMWA_EDEVICE;
+}
+
+// Phases [p0, p1] of every group: with one group on the handle's stream;
+// with several, forked from the handle's stream to the group streams and
+// joined back, so each group advances on its own.
+static int launch_phases(pmwa_t* h, int p0, int p1)
+{
+    if (h->grp.size() == 1) {
+        for (int ph = p0; ph <= p1; ph++) {
+            int rc = launch_phase(h, ph, h->grp[0]);
+            if (rc) return rc;
+        }
+        return PMWA_OK;
+    }
+    HIPCHK(hipEventRecord(h->fork_ev, h->stream));
+    for (auto& g : h->grp) {
+        if (g.stream != h->stream) HIPCHK(hipStreamWaitEvent(g.stream, h->fork_ev, 0));
+        for (int ph = p0; ph <= p1; ph++) {
+            int rc = launch_phase(h, ph, g);
+            if (rc) return rc;
+        }
+        if (g.stream != h->stream) HIPCHK(hipEventRecord(g.done, g.stream));
+    }
+    for (auto& g : h->grp)
+        if (g.stream != h->stream) HIPCHK(hipStreamWaitEvent(h->stream, g.done, 0));
+    return PMWA_OK;
 }
 
 static int drain(pmwa_t* h)
@@ -506,10 +556,17 @@ void pmwa_destroy(pmwa_t* h)
         if (hc.staging) (void)hipHostFree(hc.staging);
         if (hc.staged) (void)hipEventDestroy(hc.staged);
     }
+    for (auto& g : h->grp) {
+        void* gp[] = {g.v, g.r, g.s, g.bt, g.bsx, g.bsy, g.rw, g.fin};
+        for (void* p : gp)
+            if (p) (void)hipFree(p);
+        if (g.done) (void)hipEventDestroy(g.done);
+        if (g.own_stream) (void)hipStreamDestroy(g.stream);
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     void* ptrs[] = {h->d_cd, h->d_cdf, h->P.ev, h->P.cnt, h->P.bs, h->P.bv, h->P.bvc, h->P.dpart,
-                    h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_nd, h->P.s_wl, h->P.s_own, h->P.s_oc, h->d_blk_v, h->d_blk_r,
-                    h->d_blk_s, h->d_blk_bt, h->d_blk_bsx, h->d_blk_bsy, h->d_blk_rw, h->d_gdisp, h->d_gpart,
+                    h->P.ser, h->P.sweep, h->P.flags, h->P.nnacc, h->P.s_nd, h->P.s_wl, h->P.s_own, h->P.s_oc, h->d_gdisp, h->d_gpart,
                     h->P.acc, h->d_hash, h->d_cpts};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -529,7 +586,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0 ||
         h->opts.event_cap > 32767 || h->opts.regen_mode < 0 || h->opts.regen_mode > 2 ||
         h->opts.vertex_mode < 0 || h->opts.vertex_mode > 3 || h->opts.scatter_lds < 0 ||
-        h->opts.scatter_lds > 160 * 1024) { delete h; return PMWA_EINVAL; }
+        h->opts.scatter_lds > 160 * 1024 || h->opts.groups < 0 || h->opts.groups > 64) { delete h; return PMWA_EINVAL; }
     h->stream = (hipStream_t)h->opts.stream;
     if (!h->stream) {
         // work goes to a stream of the handle (default priority)
@@ -674,9 +731,6 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (hipMemcpy(h->d_cd, cds.data(), n_chains * sizeof(ChainDev), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_cdf, cdfs.data(), cdf * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         r2 = PMWA_EDEVICE;
-    if (!r2) { block_table(h->ch, VL, &HostChain::n_units_v, t); r2 = upload_table(t, &h->d_blk_v, &h->nblk_v); }
-    if (!r2) { block_table(h->ch, 64, &HostChain::n_units_r, t); r2 = upload_table(t, &h->d_blk_r, &h->nblk_r); }
-    if (!r2) { block_table(h->ch, 1, &HostChain::n_dom, t); r2 = upload_table(t, &h->d_blk_s, &h->nblk_s); }
     {
         // the temporal update in 16-lane groups where 64-lane ones would
         // leave CUs idle (fewer units than 64 per CU)
@@ -684,9 +738,6 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         for (auto& hc : h->ch) units += hc.n_bt;
         h->bt_lanes = units < 64LL * std::max(prop.multiProcessorCount, 1) ? 16 : 64;
     }
-    if (!r2) { block_table(h->ch, h->bt_lanes, &HostChain::n_bt, t); r2 = upload_table(t, &h->d_blk_bt, &h->nblk_bt); }
-    if (!r2) { block_table(h->ch, 1, &HostChain::n_bsx, t); r2 = upload_table(t, &h->d_blk_bsx, &h->nblk_bsx); }
-    if (!r2) { block_table(h->ch, 1, &HostChain::n_bsy, t); r2 = upload_table(t, &h->d_blk_bsy, &h->nblk_bsy); }
     {
         // worm re-generation: one lane per (site, slab), or one wavefront
         // where there are too few units for lanes to fill the device
@@ -707,10 +758,53 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
             if (e == PMWA_EINVAL && mode == 0) h->regen_wave = false;
             else if (e && !r2) r2 = e;
         }
-        if (!r2 && h->regen_wave) {
-            block_table(h->ch, 1, &HostChain::n_units_r, t);
-            r2 = upload_table(t, &h->d_blk_rw, &h->nblk_rw);
+    }
+    // launch groups: chains split by expected work (largest first, each to
+    // the lightest group); within a group the scattering domains of the
+    // heaviest chains are dispatched first, so that a launch does not end
+    // waiting for a large domain started last
+    if (!r2) {
+        const int G = slots ? 1 : std::max(1, std::min(h->opts.groups, n_chains));
+        std::vector<int> order(n_chains);
+        for (int c = 0; c < n_chains; c++) order[c] = c;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return domain_work(h->ch[a]) * h->ch[a].n_dom > domain_work(h->ch[b]) * h->ch[b].n_dom;
+        });
+        h->grp.resize(G);
+        std::vector<double> load(G, 0.0);
+        for (int c : order) {
+            const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            h->grp[g].chains.push_back(c);
+            load[g] += domain_work(h->ch[c]) * h->ch[c].n_dom;
         }
+        for (int g = 0; g < G && !r2; g++) {
+            LaunchGroup& L = h->grp[g];
+            std::sort(L.chains.begin(), L.chains.end());
+            if (g == 0) L.stream = h->stream;
+            else if (hipStreamCreate(&L.stream) != hipSuccess) { r2 = PMWA_EDEVICE; break; }
+            else L.own_stream = true;
+            if (G > 1 && hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) { r2 = PMWA_EDEVICE; break; }
+            std::vector<int> heavy = L.chains;
+            std::stable_sort(heavy.begin(), heavy.end(),
+                             [&](int a, int b) { return domain_work(h->ch[a]) > domain_work(h->ch[b]); });
+            block_table(h->ch, L.chains, VL, &HostChain::n_units_v, t); if (!r2) r2 = upload_table(t, &L.v, &L.nv);
+            block_table(h->ch, L.chains, 64, &HostChain::n_units_r, t); if (!r2) r2 = upload_table(t, &L.r, &L.nr);
+            block_table(h->ch, heavy, 1, &HostChain::n_dom, t); if (!r2) r2 = upload_table(t, &L.s, &L.ns);
+            block_table(h->ch, L.chains, h->bt_lanes, &HostChain::n_bt, t); if (!r2) r2 = upload_table(t, &L.bt, &L.nbt);
+            block_table(h->ch, L.chains, 1, &HostChain::n_bsx, t); if (!r2) r2 = upload_table(t, &L.bsx, &L.nbsx);
+            block_table(h->ch, L.chains, 1, &HostChain::n_bsy, t); if (!r2) r2 = upload_table(t, &L.bsy, &L.nbsy);
+            if (h->regen_wave) {
+                block_table(h->ch, L.chains, 1, &HostChain::n_units_r, t);
+                if (!r2) r2 = upload_table(t, &L.rw, &L.nrw);
+            }
+            if (!r2) {
+                L.nfin = (int)L.chains.size();
+                if (hipMalloc(&L.fin, L.nfin * sizeof(int)) != hipSuccess) r2 = PMWA_ENOMEM;
+                else if (hipMemcpy(L.fin, L.chains.data(), L.nfin * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+                    r2 = PMWA_EDEVICE;
+            }
+        }
+        if (!r2 && G > 1 && hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess) r2 = PMWA_EDEVICE;
     }
     {
         int maxcap = 0, maxcapb = 0;
@@ -893,7 +987,7 @@ int pmwa_phase(pmwa_t* h, int phase)
                 break;
             }
     }
-    int rc = launch_phase(h, phase);
+    int rc = launch_phases(h, phase, phase);
     if (rc == PMWA_OK && phase == 7) advance_enq(h);
     return rc;
 }
@@ -903,7 +997,7 @@ static int build_graph(pmwa_t* h)
     hipStream_t s = h->stream;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int rc = PMWA_OK;
-    for (int ph = 1; ph <= 7 && rc == PMWA_OK; ph++) rc = launch_phase(h, ph);
+    rc = launch_phases(h, 1, 7);
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(s, &g) != hipSuccess || rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -932,10 +1026,8 @@ int pmwa_sweep(pmwa_t* h, int64_t n)
         if (graph) {
             HIPCHK(hipGraphLaunch(h->gexec, h->stream));
         } else {
-            for (int ph = 1; ph <= 7; ph++) {
-                int rc = launch_phase(h, ph);
-                if (rc) return rc;
-            }
+            int rc = launch_phases(h, 1, 7);
+            if (rc) return rc;
         }
         advance_enq(h);
     }

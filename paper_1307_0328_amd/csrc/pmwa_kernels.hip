@@ -2556,9 +2556,9 @@ __global__ void __launch_bounds__(64) k_green_sum(const double* __restrict__ par
 // End of sweep: per chain, sum the domain partials in domain order, append
 // the record to the series ring, advance the sweep counter.
 // ===========================================================================
-__global__ void __launch_bounds__(256) k_finish(Pools P)
+__global__ void __launch_bounds__(256) k_finish(Pools P, const int* __restrict__ chains)
 {
-    const int chain = blockIdx.x;
+    const int chain = chains[blockIdx.x];
     const ChainDev& C = P.cd[chain];
     if (!live(P, C, chain)) return;
     const int nd = (int)C.n_dom;
