@@ -93,11 +93,11 @@ def traffic_from_profile(workload, kernel, hash_now):
 class Timed:
     """A handle of `cfgs`: thermalise, then timed sweeps."""
 
-    def __init__(self, P, cfgs, use_graph=False, scatter_mode=0, series_cap=4096, scatter_lds=0):
+    def __init__(self, P, cfgs, use_graph=False, scatter_mode=0, series_cap=4096, scatter_lds=0, groups=0):
         self.P = P
         self.cfgs = cfgs
         self.sim = P.Sim(params_of(P, cfgs), use_graph=use_graph, scatter_mode=scatter_mode,
-                         series_cap=series_cap, scatter_lds=scatter_lds)
+                         series_cap=series_cap, scatter_lds=scatter_lds, groups=groups)
 
     def close(self):
         self.sim.close()
@@ -233,6 +233,10 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=16)
     ap.add_argument("--large-sweeps", type=int, default=10)
     ap.add_argument("--large-therm", type=int, default=100)
+    ap.add_argument("--profile", action="store_true",
+                    help="under a profiler: no autotuning (the form below), no breakdown pass, no extra forms")
+    ap.add_argument("--scatter-lds", type=int, default=49152, help="LDS bytes of the scattering kernel with --profile")
+    ap.add_argument("--groups", type=int, default=1, help="launch groups with --profile")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -262,7 +266,19 @@ def main():
 
     # ------------------------------------------------------------------ [2]
     batch = W.batched_256()
-    if run("batched"):
+    if run("batched") and args.profile:
+        log(f"[bench] profile: 256 chains batched (scatter_lds {args.scatter_lds}, groups {args.groups}), "
+            f"thermalise {args.therm}, {args.steps} sweeps")
+        tb = Timed(P, batch, scatter_lds=args.scatter_lds, groups=args.groups)
+        try:
+            tb.advance(args.therm + args.warmup)
+            head = tb.timed(args.steps, timing=1 << PHASES.index("k_scatter"))
+        finally:
+            tb.close()
+        result["profile_batched"] = {"value": head["nv"] / head["seconds"],
+                                     "ms_per_step": head["seconds"] * 1e3 / args.steps,
+                                     "roofline": roofline(head, "k_scatter", "batched_256", hash_now)}
+    elif run("batched"):
         from paper_1307_0328_amd import autotune as T
         log("[bench] autotuning the launch form of the 256-chain batch")
         form, table = T.Tuner(sweeps=10, warmup=10, launch_forms=((0, False), (2, False))).tune_launch(batch)
