@@ -57,6 +57,15 @@ class Summary(C.Structure):
                                           "b", "err_E", "err_density", "err_Q", "err_Q_imp")]
 
 
+GQ_DMAX, GQ_AMAX, GQ_CAPMAX = 8, 4, 255
+ORC_ECAP = -4
+
+
+class LocalQ(C.Structure):
+    _fields_ = [("d", C.c_int32), ("nalpha", C.c_int32),
+                ("q", C.c_double * (GQ_AMAX * GQ_DMAX * GQ_DMAX))]
+
+
 OBS_DTYPE = np.dtype([("nv", "<i8"), ("nkink", "<i8"), ("nw", "<i8"),
                       ("occ2", "<i8"), ("nn2", "<i8"), ("qimp", "<f8")])
 
@@ -106,6 +115,9 @@ def bind(path: str):
     L.orc_reset_observables.restype = None
     L.orc_state_hash.argtypes = [C.c_void_p]
     L.orc_state_hash.restype = C.c_uint64
+    L.orc_worms_general.argtypes = [P(LocalQ), C.c_double, C.c_int64, C.c_int, C.c_int, C.c_uint64,
+                                    C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
     return L
 
 
@@ -140,6 +152,34 @@ def make_params(**kw) -> Params:
     for k, v in d.items():
         setattr(p, k, v)
     return p
+
+
+def local_q(mats) -> LocalQ:
+    """Pack operator types (d x d arrays, [out, in]) into the oracle's struct."""
+    g = LocalQ()
+    g.d = int(mats[0].shape[0])
+    g.nalpha = len(mats)
+    buf = np.zeros((GQ_AMAX, GQ_DMAX, GQ_DMAX))
+    for a, m in enumerate(mats):
+        buf[a, :g.d, :g.d] = m
+    C.memmove(g.q, buf.ctypes.data, buf.nbytes)
+    return g
+
+
+def worms_general(g: LocalQ, lam, ell, p, q, seed=1, stream=0, sweep=0, unit=0, cap=GQ_CAPMAX,
+                  library=None):
+    """Worms of one interval for a general local operator (orc_worms_general):
+    returns (n, slots, alpha, after, dirs); n < 0 is the error code."""
+    L = library if library is not None else lib()
+    slots = np.zeros(max(cap, 1), dtype=np.int32)
+    alpha = np.zeros(max(cap, 1), dtype=np.uint8)
+    after = np.zeros(max(cap, 1), dtype=np.uint8)
+    dirs = np.zeros(max(cap, 1), dtype=np.uint8)
+    n = L.orc_worms_general(C.byref(g), float(lam), int(ell), int(p), int(q), int(seed), int(stream),
+                            int(sweep), int(unit), int(cap), slots.ctypes.data, alpha.ctypes.data,
+                            after.ctypes.data, dirs.ctypes.data)
+    k = max(n, 0)
+    return n, slots[:k], alpha[:k], after[:k], dirs[:k]
 
 
 def philox(ctr, key):

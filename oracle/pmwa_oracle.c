@@ -1592,3 +1592,154 @@ int orc_poisson_table(const orc_chain* c, int k, double* cdf, int cap)
     for (int j = 0; j < n && j < cap; j++) cdf[j] = c->cdf[(size_t)k * KMAX + j];
     return n;
 }
+
+/* ------------------------------------------------------------------ */
+/* worms of one interval for a general local operator                  */
+/* (Eq. (worm) and the sequence rule after it, general form)           */
+/* ------------------------------------------------------------------ */
+#define GQ_TERMS 256
+enum { RNG_GQ = 10 };
+
+/* Draws the worms of an interval I of `ell` free half-tick slots whose end
+   states are p (bottom) and q (top), for Q = sum_alpha Q_alpha given as
+   nonnegative d x d matrices, x = I*eta = lam*ell:
+
+   1. the count n with probability x^n/n! <q|Q^n|p> / f_qp, where
+      f_qp = <q|exp(x Q)|p> is summed as a series of the scaled vectors
+      u_j = (x^j/j!) Q^j |p>;
+   2. n distinct uniform slots, sorted (as for hard-core worms);
+   3. the sequence: worm k (time order) carries the type alpha_k and takes
+      the state from s_{k-1} to s_k; the path (alpha_k, s_k) is drawn with
+      probability prod_k <s_k|Q_{alpha_k}|s_{k-1}> / <q|Q^n|p>, from the last
+      worm back to the first: given s_k, (alpha_k, s_{k-1}) is chosen with
+      weight <s_k|Q_{alpha_k}|s_{k-1}> <s_{k-1}|Q^{k-1}|p>;
+   4. one direction bit per worm in ascending slot order. */
+int orc_worms_general(const orc_localq* g, double lam, int64_t ell, int p, int q,
+                      uint64_t seed, uint32_t stream, uint32_t sweep, uint32_t unit,
+                      int cap, int32_t* slots, uint8_t* alpha, uint8_t* after, uint8_t* dirs)
+{
+    int d = g->d, na = g->nalpha;
+    if (d < 2 || d > ORC_GQ_DMAX || na < 1 || na > ORC_GQ_AMAX) return ORC_EINVAL;
+    if (p < 0 || p >= d || q < 0 || q >= d || ell < 0 || cap < 0 || cap > ORC_GQ_CAPMAX)
+        return ORC_EINVAL;
+    if (!(lam >= 0.0) || !isfinite(lam) || stream >= (1u << 24)) return ORC_EINVAL;
+    double Q[ORC_GQ_DMAX][ORC_GQ_DMAX];
+    for (int a = 0; a < d; a++)
+        for (int b = 0; b < d; b++) {
+            double s = 0.0;
+            for (int al = 0; al < na; al++) {
+                double v = g->q[al][a][b];
+                if (!(v >= 0.0) || !isfinite(v)) return ORC_EINVAL;
+                s = s + v;
+            }
+            Q[a][b] = s;
+        }
+    if (ell == 0) return p == q ? 0 : ORC_ESTATE;
+
+    /* y bounds the growth of the 1-norm: |Q v|_1 <= qn |v|_1 for v >= 0 */
+    double qn = 0.0;
+    for (int b = 0; b < d; b++) {
+        double s = 0.0;
+        for (int a = 0; a < d; a++) s = s + Q[a][b];
+        if (s > qn) qn = s;
+    }
+    double x = lam * (double)ell;
+    double y = x * qn;
+
+    /* series of f_qp; stop after term j once j + 2 >= 2y and the remaining
+       terms, at most 2 y |u_j|_1 / (j + 1), are below 2^-60 of the sum */
+    double u[GQ_TERMS][ORC_GQ_DMAX];
+    double tq[GQ_TERMS];
+    for (int a = 0; a < d; a++) u[0][a] = (a == p) ? 1.0 : 0.0;
+    double S = 0.0;
+    int J = -1;
+    for (int j = 0; j < GQ_TERMS; j++) {
+        if (j > 0) {
+            double c = x / (double)j;
+            for (int a = 0; a < d; a++) {
+                double s = 0.0;
+                for (int b = 0; b < d; b++) s = s + Q[a][b] * u[j - 1][b];
+                u[j][a] = c * s;
+            }
+        }
+        tq[j] = u[j][q];
+        S = S + tq[j];
+        double norm = 0.0;
+        for (int a = 0; a < d; a++) norm = norm + u[j][a];
+        if ((double)(j + 2) >= 2.0 * y &&
+            (norm == 0.0 || (S > 0.0 && 2.0 * y * norm / (double)(j + 1) <= 0x1p-60 * S))) {
+            J = j;
+            break;
+        }
+    }
+    if (J < 0) return ORC_EINVAL;            /* x |Q| too large for the series */
+    if (!(S > 0.0)) return ORC_ESTATE;       /* q cannot be reached from p     */
+    double f = S;
+
+    rstream s;
+    s.key[0] = (uint32_t)seed; s.key[1] = (uint32_t)(seed >> 32);
+    s.ctr[0] = 0; s.ctr[1] = unit; s.ctr[2] = sweep; s.ctr[3] = (stream << 8) | RNG_GQ;
+    s.w = 0; s.have = 0; s.blk = 0;
+
+    /* 1. the count */
+    int n = -1;
+    for (int tries = 0; tries < 1000 && n < 0; tries++) {
+        double U = u53(rs_next(&s)) * f;
+        double cum = 0.0;
+        for (int j = 0; j <= J; j++) {
+            cum = cum + tq[j];
+            if (U < cum) {
+                if ((int64_t)j <= ell) n = j;
+                break;
+            }
+        }
+    }
+    if (n < 0) return ORC_ESTATE;
+    if (n > cap) return ORC_ECAP;
+
+    /* 2. the slots */
+    for (int i = 0; i < n; i++) {
+        int32_t r;
+        int again, guard = 0;
+        do {
+            r = (int32_t)below(rs_next(&s), (uint64_t)ell);
+            again = 0;
+            for (int k = 0; k < i; k++) if (slots[k] == r) { again = 1; break; }
+        } while (again && ++guard < 100000);
+        if (again) return ORC_ESTATE;
+        slots[i] = r;
+    }
+    for (int a = 1; a < n; a++) {
+        int32_t v = slots[a]; int b = a - 1;
+        while (b >= 0 && slots[b] > v) { slots[b + 1] = slots[b]; b--; }
+        slots[b + 1] = v;
+    }
+
+    /* 3. the sequence, from the last worm back to the first */
+    int st = q;
+    for (int k = n; k >= 1; k--) {
+        double T = 0.0;
+        for (int al = 0; al < na; al++)
+            for (int b = 0; b < d; b++) T = T + g->q[al][st][b] * u[k - 1][b];
+        if (!(T > 0.0)) return ORC_ESTATE;
+        double U = u53(rs_next(&s)) * T;
+        double cum = 0.0;
+        int ca = -1, cb = -1, la = -1, lb = -1;
+        for (int al = 0; al < na && ca < 0; al++)
+            for (int b = 0; b < d; b++) {
+                double w = g->q[al][st][b] * u[k - 1][b];
+                if (w > 0.0) { la = al; lb = b; }
+                cum = cum + w;
+                if (U < cum) { ca = al; cb = b; break; }
+            }
+        if (ca < 0) { ca = la; cb = lb; }   /* U rounded up to T */
+        alpha[k - 1] = (uint8_t)ca;
+        after[k - 1] = (uint8_t)st;
+        st = cb;
+    }
+    if (st != p) return ORC_ESTATE;
+
+    /* 4. the directions */
+    for (int i = 0; i < n; i++) dirs[i] = (uint8_t)(rs_next(&s) >> 63);
+    return n;
+}

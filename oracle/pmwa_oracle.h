@@ -12,6 +12,9 @@
  *   - measurement                       (Step 6; Supplemental S-I)
  *   - temporal-boundary update          (Eq. (Para), Step 1)
  *   - spatial-boundary vertex update    (Eq. (ParaSpace), Step 2)
+ * and, on its own, the worm law of one interval for a general local
+ * operator Q = sum_alpha Q_alpha (Eq. (worm), general form, and the
+ * sequence rule after it: soft-core bosons, spin S).
  * Only tests, the smoke check and the CPU-baseline leg of the benchmark
  * may load it.  It shares no code with the GPU library.
  *
@@ -83,7 +86,7 @@ typedef struct orc_summary {
 
 typedef struct orc_chain orc_chain;
 
-enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESTATE = -3 };
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESTATE = -3, ORC_ECAP = -4 };
 
 /* phases, in sweep order */
 enum { ORC_PH_V = 1, ORC_PH_R = 2, ORC_PH_S = 3, ORC_PH_BT = 4,
@@ -146,6 +149,26 @@ int  orc_test_worms(orc_chain* c, uint32_t phase, uint32_t unit, int32_t ell,
 int  orc_test_choose(const double* w, int n, double u);
 double orc_test_temporal_p0(const orc_chain* c, int p, int q, int64_t l1,
                             int64_t l2);
+
+/* General local operator Q = sum_alpha Q_alpha on one site (Eq. (worm),
+   general form): q[alpha][out][in] = <out|Q_alpha|in> >= 0, states 0..d-1. */
+#define ORC_GQ_DMAX 8
+#define ORC_GQ_AMAX 4
+#define ORC_GQ_CAPMAX 255
+typedef struct orc_localq {
+    int32_t d, nalpha;
+    double  q[ORC_GQ_AMAX][ORC_GQ_DMAX][ORC_GQ_DMAX];
+} orc_localq;
+/* Worms of one interval of `ell` free half-tick slots, bottom state p, top
+   state q, x = lam * ell (lam = eta * beta / M): count, sorted distinct slot
+   offsets in [0, ell), the type alpha and the state just above each worm,
+   and a direction bit per worm, from the Philox stream with key `seed` and
+   counter (word block, unit, sweep, stream << 8 | 10).  Returns n >= 0;
+   ORC_ECAP when n > cap; ORC_ESTATE when q cannot be reached from p;
+   ORC_EINVAL for bad arguments or x |Q| too large for 256 series terms. */
+int orc_worms_general(const orc_localq* g, double lam, int64_t ell, int p, int q,
+                      uint64_t seed, uint32_t stream, uint32_t sweep, uint32_t unit,
+                      int cap, int32_t* slots, uint8_t* alpha, uint8_t* after, uint8_t* dirs);
 
 /* Philox4x32-10 block */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

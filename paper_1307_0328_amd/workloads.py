@@ -84,3 +84,48 @@ def serving_slot_shape(L_max: int, beta_max: float, edge: int = 8, slab_beta: fl
     return dict(Lx=L_max, Ly=L_max, beta=slab_beta * ntau, t=1.0, V=1.0, mu=-2.0, eta=0.05,
                 dom_x=L_max // edge, dom_y=L_max // edge, dom_tau=ntau, ticks_log2=24,
                 seed=0, chain_id=0)
+
+
+# --------------------------------------------------------------------------
+# Local operators for the general worm law (soft-core bosons, spin S): the
+# matrices <out|Q_alpha|in> of the operator types, and seeded intervals.
+# --------------------------------------------------------------------------
+def boson_ops(n_max: int) -> list[np.ndarray]:
+    """[b, b^+] on occupations 0..n_max: b|n> = sqrt(n)|n-1>."""
+    d = n_max + 1
+    b = np.zeros((d, d))
+    for n in range(1, d):
+        b[n - 1, n] = np.sqrt(n)
+    return [b, b.T.copy()]
+
+
+def spin_ops(two_s: int) -> list[np.ndarray]:
+    """[S^-, S^+] on m = -S..S (index m + S): S^+|m> = sqrt(S(S+1) - m(m+1))|m+1>."""
+    S = two_s / 2.0
+    d = two_s + 1
+    sp = np.zeros((d, d))
+    for i in range(d - 1):
+        m = i - S
+        sp[i + 1, i] = np.sqrt(S * (S + 1) - m * (m + 1))
+    return [sp.T.copy(), sp]
+
+
+def random_ops(seed: int, d: int, n_alpha: int, density: float = 0.5) -> list[np.ndarray]:
+    """Asymmetric nonnegative operator types with a strongly connected sum."""
+    rng = np.random.default_rng(seed)
+    mats = [np.where(rng.random((d, d)) < density, rng.random((d, d)) * 2.0, 0.0)
+            for _ in range(n_alpha)]
+    ring = np.roll(np.eye(d), 1, axis=0) * 0.5        # |i> -> |i+1>: every state reachable
+    mats[0] = mats[0] + ring
+    return mats
+
+
+def general_intervals(n: int, seed: int, d: int, ell_lo: int = 1, ell_hi: int = 1 << 20):
+    """n intervals: bottom and top states uniform over 0..d-1, lengths
+    (half-tick slots) log-uniform in [ell_lo, ell_hi]."""
+    rng = np.random.default_rng(seed)
+    p = rng.integers(0, d, size=n).astype(np.int32)
+    q = rng.integers(0, d, size=n).astype(np.int32)
+    ell = np.exp(rng.uniform(np.log(ell_lo), np.log(ell_hi), size=n)).astype(np.int64)
+    ell = np.clip(ell, ell_lo, ell_hi)
+    return p, q, ell
