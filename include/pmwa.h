@@ -330,6 +330,56 @@ int pmwa_correlator(pmwa_t* h, int chain, int npt, const int32_t* pts, int ncorr
 #define PMWA_GREEN_STATIC_PARTIALS (1 << 19)
 int pmwa_green_static(pmwa_t* h, int chain, const int32_t* disp, int n, double* out);
 
+/* ------------------------------------------------------------------------
+   Worms of an interval for a general local operator (paper: "Worm creation
+   and annihilation", Eq. (worm) in its general form and the sequence rule
+   after it).  The worm-generating operator of a site is Q = sum_alpha
+   Q_alpha over up to PMWA_GQ_AMAX operator types, each a nonnegative
+   d x d matrix q[alpha][out][in] = <out|Q_alpha|in> on local states
+   0..d-1, d <= PMWA_GQ_DMAX (soft-core bosons: b, b^+ with n <= d - 1;
+   spin S: S^-, S^+ with d = 2S + 1; hard-core bosons are d = 2).
+   ------------------------------------------------------------------------ */
+#define PMWA_GQ_DMAX 8
+#define PMWA_GQ_AMAX 4
+#define PMWA_GQ_CAPMAX 255
+typedef struct pmwa_localq {
+    int32_t d, nalpha;
+    double  q[PMWA_GQ_AMAX][PMWA_GQ_DMAX][PMWA_GQ_DMAX];   /* entries beyond d, nalpha ignored */
+} pmwa_localq;
+
+/* Draws the worms of n_int intervals.  Interval i has ell[i] free half-tick
+   slots, bottom state p[i] and top state q[i]; with x = lam * ell[i]
+   (lam = eta * beta / M, I*eta of the paper):
+     - the count n with probability x^n/n! <q|Q^n|p> / <q|exp(xQ)|p>;
+       <q|exp(xQ)|p> is the series of u_j = (x/j) Q u_{j-1}, u_0 = |p>,
+       stopped after the first term j with j + 2 >= 2y, y = x * (largest
+       column sum of Q), and either u_j = 0 or 2 y |u_j|_1 / (j + 1) <=
+       2^-60 (sum so far); n by inversion of the partial sums (a new
+       uniform when u*f rounds to f or n > ell[i]);
+     - n distinct uniform slot offsets in [0, ell[i]), ascending;
+     - the type alpha_k of worm k (time order) and the state s_k just above
+       it, the path having probability prod_k <s_k|Q_alpha_k|s_{k-1}> /
+       <q|Q^n|p> (s_0 = p, s_n = q), drawn from the last worm back;
+     - one direction bit per worm (1 = up) in slot order.
+   Random words: Philox4x32-10 with key `seed`, counter (word pair, unit0 +
+   i, sweep, stream << 8 | 10), 64-bit words u53 / high-product as in the
+   sweep.  All pointers except g are DEVICE pointers: p, q, ell[n_int] in;
+   n_out[n_int] out (the count, or for this interval PMWA_EINVAL (state out
+   of range, negative length, x |Q| too large for 256 series terms),
+   PMWA_ESTATE (q unreachable from p, or no draw), PMWA_EOVERFLOW (n >
+   cap)); slots (int32), alpha, after (state above the worm), dirs (uint8)
+   are cap x n_int, worm k of interval i at k * n_int + i (may be NULL when
+   cap = 0).  Asynchronous on hip_stream (NULL: the default stream); the
+   library keeps a device workspace of (cap + 1) * d doubles per lane (at most
+   256 MB, grown on demand) and orders calls on it with an event.  Returns
+   PMWA_EINVAL for bad arguments (d, nalpha, negative or non-finite
+   entries, lam, cap > PMWA_GQ_CAPMAX, stream >= 2^24, unit0 + n_int >
+   2^32), PMWA_ENOMEM, PMWA_EDEVICE. */
+int pmwa_worms_general(const pmwa_localq* g, double lam, int64_t n_int, const int32_t* p, const int32_t* q,
+                       const int64_t* ell, uint64_t seed, uint32_t stream, uint32_t sweep, uint32_t unit0,
+                       int32_t cap, int32_t* n_out, int32_t* slots, uint8_t* alpha, uint8_t* after,
+                       uint8_t* dirs, void* hip_stream);
+
 /* Events per (site, slab) a chain would be given by default. */
 int pmwa_default_event_cap(const pmwa_params* p);
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmwa.so")
-SOURCES = [os.path.join(CSRC, "pmwa_kernels.hip"), os.path.join(CSRC, "pmwa_host.hip")]
+SOURCES = [os.path.join(CSRC, "pmwa_kernels.hip"), os.path.join(CSRC, "pmwa_host.hip"),
+           os.path.join(CSRC, "pmwa_worms_general.hip")]
 HEADERS = [os.path.join(CSRC, "pmwa_device.h"), os.path.join(ROOT, "include", "pmwa.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -22,7 +22,8 @@ EXPORTS = ["pmwa_create", "pmwa_sweep", "pmwa_phase", "pmwa_measure", "pmwa_stat
            "pmwa_destroy", "pmwa_strerror", "pmwa_set_timing", "pmwa_set_timing_phases", "pmwa_phase_times", "pmwa_diag",
            "pmwa_green", "pmwa_chain_status", "pmwa_observables", "pmwa_reset_observables",
            "pmwa_state_hash", "pmwa_slot_fits", "pmwa_green_static", "pmwa_correlator",
-           "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress"]
+           "pmwa_create_slots", "pmwa_slot_load", "pmwa_slot_release", "pmwa_slot_progress",
+           "pmwa_worms_general"]
 
 
 class pmwa_params(C.Structure):
@@ -49,6 +50,14 @@ class pmwa_summary(C.Structure):
                [(n, C.c_double) for n in ("qimp", "nv_sq", "nkink_sq", "nw_sq", "occ2_sq", "nn2_sq",
                                           "qimp_sq", "E", "E_alt", "E_eta", "density", "Q", "Q_imp",
                                           "b", "err_E", "err_density", "err_Q", "err_Q_imp")]
+
+
+GQ_DMAX, GQ_AMAX, GQ_CAPMAX = 8, 4, 255
+
+
+class pmwa_localq(C.Structure):
+    _fields_ = [("d", C.c_int32), ("nalpha", C.c_int32),
+                ("q", C.c_double * (GQ_AMAX * GQ_DMAX * GQ_DMAX))]
 
 
 class pmwa_info(C.Structure):
@@ -101,6 +110,10 @@ def lib():
         L.pmwa_slot_fits.argtypes = [C.c_void_p, C.c_int, P(pmwa_params)]
         L.pmwa_green_static.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p]
         L.pmwa_correlator.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        L.pmwa_worms_general.argtypes = [P(pmwa_localq), C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                         C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]
         L.pmwa_strerror.argtypes = [C.c_int]
         L.pmwa_strerror.restype = C.c_char_p
         _lib = L
@@ -129,6 +142,18 @@ def make_params(**kw) -> pmwa_params:
     for k, v in d.items():
         setattr(p, k, v)
     return p
+
+
+def localq(mats) -> pmwa_localq:
+    """Operator types (d x d arrays indexed [out, in]) as a pmwa_localq."""
+    g = pmwa_localq()
+    g.d = int(mats[0].shape[0])
+    g.nalpha = len(mats)
+    buf = np.zeros((GQ_AMAX, GQ_DMAX, GQ_DMAX))
+    for a, m in enumerate(mats):
+        buf[a, :g.d, :g.d] = m
+    C.memmove(g.q, buf.ctypes.data, buf.nbytes)
+    return g
 
 
 # --- thin wrappers with the C names -------------------------------------
@@ -390,3 +415,32 @@ class Sim:
 
     def chain_status(self, chain=0):
         return pmwa_chain_status(self.h, chain)
+
+
+def pmwa_worms_general(g, lam, p, q, ell, seed=1, stream=0, sweep=0, unit0=0, cap=64, hip_stream=None,
+                       out=None):
+    """Worms of len(p) intervals (pmwa_worms_general).  p, q: int32 and ell:
+    int64 device tensors; returns device tensors n (int32), slots (int32),
+    alpha, after, dirs (uint8), the last four [cap, n_int] (worm k of
+    interval i at [k, i]).  `out` may hold such tensors to reuse."""
+    import torch
+    n = int(p.numel())
+    if p.dtype != torch.int32 or q.dtype != torch.int32 or ell.dtype != torch.int64:
+        raise TypeError("p, q must be int32 and ell int64 device tensors")
+    if not (p.is_cuda and q.is_cuda and ell.is_cuda and p.is_contiguous() and q.is_contiguous()
+            and ell.is_contiguous()) or q.numel() != n or ell.numel() != n:
+        raise ValueError("p, q, ell must be contiguous device tensors of one length")
+    dev = p.device
+    if out is None:
+        out = dict(n=torch.empty(n, dtype=torch.int32, device=dev),
+                   slots=torch.empty((cap, n), dtype=torch.int32, device=dev),
+                   alpha=torch.empty((cap, n), dtype=torch.uint8, device=dev),
+                   after=torch.empty((cap, n), dtype=torch.uint8, device=dev),
+                   dirs=torch.empty((cap, n), dtype=torch.uint8, device=dev))
+    st = hip_stream if hip_stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().pmwa_worms_general(C.byref(g), float(lam), n, p.data_ptr(), q.data_ptr(), ell.data_ptr(),
+                                  int(seed), int(stream), int(sweep), int(unit0), int(cap),
+                                  out["n"].data_ptr(), out["slots"].data_ptr(), out["alpha"].data_ptr(),
+                                  out["after"].data_ptr(), out["dirs"].data_ptr(), C.c_void_p(st))
+    _check(rc, "pmwa_worms_general")
+    return out
