@@ -19,6 +19,8 @@ Also reported:
 - one 64x64 chain (beta*t = 16, 8x8x2 domains), plain and graph;
 - one 2048x2048 system (beta*t = 16, 64x64x4 domains) with its own roofline,
   and the order parameter at L = 256, 512, 1024 on the same domain shape;
+- the worm law of a general local operator (soft-core bosons, n_max = 3)
+  over 2^22 intervals: intervals/s, worms/s and the fp64 rate;
 - a continuous-batching serving run (p50/p99 job latency);
 - per-kernel device times and the roofline of the dominant kernel (HIP
   events on the handle's stream around that kernel, in the timed region);
@@ -44,8 +46,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PHASES = ["k_vertex", "k_assemble", "k_scatter", "k_btemporal", "k_bspatial_x", "k_bspatial_y", "k_finish"]
-KERNEL_SOURCES = ["paper_1307_0328_amd/csrc/pmwa_kernels.hip", "paper_1307_0328_amd/csrc/pmwa_device.h"]
-WORKLOADS = ("batched", "single", "large", "scaling", "serving", "cpu")
+KERNEL_SOURCES = ["paper_1307_0328_amd/csrc/pmwa_kernels.hip", "paper_1307_0328_amd/csrc/pmwa_device.h",
+                  "paper_1307_0328_amd/csrc/pmwa_host.hip"]
+WORKLOADS = ("batched", "single", "large", "scaling", "worms_general", "serving", "cpu")
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -76,16 +80,16 @@ def alg_bytes(kernel, nv, nw):
             "k_assemble": 24.0 * nv + 8.0 * nw}.get(kernel, 32.0 * nv)
 
 
-def traffic_from_profile(workload, kernel, hash_now):
+def traffic_from_profile(workload, kernel, hash_now, form=None):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
     WRITE_SIZE summary of this workload, if it was taken on the current
-    kernel sources."""
+    kernel and host sources and in the same launch form."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
     if not os.path.exists(path):
         return None, None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_hash") != hash_now:
+    if rec.get("kernel_source_hash") != hash_now or (form is not None and rec.get("form") != form):
         return None, os.path.relpath(path, ROOT)
     return rec.get("bytes_per_launch"), os.path.relpath(path, ROOT)
 
@@ -137,13 +141,13 @@ def kernel_table(res):
     return {PHASES[i]: float(res["ms"][i]) / max(int(res["launches"][i]), 1) for i in range(7)}
 
 
-def roofline(res, kernel, workload, hash_now):
+def roofline(res, kernel, workload, hash_now, form=None):
     ph = PHASES.index(kernel)
     avg_ms = float(res["ms"][ph]) / max(int(res["launches"][ph]), 1)
     nv, nw = res["nv"] / res["steps"], res["nw"] / res["steps"]
     b = alg_bytes(kernel, nv, nw)
     achieved = b / (avg_ms * 1e-3) / 1e9
-    traffic, src = traffic_from_profile(workload, kernel, hash_now)
+    traffic, src = traffic_from_profile(workload, kernel, hash_now, form)
     out = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
            "algorithmic_bytes_per_launch": b, "avg_launch_ms": avg_ms,
@@ -151,6 +155,78 @@ def roofline(res, kernel, workload, hash_now):
     if src:
         out["traffic_source"] = src
     return out
+
+
+def series_terms(mats, lam, p, q, ell):
+    """Series length J + 1 of every interval under the stopping rule of
+    pmwa_worms_general (for the flop count of the benchmark only)."""
+    Q = sum(mats)
+    d = Q.shape[0]
+    qn = Q.sum(axis=0).max()
+    x = lam * ell.astype(np.float64)
+    y = x * qn
+    u = np.zeros((len(p), d))
+    u[np.arange(len(p)), p] = 1.0
+    S = np.zeros(len(p))
+    J = np.full(len(p), -1)
+    for j in range(256):
+        if j > 0:
+            u = (x / j)[:, None] * (u @ Q.T)
+        S += u[np.arange(len(p)), q]
+        norm = u.sum(axis=1)
+        stop = (J < 0) & (j + 2 >= 2.0 * y) & ((norm == 0.0) | ((S > 0) & (2.0 * y * norm / (j + 1) <= 2.0 ** -60 * S)))
+        J[stop] = j
+        if (J >= 0).all():
+            break
+    return np.where(J >= 0, J, 255) + 1
+
+
+def worms_general_leg(P, W, reps):
+    """pmwa_worms_general on 2^22 intervals of soft-core bosons (n_max = 3):
+    bottom and top occupations uniform in 0..3, lengths log-uniform over
+    1 .. 2^22 slots, lam = 4 / 2^22 (x = I*eta up to 4), cap 64."""
+    import torch
+    mats = W.boson_ops(3)
+    n_int = 1 << 22
+    p, q, ell = W.general_intervals(n_int, 41, 4, 1, 1 << 22)
+    lam = 4.0 / (1 << 22)
+    g = P.localq(mats)
+    tp = torch.from_numpy(p).cuda()
+    tq = torch.from_numpy(q).cuda()
+    tl = torch.from_numpy(ell).cuda()
+    out = P.pmwa_worms_general(g, lam, tp, tq, tl, seed=9, cap=64)
+    torch.cuda.synchronize()
+    reps = max(1, min(reps, 50))
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for r in range(reps):
+        P.pmwa_worms_general(g, lam, tp, tq, tl, seed=9, sweep=r + 1, cap=64, out=out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = out["n"].cpu().numpy()
+    ok = n >= 0
+    terms = series_terms(mats, lam, p, q, ell)
+    d, na = 4, 2
+    flops = float((terms * (2 * d * d + 2 * d)).sum() + (np.where(ok, n, 0) * (4 * na * d)).sum())
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"workload": "2^22 intervals of soft-core bosons (b, b^+ with n <= 3): end occupations uniform, "
+                        "lengths log-uniform over 1..2^22 half-tick slots, x = lam*ell up to 4, cap 64",
+            "intervals_per_s": n_int / (ms * 1e-3), "worms_per_s": float(np.where(ok, n, 0).sum()) / (ms * 1e-3),
+            "ms_per_call": ms, "calls_timed": reps, "failed_intervals": int((~ok).sum()),
+            "mean_series_terms": float(terms.mean()),
+            "roofline": {"bound": "alu", "kernel": "k_worms_general", "achieved": achieved,
+                         "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                         "flops_per_call": flops,
+                         "flop_count": "per series term 2d^2 + 2d (matrix-vector product, scaling, norm), "
+                                       "per worm 4 * types * d (sequence weights, two passes)"}}
+
+
+def batched_form(slab, lds):
+    """Launch form of the 256-chain batch, as the profile summaries name it."""
+    return f"temporal slabs of at most beta*t {slab}, scatter_lds {lds}" if slab else f"one slab, scatter_lds {lds}"
 
 
 def plain_from_states(P, cfgs, states, steps):
@@ -237,6 +313,8 @@ def main():
                     help="under a profiler: no autotuning (the form below), no breakdown pass, no extra forms")
     ap.add_argument("--scatter-lds", type=int, default=49152, help="LDS bytes of the scattering kernel with --profile")
     ap.add_argument("--groups", type=int, default=1, help="launch groups with --profile")
+    ap.add_argument("--slab", type=float, default=8.0,
+                    help="with --profile: temporal domains ceil(beta*t / slab) per chain (0: one)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -267,8 +345,10 @@ def main():
     # ------------------------------------------------------------------ [2]
     batch = W.batched_256()
     if run("batched") and args.profile:
-        log(f"[bench] profile: 256 chains batched (scatter_lds {args.scatter_lds}, groups {args.groups}), "
-            f"thermalise {args.therm}, {args.steps} sweeps")
+        from paper_1307_0328_amd import autotune as T
+        batch = T.temporal_tiling(batch, args.slab if args.slab > 0 else None)
+        log(f"[bench] profile: 256 chains batched (slab {args.slab}, scatter_lds {args.scatter_lds}, "
+            f"groups {args.groups}), thermalise {args.therm}, {args.steps} sweeps")
         tb = Timed(P, batch, scatter_lds=args.scatter_lds, groups=args.groups)
         try:
             tb.advance(args.therm + args.warmup)
@@ -277,13 +357,16 @@ def main():
             tb.close()
         result["profile_batched"] = {"value": head["nv"] / head["seconds"],
                                      "ms_per_step": head["seconds"] * 1e3 / args.steps,
-                                     "roofline": roofline(head, "k_scatter", "batched_256", hash_now)}
+                                     "roofline": roofline(head, "k_scatter", "batched_256", hash_now,
+                                                          batched_form(args.slab if args.slab > 0 else None,
+                                                                       args.scatter_lds))}
     elif run("batched"):
         from paper_1307_0328_amd import autotune as T
-        log("[bench] autotuning the launch form of the 256-chain batch")
-        form, table = T.Tuner(sweeps=10, warmup=10, launch_forms=((0, False), (2, False))).tune_launch(batch)
-        mode, lds = form[0], form[2]
-        log(f"[bench] 256 chains batched (scatter_mode {mode}, LDS {lds}): thermalise {args.therm}, "
+        log("[bench] autotuning the temporal tiling and scattering LDS of the 256-chain batch")
+        tuner = T.Tuner(sweeps=20, warmup=100)
+        (slab, lds), batch, table = tuner.tune_tiling(batch)
+        mode = 0
+        log(f"[bench] 256 chains batched (slabs of at most beta*t {slab}, LDS {lds}): thermalise {args.therm}, "
             f"warm-up {args.warmup}")
         tb = Timed(P, batch, scatter_mode=mode, scatter_lds=lds)
         try:
@@ -330,16 +413,18 @@ def main():
                                    "beta*t in {4,8,16}, mu on the 16-point grid in [-2,2] (host RNG seed 3), "
                                    "t=1, V=0, eta=0.05, 4x4 spatial domains, M=2^24 ticks",
                        "chains": len(batch), "thermalisation_sweeps": args.therm, "sweeps_timed": args.steps,
-                       "form": f"batched, one launch per phase for all chains (scatter_mode {mode}, "
-                               f"scatter_lds {lds})"},
-            "roofline": roofline(head, dom, "batched_256", hash_now),
+                       "tiling": ("autotuned: temporal domains ceil(beta*t / %s) per chain" % slab) if slab
+                                 else "autotuned: one temporal domain per chain",
+                       "dom_tau_per_beta": sorted({f"{c['beta']:g}:{c['dom_tau']}" for c in batch}),
+                       "slab_beta_t": slab, "scatter_lds": lds,
+                       "form": f"batched, one launch per phase for all chains (scatter_lds {lds})"},
+            "roofline": roofline(head, dom, "batched_256", hash_now, batched_form(slab, lds)),
             "plain": {"value": pl["nv"] / pl["seconds"], "ms_per_step": pl["seconds"] * 1e3 / args.steps,
                       "form": "one chain per handle, one launch sequence per phase per sweep, no graph, "
                               "same thermalised states, same sweeps",
                       "batched_over_plain": value / (pl["nv"] / pl["seconds"]), "same_work": same_work},
             "graph_form": {"value": gr["nv"] / gr["seconds"], "ms_per_step": gr["seconds"] * 1e3 / args.steps},
-            "autotune_table": [{"scatter_mode": f[0], "graph": bool(f[1]), "scatter_lds": f[2], "value": v}
-                               for f, v in table],
+            "autotune_table": [{"slab_beta_t": f[0], "scatter_lds": f[1], "value": v} for f, v in table],
             "kernel_ms_per_sweep": kern,
             "algorithmic_GBps_per_sweep": 32.0 * nv_per / (ms_step * 1e-3) / 1e9,
             "worm_scatterings_per_s": head["attempts"] / head["seconds"],
@@ -421,6 +506,9 @@ def main():
             "workload": "the 2048^2 workload's parameters and domain shape at L = 256, 512, 1024: 200 "
                         "thermalisation + 200 measured sweeps each (errors ignore autocorrelation)",
             "rows": rows}
+
+    if run("worms_general"):
+        result["worms_general"] = worms_general_leg(P, W, args.steps)
 
     # ------------------------------------------------------------------ [4]
     if run("serving") and args.serving_jobs > 0:

@@ -371,7 +371,7 @@ typedef struct pmwa_localq {
    are cap x n_int, worm k of interval i at k * n_int + i (may be NULL when
    cap = 0).  Asynchronous on hip_stream (NULL: the default stream); the
    library keeps a device workspace of (cap + 1) * d doubles per lane (at most
-   256 MB, grown on demand) and orders calls on it with an event.  Returns
+   512 MB, grown on demand) and orders calls on it with an event.  Returns
    PMWA_EINVAL for bad arguments (d, nalpha, negative or non-finite
    entries, lam, cap > PMWA_GQ_CAPMAX, stream >= 2^24, unit0 + n_int >
    2^32), PMWA_ENOMEM, PMWA_EDEVICE. */

@@ -1,6 +1,7 @@
 """Autotuner of the PMWA sweep on one GPU.
 
-It picks, per problem class, the domain grid and the launch form:
+It picks, per problem class or for a whole batch, the domain grid and the
+launch form:
 - the spatial tile edge and the number of temporal slabs;
 - the node store of the scattering kernel (LDS or HBM) and the LDS bytes a
   domain of the LDS form may take (fewer bytes let more domains share a CU;
@@ -85,6 +86,18 @@ def tile_candidates(Lx: int, Ly: int, beta: float, t: float = 1.0, edges=(4, 8, 
         bt = beta * (t if t > 0 else 1.0)
         taus = sorted({min(64, max(1, math.ceil(bt / s))) for s in slab_bt})
     return [Candidate(dx, dy, nt) for (dx, dy) in sorted(set(spatial)) for nt in taus]
+
+
+def temporal_tiling(chains: list[dict], slab_bt: float | None) -> list[dict]:
+    """The chains with ceil(beta*t / slab_bt) temporal domains each (at most
+    64; slab_bt None leaves them unchanged)."""
+    if slab_bt is None:
+        return [dict(c) for c in chains]
+    out = []
+    for c in chains:
+        bt = c["beta"] * (c.get("t", 1.0) if c.get("t", 1.0) > 0 else 1.0)
+        out.append(dict(c, dom_tau=min(64, max(1, math.ceil(bt / slab_bt - 1e-9)))))
+    return out
 
 
 def measure_rate(chains: list[dict], cand: Candidate | None, sweeps: int = 20, warmup: int = 10,
@@ -197,6 +210,31 @@ class Tuner:
         if rate <= 0.0:
             raise RuntimeError("autotune: no launch form ran for the batch")
         return best, table
+
+    def tune_tiling(self, chains: list[dict], slab_options=(None, 8.0, 4.0),
+                    lds_options=(28672, 36864, 49152, 65536)):
+        """Temporal tiling and scattering LDS bytes for a whole batch, spatial
+        grids as given: every chain gets ceil(beta*t / slab) temporal domains
+        (slab None: the chains' own), and each (slab, LDS bytes) pair is timed
+        on all chains together.  Smaller slabs put more domains in the LDS
+        node store and give the per-(bond, slab) and per-(site, slab) kernels
+        more units; larger ones keep fewer boundaries.  Returns the best
+        (slab, lds), the tiled chains and the table."""
+        table = []
+        for slab in slab_options:
+            tiled = temporal_tiling(chains, slab)
+            for lds in lds_options:
+                rate = 0.0
+                try:
+                    rate = float(self.measure(tiled, None, self.sweeps, self.warmup, mode=0, use_graph=False,
+                                              lds=lds))
+                except P.PmwaError:
+                    pass
+                table.append(((slab, lds), rate))
+        best, rate = max(table, key=lambda fr: fr[1])
+        if rate <= 0.0:
+            raise RuntimeError("autotune: no tiling ran for the batch")
+        return best, temporal_tiling(chains, best[0]), table
 
     def tune_batch(self, chains: list[dict], fix_spatial=None, fix_tau=None):
         """Tune each problem class of a batch once (timing one chain of the

@@ -256,7 +256,7 @@ namespace {
 // the process.  A call waits (on its stream) for the previous call's kernel
 // before reusing it, so calls on different streams do not overlap on it.
 constexpr int WS_MAX_DEVICES = 64;
-constexpr size_t WS_BUDGET = size_t(256) << 20;
+constexpr size_t WS_BUDGET = size_t(512) << 20;
 struct Workspace {
     void* ptr = nullptr;
     size_t bytes = 0;

@@ -77,3 +77,25 @@ def test_tune_batch_times_each_class_once():
     assert [c["chain_id"] for c in tuned] == [0, 1, 2, 3]
     # the largest slab count offered wins under this timing
     assert tuned[0]["dom_tau"] == max(c.dom_tau for c in T.tile_candidates(16, 16, 4.0, fix_spatial=(4, 4)))
+
+
+def test_temporal_tiling_and_tune_tiling():
+    chains = [dict(Lx=16, Ly=16, beta=b, t=1.0, V=0.0, mu=0.0, eta=0.05, dom_x=4, dom_y=4, dom_tau=1,
+                   seed=3, chain_id=i) for i, b in enumerate([4.0, 8.0, 16.0, 6.0])]
+    assert [c["dom_tau"] for c in T.temporal_tiling(chains, 4.0)] == [1, 2, 4, 2]
+    assert [c["dom_tau"] for c in T.temporal_tiling(chains, 8.0)] == [1, 1, 2, 1]
+    assert T.temporal_tiling(chains, None) == chains
+    seen = []
+
+    def fake(cs, cand, sweeps, warmup, mode=0, use_graph=False, lds=0):
+        assert cand is None and mode == 0 and not use_graph
+        taus = tuple(c["dom_tau"] for c in cs)
+        seen.append((taus, lds))
+        # prefer slabs of beta*t 8 with 36 KB
+        return 1e6 * (1.0 + (taus == (1, 1, 2, 1)) + 0.5 * (lds == 36864))
+
+    best, tiled, table = T.Tuner(measure=fake).tune_tiling(chains)
+    assert best == (8.0, 36864)
+    assert [c["dom_tau"] for c in tiled] == [1, 1, 2, 1]
+    assert [c["chain_id"] for c in tiled] == [0, 1, 2, 3]
+    assert len(table) == len(seen) == 12
