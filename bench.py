@@ -32,6 +32,7 @@ Also reported:
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import hashlib
 import json
 import multiprocessing as mp
@@ -185,27 +186,36 @@ def worms_general_leg(P, W, reps):
     """pmwa_worms_general on 2^22 intervals of soft-core bosons (n_max = 3):
     bottom and top occupations uniform in 0..3, lengths log-uniform over
     1 .. 2^22 slots, lam = 4 / 2^22 (x = I*eta up to 4), cap 64."""
-    import torch
     mats = W.boson_ops(3)
     n_int = 1 << 22
     p, q, ell = W.general_intervals(n_int, 41, 4, 1, 1 << 22)
     lam = 4.0 / (1 << 22)
     g = P.localq(mats)
-    tp = torch.from_numpy(p).cuda()
-    tq = torch.from_numpy(q).cuda()
-    tl = torch.from_numpy(ell).cuda()
-    out = P.pmwa_worms_general(g, lam, tp, tq, tl, seed=9, cap=64)
-    torch.cuda.synchronize()
-    reps = max(1, min(reps, 50))
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for r in range(reps):
-        P.pmwa_worms_general(g, lam, tp, tq, tl, seed=9, sweep=r + 1, cap=64, out=out)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    n = out["n"].cpu().numpy()
+    H = P.hip()
+    work = P.WormsGeneral(p, q, ell, cap=64)
+    st = P.DeviceStream()
+    e0, e1 = C.c_void_p(), C.c_void_p()
+    H.hipEventCreate(C.byref(e0))
+    H.hipEventCreate(C.byref(e1))
+    try:
+        work.run(g, lam, seed=9, hip_stream=st)          # first call: the workspace grows
+        st.synchronize()
+        reps = max(1, min(reps, 50))
+        H.hipEventRecord(e0, st.h)
+        for r in range(reps):
+            work.run(g, lam, seed=9, sweep=r + 1, hip_stream=st)
+        H.hipEventRecord(e1, st.h)
+        H.hipEventSynchronize(e1)
+        f = C.c_float()
+        H.hipEventElapsedTime(C.byref(f), e0, e1)
+        ms = f.value / reps
+        out = work.result()
+    finally:
+        H.hipEventDestroy(e0)
+        H.hipEventDestroy(e1)
+        st.close()
+        work.close()
+    n = out["n"]
     ok = n >= 0
     terms = series_terms(mats, lam, p, q, ell)
     d, na = 4, 2

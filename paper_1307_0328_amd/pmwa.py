@@ -417,30 +417,142 @@ class Sim:
         return pmwa_chain_status(self.h, chain)
 
 
-def pmwa_worms_general(g, lam, p, q, ell, seed=1, stream=0, sweep=0, unit0=0, cap=64, hip_stream=None,
-                       out=None):
-    """Worms of len(p) intervals (pmwa_worms_general).  p, q: int32 and ell:
-    int64 device tensors; returns device tensors n (int32), slots (int32),
-    alpha, after, dirs (uint8), the last four [cap, n_int] (worm k of
-    interval i at [k, i]).  `out` may hold such tensors to reuse."""
-    import torch
-    n = int(p.numel())
-    if p.dtype != torch.int32 or q.dtype != torch.int32 or ell.dtype != torch.int64:
-        raise TypeError("p, q must be int32 and ell int64 device tensors")
-    if not (p.is_cuda and q.is_cuda and ell.is_cuda and p.is_contiguous() and q.is_contiguous()
-            and ell.is_contiguous()) or q.numel() != n or ell.numel() != n:
-        raise ValueError("p, q, ell must be contiguous device tensors of one length")
-    dev = p.device
-    if out is None:
-        out = dict(n=torch.empty(n, dtype=torch.int32, device=dev),
-                   slots=torch.empty((cap, n), dtype=torch.int32, device=dev),
-                   alpha=torch.empty((cap, n), dtype=torch.uint8, device=dev),
-                   after=torch.empty((cap, n), dtype=torch.uint8, device=dev),
-                   dirs=torch.empty((cap, n), dtype=torch.uint8, device=dev))
-    st = hip_stream if hip_stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    rc = lib().pmwa_worms_general(C.byref(g), float(lam), n, p.data_ptr(), q.data_ptr(), ell.data_ptr(),
-                                  int(seed), int(stream), int(sweep), int(unit0), int(cap),
-                                  out["n"].data_ptr(), out["slots"].data_ptr(), out["alpha"].data_ptr(),
-                                  out["after"].data_ptr(), out["dirs"].data_ptr(), C.c_void_p(st))
-    _check(rc, "pmwa_worms_general")
-    return out
+# --- device buffers through the library's own HIP runtime ---------------
+# The general worm law takes device arrays.  They are allocated with the HIP
+# runtime that libpmwa.so itself loaded (dlopen by its soname returns that
+# copy), so the pointers and streams are those of the library's runtime.
+_hip = None
+H2D, D2H = 1, 2
+
+
+def hip():
+    global _hip
+    if _hip is None:
+        lib()
+        H = C.CDLL("libamdhip64.so.7")
+        H.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        H.hipFree.argtypes = [C.c_void_p]
+        H.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        H.hipDeviceSynchronize.argtypes = []
+        H.hipStreamCreate.argtypes = [C.POINTER(C.c_void_p)]
+        H.hipStreamDestroy.argtypes = [C.c_void_p]
+        H.hipStreamSynchronize.argtypes = [C.c_void_p]
+        H.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        H.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+        H.hipEventSynchronize.argtypes = [C.c_void_p]
+        H.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        H.hipEventDestroy.argtypes = [C.c_void_p]
+        _hip = H
+    return _hip
+
+
+def _hip_check(rc, where):
+    if rc != 0:
+        raise PmwaError(PMWA_EDEVICE, f"{where} (hip error {rc})")
+
+
+class DeviceArray:
+    """A device allocation holding one numpy array's worth of data."""
+
+    def __init__(self, shape, dtype):
+        self.shape = tuple(shape) if np.ndim(shape) else (int(shape),)
+        self.dtype = np.dtype(dtype)
+        self.nbytes = int(np.prod(self.shape)) * self.dtype.itemsize
+        self.ptr = C.c_void_p()
+        _hip_check(hip().hipMalloc(C.byref(self.ptr), max(self.nbytes, 1)), "hipMalloc")
+
+    @classmethod
+    def from_numpy(cls, a):
+        a = np.ascontiguousarray(a)
+        d = cls(a.shape, a.dtype)
+        if a.nbytes:
+            _hip_check(hip().hipMemcpy(d.ptr, a.ctypes.data, a.nbytes, H2D), "hipMemcpy")
+        return d
+
+    def numpy(self):
+        a = np.empty(self.shape, self.dtype)
+        if self.nbytes:
+            _hip_check(hip().hipMemcpy(a.ctypes.data, self.ptr, self.nbytes, D2H), "hipMemcpy")
+        return a
+
+    def free(self):
+        if self.ptr:
+            hip().hipFree(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class DeviceStream:
+    """A HIP stream of the library's runtime (default priority)."""
+
+    def __init__(self):
+        self.h = C.c_void_p()
+        _hip_check(hip().hipStreamCreate(C.byref(self.h)), "hipStreamCreate")
+
+    def synchronize(self):
+        _hip_check(hip().hipStreamSynchronize(self.h), "hipStreamSynchronize")
+
+    def close(self):
+        if self.h:
+            hip().hipStreamDestroy(self.h)
+            self.h = C.c_void_p()
+
+
+class WormsGeneral:
+    """Inputs and outputs of pmwa_worms_general for n_int intervals and a
+    cap, in device memory: n (int32), slots (int32), alpha, after, dirs
+    (uint8), the last four cap x n_int (worm k of interval i at [k, i])."""
+
+    def __init__(self, p, q, ell, cap=64):
+        p, q, ell = (np.asarray(a) for a in (p, q, ell))
+        self.n_int = int(p.size)
+        if q.size != self.n_int or ell.size != self.n_int:
+            raise ValueError("p, q and ell must have one length")
+        self.cap = int(cap)
+        self.p = DeviceArray.from_numpy(p.astype(np.int32))
+        self.q = DeviceArray.from_numpy(q.astype(np.int32))
+        self.ell = DeviceArray.from_numpy(ell.astype(np.int64))
+        self.n = DeviceArray(self.n_int, np.int32)
+        k = max(self.cap, 1)
+        self.slots = DeviceArray((k, self.n_int), np.int32)
+        self.alpha = DeviceArray((k, self.n_int), np.uint8)
+        self.after = DeviceArray((k, self.n_int), np.uint8)
+        self.dirs = DeviceArray((k, self.n_int), np.uint8)
+
+    def run(self, g, lam, seed=1, stream=0, sweep=0, unit0=0, hip_stream=None):
+        """Enqueue the draws (asynchronous on hip_stream, a DeviceStream or
+        None for the default stream)."""
+        st = hip_stream.h if isinstance(hip_stream, DeviceStream) else hip_stream
+        rc = lib().pmwa_worms_general(C.byref(g), float(lam), self.n_int, self.p.ptr, self.q.ptr, self.ell.ptr,
+                                      int(seed), int(stream), int(sweep), int(unit0), self.cap, self.n.ptr,
+                                      self.slots.ptr, self.alpha.ptr, self.after.ptr, self.dirs.ptr, st)
+        _check(rc, "pmwa_worms_general")
+        return self
+
+    def result(self):
+        """Synchronise the device and copy the outputs to host arrays."""
+        _hip_check(hip().hipDeviceSynchronize(), "hipDeviceSynchronize")
+        out = dict(n=self.n.numpy())
+        for k in ("slots", "alpha", "after", "dirs"):
+            out[k] = getattr(self, k).numpy()[:self.cap]
+        return out
+
+    def close(self):
+        for k in ("p", "q", "ell", "n", "slots", "alpha", "after", "dirs"):
+            getattr(self, k).free()
+
+
+def pmwa_worms_general(g, lam, p, q, ell, seed=1, stream=0, sweep=0, unit0=0, cap=64):
+    """Worms of the intervals (p, q, ell host arrays) drawn on the device;
+    returns host arrays n, slots, alpha, after, dirs (the last four cap x
+    n_int).  See WormsGeneral for device-resident use."""
+    w = WormsGeneral(p, q, ell, cap)
+    try:
+        return w.run(g, lam, seed, stream, sweep, unit0).result()
+    finally:
+        w.close()
