@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-jobs", type=int, default=16)
     ap.add_argument("--large-sweeps", type=int, default=10)
-    ap.add_argument("--large-therm", type=int, default=100)
+    ap.add_argument("--large-therm", type=int, default=300)
     ap.add_argument("--profile", action="store_true",
                     help="under a profiler: no autotuning (the form below), no breakdown pass, no extra forms")
     ap.add_argument("--scatter-lds", type=int, default=49152, help="LDS bytes of the scattering kernel with --profile")

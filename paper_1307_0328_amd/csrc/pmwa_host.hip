@@ -664,17 +664,17 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         if (h->opts.scatter_lds == 0 && ndom >= 2LL * std::max(prop.multiProcessorCount, 1)) {
             lds = std::min<size_t>(lds, 80 * 1024);
             // when no chain's typical domain fits even then, every domain takes
-            // the HBM store: keep 32 KB, so that five domains share a CU (more
-            // wavefronts hide more of the store's latency, while the full HBM
-            // form's many more per CU thrash the caches; measured on 2048^2
-            // with 32x32 sites x beta*t 4 domains: 32 KB 36.5 ms, 80 KB 40.7,
-            // 16 KB 42.0, the 6 KB HBM form 46.2)
+            // the HBM store: a third of the CU's LDS, so that three domains
+            // share a CU and each keeps its owner stamps (one per node pair) in
+            // LDS.  Measured on 2048^2 with 32x32 sites x beta*t 4 domains
+            // (about 18k nodes): 52 KB 30.3 ms; 56-80 KB (two per CU) 35.4;
+            // 48 KB (stamps in HBM) 36.4; 16 KB 42.0; the 6 KB HBM form 46.2.
             bool any_fits = false;
             for (auto& hc : h->ch) {
                 const double typ = hc.d.nloc * (mean_events(hc.p, hc.rho_max) * 0.5 + 2.0);
                 if ((double)fixed_al + 12.0 * typ + 256.0 <= (double)lds) any_fits = true;
             }
-            if (!any_fits) lds = std::max<size_t>(fixed_al + 64, 32 * 1024);
+            if (!any_fits) lds = std::max<size_t>(fixed_al + 64, (lds_max / 3) & ~(size_t)255);
         }
         lds = std::min(lds, lds_max);
         lds = std::max(lds, fixed_al + 64);

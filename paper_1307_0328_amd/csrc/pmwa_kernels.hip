@@ -619,7 +619,9 @@ struct NodeAll {
 struct HbmStore {
     uint4* nd;
     uint32_t* wl;    // worm list
-    uint32_t* own;
+    uint32_t* own;   // per-node scratch in HBM (rank tables, estimator intervals; stamps when sh = 0)
+    uint32_t* stp;   // owner stamps: own (one per node, sh = 0), or in the block's LDS, one per
+    int sh;          // node pair (sh = 1; sharing can only end a window early, as in LDS)
     static constexpr bool in_lds = false;
     PMWA_DEV NodeAll all(uint32_t i) const
     {
@@ -641,8 +643,9 @@ struct HbmStore {
     PMWA_DEV void put_fl(uint32_t i, int32_t, uint32_t f, uint32_t px) { nd[i].w = (px << 8) | f; }
     PMWA_DEV void set_nx(uint32_t i, uint32_t v) { nd[i].y = v; }
     PMWA_DEV void set_pv(uint32_t i, uint32_t v) { nd[i].z = v; }
-    PMWA_DEV uint32_t* stamp(uint32_t i) { return own + i; }
-    PMWA_DEV static int stamps(int nn) { return nn; }
+    PMWA_DEV uint32_t* stamp(uint32_t i) { return stp + (i >> sh); }
+    PMWA_DEV int stamps(int nn) const { return (nn + sh) >> sh; }
+    PMWA_DEV uint32_t* stamp_base() { return stp; }
 };
 
 // Node store in LDS (the LDS form), 12 bytes a node: one 32-bit word
@@ -685,7 +688,8 @@ struct LdsStore {
     PMWA_DEV void set_nx(uint32_t i, uint32_t v) { nxt[i] = (uint16_t)v; }
     PMWA_DEV void set_pv(uint32_t i, uint32_t v) { prv[i] = (uint16_t)v; }
     PMWA_DEV uint32_t* stamp(uint32_t i) { return own + (i >> 1); }
-    PMWA_DEV static int stamps(int nn) { return (nn + 1) >> 1; }
+    PMWA_DEV int stamps(int nn) const { return (nn + 1) >> 1; }
+    PMWA_DEV uint32_t* stamp_base() { return own; }
 };
 
 // floor(w * n / 2^64) for n < 2^32, exact
@@ -763,7 +767,7 @@ PMWA_DEV long long scatter_windows(Store& A, uint64_t* __restrict__ ring, int NN
             filled += 128u;
         }
         if (++wid == (1u << 23)) {
-            for (int i = lane; i < Store::stamps(NN); i += 64) A.own[i] = 0u;
+            for (int i = lane; i < A.stamps(NN); i += 64) A.stamp_base()[i] = 0u;
             wid = 1;
         }
         wave_order<Store>();
@@ -1094,7 +1098,7 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     if (__any(P.flags[chain] != 0)) return;
 
     // 4. N_cycle cycles, worms in list order, evaluated in windows
-    for (int i = lane; i < NE + 2 * nloc; i += 64) own[i] = 0u;
+    for (int i = lane; i < A.stamps(NE + 2 * nloc); i += 64) A.stamp_base()[i] = 0u;
     __syncthreads();
     const long long windows = scatter_windows(A, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
                                               (uint32_t)D, sthr, &P.flags[chain]);
@@ -1544,6 +1548,18 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     A.nd = P.s_nd + b;
     A.wl = P.s_wl + b;
     A.own = P.s_own + b;
+    A.stp = A.own;
+    A.sh = 0;
+    if constexpr (!HBM_ONLY) {
+        // the owner stamps, the store's most frequent random accesses, stay
+        // in the block's LDS when one per node pair fits there
+        const size_t fixed = 768 * sizeof(uint64_t) + (size_t)(2 * nloc + 1) * sizeof(int);
+        const size_t fixed_al = (fixed + 15) & ~(size_t)15;
+        if ((size_t)P.lds_bytes >= fixed_al + (size_t)((NN + 1) >> 1) * sizeof(uint32_t)) {
+            A.stp = reinterpret_cast<uint32_t*>(smem + fixed_al);
+            A.sh = 1;
+        }
+    }
     scatter_domain(P, C, bt.x, D, A, ring, off, cnt, sthr, sE, NE);
 }
 template __global__ void k_scatter<false>(Pools, const int2* __restrict__);

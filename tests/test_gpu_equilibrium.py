@@ -81,14 +81,19 @@ def test_single_64_500_sweeps(graph):
         run_against(sim, 0, g, f"single_64 graph={graph}")
 
 
-def test_large_domain_shape_300_sweeps():
-    """The 2048^2 workload's domains (32x32 sites x beta*t 4, scattering
-    nodes in HBM) on a 256x256 lattice, 300 sweeps from the empty state."""
+@pytest.mark.parametrize("form", ["auto", "lds32k", "hbm_only"])
+def test_large_domain_shape_300_sweeps(form):
+    """The 2048^2 workload's domains (32x32 sites x beta*t 4) on a 256x256
+    lattice, 300 sweeps from the empty state, in three forms of the
+    scattering store: auto (nodes in HBM once they outgrow the LDS, owner
+    stamps in LDS), 32 KB of LDS (nodes and stamps in HBM at equilibrium),
+    and the HBM form (everything in HBM from the first sweep)."""
     from paper_1307_0328_amd import pmwa as P
     g = load("l256_dom32x32x4")
-    say("[equilibrium] 256x256, 8x8x4 domains: 300 sweeps")
-    with P.Sim(P.make_params(**g["params"]), series_cap=1024) as sim:
-        run_against(sim, 0, g, "l256_dom32x32x4")
+    kw = {"auto": {}, "lds32k": dict(scatter_lds=32768), "hbm_only": dict(scatter_mode=2)}[form]
+    say(f"[equilibrium] 256x256, 8x8x4 domains, {form}: 300 sweeps")
+    with P.Sim(P.make_params(**g["params"]), series_cap=1024, **kw) as sim:
+        run_against(sim, 0, g, f"l256_dom32x32x4 {form}")
 
 
 def test_batched_256_largest_chains_500_sweeps():
