@@ -951,8 +951,9 @@ PMWA_DEV int wave_excl_scan(int v, int& total)
 
 PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D,
                              HbmStore A, uint64_t* __restrict__ ring,
-                             const int* __restrict__ off, const int* __restrict__ cnt,
-                             const uint64_t* __restrict__ sthr, const double* __restrict__ sE, int NE)
+                             int* __restrict__ off, int* __restrict__ cnt,
+                             const uint64_t* __restrict__ sthr, const double* __restrict__ sE, int NE,
+                             bool restore_oc)
 {
     const int lane = (int)threadIdx.x;
     const int k = D / C.ndsp, dsp = D - k * C.ndsp;
@@ -1102,6 +1103,25 @@ PMWA_DEV void scatter_domain(const Pools& P, const ChainDev& C, int chain, int D
     __syncthreads();
     const long long windows = scatter_windows(A, ring, NE + 2 * nloc, nw, C, (uint32_t)P.sweep[chain],
                                               (uint32_t)D, sthr, &P.flags[chain]);
+    if (restore_oc) {
+        // the stamps took the LDS of the per-site counts and offsets: the
+        // counts are read again (unchanged until the write-back below) and
+        // scanned again
+        __syncthreads();
+        for (int s = lane; s < nloc; s += 64) cnt[s] = P.cnt[C.cnt_off + unit_su(C, k, dsp, s)];
+        __syncthreads();
+        int carry = 0;
+        for (int base = 0; base < nloc; base += 64) {
+            const int s = base + lane;
+            const int v = s < nloc ? cnt[s] : 0;
+            int tot;
+            const int ex_ = wave_excl_scan(v, tot);
+            if (s < nloc) off[s] = carry + ex_;
+            carry += tot;
+        }
+        if (lane == 0) off[nloc] = carry;
+        __syncthreads();
+    }
 
     // 5. measurement (Step 6) and write-back.  One lane per site follows the
     //    site's node list and writes the events back; the length and worm
@@ -1550,17 +1570,20 @@ __global__ void __launch_bounds__(64) k_scatter(Pools P, const int2* __restrict_
     A.own = P.s_own + b;
     A.stp = A.own;
     A.sh = 0;
+    bool restore_oc = false;
     if constexpr (!HBM_ONLY) {
         // the owner stamps, the store's most frequent random accesses, stay
-        // in the block's LDS when one per node pair fits there
-        const size_t fixed = 768 * sizeof(uint64_t) + (size_t)(2 * nloc + 1) * sizeof(int);
-        const size_t fixed_al = (fixed + 15) & ~(size_t)15;
-        if ((size_t)P.lds_bytes >= fixed_al + (size_t)((NN + 1) >> 1) * sizeof(uint32_t)) {
-            A.stp = reinterpret_cast<uint32_t*>(smem + fixed_al);
+        // in the block's LDS when one per node pair fits there: after the
+        // exit thresholds and the ring, over the per-site counts and offsets,
+        // which the windows do not read (they are rebuilt after them)
+        const size_t base = 768 * sizeof(uint64_t);
+        if ((size_t)P.lds_bytes >= base + (size_t)((NN + 1) >> 1) * sizeof(uint32_t)) {
+            A.stp = reinterpret_cast<uint32_t*>(smem + base);
             A.sh = 1;
+            restore_oc = true;
         }
     }
-    scatter_domain(P, C, bt.x, D, A, ring, off, cnt, sthr, sE, NE);
+    scatter_domain(P, C, bt.x, D, A, ring, off, cnt, sthr, sE, NE, restore_oc);
 }
 template __global__ void k_scatter<false>(Pools, const int2* __restrict__);
 template __global__ void k_scatter<true>(Pools, const int2* __restrict__);
