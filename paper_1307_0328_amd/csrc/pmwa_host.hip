@@ -365,6 +365,45 @@ static void block_table(const std::vector<HostChain>& ch, const std::vector<int>
     }
 }
 
+// Cross bonds of direction d (0: x, 1: y) for the spatial-boundary kernel, one
+// block each.  The bonds along one domain edge in one slab are adjacent in
+// the table (x-crossing bonds along y, y-crossing bonds along x), and runs of
+// 16 entries go to one XCD (workgroups are dealt round-robin over the 8
+// XCDs), so that blocks reading the same cache lines of the site-interleaved
+// event arrays share an L2.  The units are independent, so the order changes
+// no result.  Entries past the end carry an out-of-range unit: their block
+// returns at once.
+static void spatial_table(const std::vector<HostChain>& ch, const std::vector<int>& chains, int d,
+                          std::vector<int2>& out)
+{
+    std::vector<int2> items;
+    for (int c : chains) {
+        const HostChain& hc = ch[c];
+        const int64_t n = d == 0 ? hc.n_bsx : hc.n_bsy;
+        if (n <= 0) continue;
+        const int nt = hc.p.dom_tau;
+        const int outer = d == 0 ? hc.p.dom_x : hc.p.dom_y;   // the domain column (row)
+        const int inner = d == 0 ? hc.p.Ly : hc.p.Lx;         // position along the edge
+        for (int o = 0; o < outer; o++)
+            for (int k = 0; k < nt; k++)
+                for (int i = 0; i < inner; i++) {
+                    const int64_t u = d == 0 ? (int64_t)i * hc.p.dom_x + o : (int64_t)o * hc.p.Lx + i;
+                    items.push_back(make_int2(c, (int)(u * nt + k)));
+                }
+    }
+    out.clear();
+    if (items.empty()) return;
+    constexpr int64_t XCD = 8, RUN = 16;
+    const int64_t n = (int64_t)items.size();
+    const int64_t nb = (n + XCD * RUN - 1) / (XCD * RUN) * (XCD * RUN);
+    out.assign((size_t)nb, make_int2(items[0].x, 0x7FFFFFFF));
+    for (int64_t b = 0; b < nb; b++) {
+        const int64_t x = b % XCD, i = b / XCD;
+        const int64_t item = ((i / RUN) * XCD + x) * RUN + (i % RUN);
+        if (item < n) out[(size_t)b] = items[(size_t)item];
+    }
+}
+
 // expected work of one scattering domain of a chain: its expected nodes
 // (4 (rho_max + t) beta per site and slab, the vertex ends) and attempts
 // (N_cycle times the worms, ~ 4 C beta per site and slab)
@@ -664,17 +703,18 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         if (h->opts.scatter_lds == 0 && ndom >= 2LL * std::max(prop.multiProcessorCount, 1)) {
             lds = std::min<size_t>(lds, 80 * 1024);
             // when no chain's typical domain fits even then, every domain takes
-            // the HBM store: a third of the CU's LDS, so that three domains
-            // share a CU and each keeps its owner stamps (one per node pair) in
-            // LDS.  Measured on 2048^2 with 32x32 sites x beta*t 4 domains
-            // (about 18k nodes): 52 KB 30.3 ms; 56-80 KB (two per CU) 35.4;
-            // 48 KB (stamps in HBM) 36.4; 16 KB 42.0; the 6 KB HBM form 46.2.
+            // the HBM store: a third of the CU's LDS, rounded down to 2 KB so
+            // that three domains share a CU whatever the allocation granule,
+            // each keeping its owner stamps (one per node pair) in LDS.
+            // Measured on 2048^2 with 32x32 sites x beta*t 4 domains (18-20k
+            // nodes): 52 KB 30.3 ms; 56-80 KB (two per CU) 35.4; 48 KB with the
+            // stamps in HBM 36.4; 16 KB 42.0; the 6 KB HBM form 46.2.
             bool any_fits = false;
             for (auto& hc : h->ch) {
                 const double typ = hc.d.nloc * (mean_events(hc.p, hc.rho_max) * 0.5 + 2.0);
                 if ((double)fixed_al + 12.0 * typ + 256.0 <= (double)lds) any_fits = true;
             }
-            if (!any_fits) lds = std::max<size_t>(fixed_al + 64, (lds_max / 3) & ~(size_t)255);
+            if (!any_fits) lds = std::max<size_t>(fixed_al + 64, (lds_max / 3) & ~(size_t)2047);
         }
         lds = std::min(lds, lds_max);
         lds = std::max(lds, fixed_al + 64);
@@ -804,8 +844,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
             block_table(h->ch, L.chains, 64, &HostChain::n_units_r, t); if (!r2) r2 = upload_table(t, &L.r, &L.nr);
             block_table(h->ch, heavy, 1, &HostChain::n_dom, t); if (!r2) r2 = upload_table(t, &L.s, &L.ns);
             block_table(h->ch, L.chains, h->bt_lanes, &HostChain::n_bt, t); if (!r2) r2 = upload_table(t, &L.bt, &L.nbt);
-            block_table(h->ch, L.chains, 1, &HostChain::n_bsx, t); if (!r2) r2 = upload_table(t, &L.bsx, &L.nbsx);
-            block_table(h->ch, L.chains, 1, &HostChain::n_bsy, t); if (!r2) r2 = upload_table(t, &L.bsy, &L.nbsy);
+            spatial_table(h->ch, L.chains, 0, t); if (!r2) r2 = upload_table(t, &L.bsx, &L.nbsx);
+            spatial_table(h->ch, L.chains, 1, t); if (!r2) r2 = upload_table(t, &L.bsy, &L.nbsy);
             if (h->regen_wave) {
                 block_table(h->ch, L.chains, 1, &HostChain::n_units_r, t);
                 if (!r2) r2 = upload_table(t, &L.rw, &L.nrw);
