@@ -495,12 +495,10 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    __shared__ double sE[1024];
+    // the expm1 table is read from L2 (12 KB of LDS per block instead of 20
+    // lets more lane groups share a CU)
+    const double* sE = C.F;
     __shared__ int32_t s_off[NWL * 64];
-    // (unrolled, so that the loads are in flight together)
-#pragma unroll
-    for (int q = 0; q < 16; q++) sE[q * 64 + (int)threadIdx.x] = C.F[q * 64 + (int)threadIdx.x];
-    __syncthreads();
     if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
     int32_t* off = s_off + threadIdx.x;
@@ -1653,16 +1651,9 @@ __global__ void __launch_bounds__(LANES) k_btemporal(Pools P, const int2* __rest
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    // full wavefronts copy the expm1 table to LDS (unrolled, the loads in
-    // flight together); 16-lane groups, used where 64-lane ones would leave
-    // most CUs idle, read it from L2 (a copy per small group costs more)
+    // the expm1 table is read from L2 (an LDS copy would take 8 KB more per
+    // group and leave fewer groups per CU)
     const double* sE = C.F;
-    if constexpr (LANES == 64) {
-        __shared__ double sEl[1024];
-#pragma unroll
-        for (int q = 0; q < 16; q++) sEl[q * 64 + (int)threadIdx.x] = C.F[q * 64 + (int)threadIdx.x];
-        sE = sEl;
-    }
     __shared__ int32_t s_off[2 * NWL * LANES];
     // the boundary ticks in LDS and the chain fields the loop reads in
     // registers: the loop's event stores could alias fields of C, which
