@@ -90,8 +90,12 @@ def traffic_from_profile(workload, kernel, hash_now, form=None):
         return None, None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_hash") != hash_now or (form is not None and rec.get("form") != form):
+    if rec.get("kernel_source_hash") != hash_now:
         return None, os.path.relpath(path, ROOT)
+    if form is not None:
+        # one record per launch form that was profiled
+        entry = rec.get("by_form", {}).get(form)
+        return (entry.get("bytes_per_launch") if entry else None), os.path.relpath(path, ROOT)
     return rec.get("bytes_per_launch"), os.path.relpath(path, ROOT)
 
 

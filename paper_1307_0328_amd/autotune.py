@@ -212,7 +212,7 @@ class Tuner:
         return best, table
 
     def tune_tiling(self, chains: list[dict], slab_options=(None, 8.0, 4.0),
-                    lds_options=(28672, 36864, 45056, 53248)):
+                    lds_options=(24576, 28672, 36864, 45056)):
         """Temporal tiling and scattering LDS bytes for a whole batch, spatial
         grids as given: every chain gets ceil(beta*t / slab) temporal domains
         (slab None: the chains' own), and each (slab, LDS bytes) pair is timed
