@@ -238,6 +238,27 @@ def worms_general_leg(P, W, reps):
                                        "per worm 4 * types * d (sequence weights, two passes)"}}
 
 
+def sweep_traffic(workload, hash_now, form, nv_per, ms_step):
+    """HBM bytes of a whole sweep from the committed counter summary (every
+    kernel's bytes per launch, the spatial kernel twice), per vertex and as
+    GB/s over the sweep; None unless the summary matches the sources and the
+    launch form."""
+    path = os.path.join(ROOT, "profiles", f"k_scatter_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != hash_now:
+        return None
+    entry = rec.get("by_form", {}).get(form) if form is not None else rec
+    if not entry or "per_kernel" not in entry:
+        return None
+    total = sum(v["bytes"] * (2 if "bspatial" in k else 1) for k, v in entry["per_kernel"].items())
+    return {"bytes_per_sweep": total, "bytes_per_vertex": total / nv_per,
+            "GBps": total / (ms_step * 1e-3) / 1e9, "frac_of_peak": total / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "source": os.path.relpath(path, ROOT)}
+
+
 def batched_form(slab, lds):
     """Launch form of the 256-chain batch, as the profile summaries name it."""
     return f"temporal slabs of at most beta*t {slab}, scatter_lds {lds}" if slab else f"one slab, scatter_lds {lds}"
@@ -441,6 +462,8 @@ def main():
             "autotune_table": [{"slab_beta_t": f[0], "scatter_lds": f[1], "value": v} for f, v in table],
             "kernel_ms_per_sweep": kern,
             "algorithmic_GBps_per_sweep": 32.0 * nv_per / (ms_step * 1e-3) / 1e9,
+            "measured_traffic_per_sweep": sweep_traffic("batched_256", hash_now, batched_form(slab, lds),
+                                                         nv_per, ms_step),
             "worm_scatterings_per_s": head["attempts"] / head["seconds"],
             "vertices_per_sweep": nv_per,
             "worms_per_sweep": nw_per,
@@ -495,6 +518,8 @@ def main():
             "thermalisation_sweeps": args.large_therm, "sweeps_timed": args.large_sweeps,
             "vertices_per_sweep": g2["nv"] / args.large_sweeps, "worms_per_sweep": g2["nw"] / args.large_sweeps,
             "algorithmic_GBps": (32.0 * g2["nv"] + 16.0 * g2["nw"]) / args.large_sweeps / (msb * 1e-3) / 1e9,
+            "measured_traffic_per_sweep": sweep_traffic("large_2048", hash_now, None, g2["nv"] / args.large_sweeps,
+                                                        msb),
             "roofline": roofline(g2, domk, "large_2048", hash_now),
             "kernel_ms_per_sweep_with_events": kb,
             "Q_imp_per_site": obs["Q_imp"], "density": obs["density"],
