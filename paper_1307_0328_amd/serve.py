@@ -9,6 +9,14 @@ device.  A job's result depends only on its own parameters (the random
 streams are keyed by its seed and chain id), never on its slot or on the
 other jobs.
 
+Checkpoints and capacity regrowth: every `checkpoint_every` scheduling
+points the loop copies each running job's canonical state (and the records
+so far) to the host.  A job whose chain overflows its event capacity can be
+re-admitted (`regrow` times at most) to a pool of slots with twice the
+capacity, restarting from its last checkpoint: the random streams are keyed
+by the sweep, so the replayed sweeps are the ones a large enough capacity
+would have run, and the result equals that run's bit for bit.
+
 Everything here is scheduling; the sweeps run in libpmwa.so.
 """
 from __future__ import annotations
@@ -35,6 +43,11 @@ class Job:
     state: dict | None = None
     nv: int = 0
     error: int = 0                   # 0, or the library's error code for this job
+    pool: int = 0                    # capacity pool: event capacity event_cap * 2^pool
+    regrows: int = 0
+    resumes: int = 0                 # admissions that restarted from a checkpoint
+    ckpt: dict | None = None         # canonical state at the last checkpoint (with its sweep)
+    rows_done: list = field(default_factory=list)   # records up to the checkpoint
 
 
 def footprint_bytes(params: dict, event_cap: int) -> int:
@@ -46,6 +59,14 @@ def footprint_bytes(params: dict, event_cap: int) -> int:
 
 
 @dataclass
+class _Pool:
+    h: object
+    event_cap: int
+    free: set
+    cap_bytes: list
+
+
+@dataclass
 class Server:
     shapes: list                     # pmwa_params-like dicts, one per slot
     event_cap: int = 256
@@ -53,56 +74,104 @@ class Server:
     use_graph: bool = True
     keep_state: bool = False
     series_cap: int = 8192
+    regrow: int = 0                  # times a job's event capacity may double after an overflow
+    checkpoint_every: int = 0        # scheduling points between checkpoints (0: none, a regrown job restarts)
     jobs_done: list = field(default_factory=list)
     backend: object = None           # the pmwa binding (a stand-in in host-only tests)
 
     def __post_init__(self):
-        B = self.backend if self.backend is not None else P
-        self.B = B
-        o = B.pmwa_opts()
-        o.event_cap = self.event_cap
-        o.series_cap = self.series_cap
-        o.use_graph = 1 if self.use_graph else 0
-        self.h = B.pmwa_create_slots([B.make_params(**s) for s in self.shapes], o)
-        self.cap_bytes = [footprint_bytes(s, self.event_cap) for s in self.shapes]
-        self.free = set(range(len(self.shapes)))
+        self.B = self.backend if self.backend is not None else P
+        self.pools: list[_Pool] = []
+        self._pool(0)
+        self.h = self.pools[0].h
+
+    @property
+    def free(self):
+        return self.pools[0].free
+
+    def _pool(self, level: int) -> _Pool:
+        """The slots with event capacity event_cap * 2^level (created on
+        first use, with the same shapes)."""
+        B = self.B
+        while len(self.pools) <= level:
+            cap = self.event_cap << len(self.pools)
+            o = B.pmwa_opts()
+            o.event_cap = cap
+            o.series_cap = self.series_cap
+            o.use_graph = 1 if self.use_graph else 0
+            h = B.pmwa_create_slots([B.make_params(**s) for s in self.shapes], o)
+            self.pools.append(_Pool(h, cap, set(range(len(self.shapes))),
+                                    [footprint_bytes(s, cap) for s in self.shapes]))
+        return self.pools[level]
 
     def close(self):
-        if self.h:
-            self.B.pmwa_destroy(self.h)
-            self.h = None
+        for pl in self.pools:
+            if pl.h:
+                self.B.pmwa_destroy(pl.h)
+                pl.h = None
+        self.h = None
 
     def _fits_some_slot(self, job: Job) -> bool:
         p = self.B.make_params(**job.params)
         return any(self.B.pmwa_slot_fits(self.h, s, p) for s in range(len(self.shapes)))
 
+    def _rows(self, job: Job, rows):
+        parts = job.rows_done + ([rows] if rows is not None else [])
+        return np.concatenate(parts) if parts else np.zeros(0, dtype=P.OBS_DTYPE)
+
     def _finish(self, job: Job, t0: float, error: int = 0):
         B = self.B
         job.error = error
         if job.slot >= 0:
+            pl = self.pools[job.pool]
             if error == 0:
-                job.rows = B.pmwa_measure(self.h, job.slot)
+                job.rows = self._rows(job, B.pmwa_measure(pl.h, job.slot))
                 if self.keep_state:
                     pr = job.params
-                    job.state = B.pmwa_get_state(self.h, job.slot, pr["Lx"] * pr["Ly"], pr["dom_tau"])
+                    job.state = B.pmwa_get_state(pl.h, job.slot, pr["Lx"] * pr["Ly"], pr["dom_tau"])
                 job.nv = int(job.rows["nv"].sum())
-            B.pmwa_slot_release(self.h, job.slot)
-            self.free.add(job.slot)
+            B.pmwa_slot_release(pl.h, job.slot)
+            pl.free.add(job.slot)
+            job.slot = -1
         job.finished = time.perf_counter() - t0
         self.jobs_done.append(job)
 
+    def _checkpoint(self, job: Job):
+        B = self.B
+        pl = self.pools[job.pool]
+        pr = job.params
+        job.rows_done.append(B.pmwa_measure(pl.h, job.slot))
+        job.ckpt = B.pmwa_get_state(pl.h, job.slot, pr["Lx"] * pr["Ly"], pr["dom_tau"])
+
+    def _regrow(self, job: Job):
+        """Back to the queue with twice the event capacity, from the last
+        checkpoint (the records after it are dropped with the slot)."""
+        pl = self.pools[job.pool]
+        self.B.pmwa_slot_release(pl.h, job.slot)
+        pl.free.add(job.slot)
+        job.slot = -1
+        job.pool += 1
+        job.regrows += 1
+        if job.ckpt is None:
+            job.rows_done = []
+
     def _admit(self, job: Job) -> bool:
-        need = footprint_bytes(job.params, self.event_cap)
-        for slot in sorted(self.free, key=lambda s: self.cap_bytes[s]):
-            if self.cap_bytes[slot] < need:
+        B = self.B
+        pl = self._pool(job.pool)
+        need = footprint_bytes(job.params, pl.event_cap)
+        for slot in sorted(pl.free, key=lambda s: pl.cap_bytes[s]):
+            if pl.cap_bytes[slot] < need:
                 continue
-            rc = self.B.lib().pmwa_slot_load(self.h, slot, self.B.make_params(**job.params), job.sweeps)
+            rc = B.lib().pmwa_slot_load(pl.h, slot, B.make_params(**job.params), job.sweeps)
             if rc == 0:
-                self.free.discard(slot)
+                pl.free.discard(slot)
                 job.slot = slot
+                if job.ckpt is not None:
+                    B.pmwa_set_state(pl.h, slot, job.ckpt)
+                    job.resumes += 1
                 return True
-            if rc != self.B.PMWA_EINVAL:
-                raise self.B.PmwaError(rc, "pmwa_slot_load")
+            if rc != B.PMWA_EINVAL:
+                raise B.PmwaError(rc, "pmwa_slot_load")
         return False
 
     def run(self, jobs: list[Job], realtime: bool = True, max_seconds: float = 600.0) -> dict:
@@ -111,15 +180,18 @@ class Server:
 
         A job that no slot can hold is rejected on arrival (error
         PMWA_EINVAL).  A job whose chain raises a device error (a capacity
-        overflow, a sampler or state error) stops advancing; it is finished
-        with that error code at the next scheduling point and its slot is
-        released.  Neither stops the other jobs."""
+        overflow, a sampler or state error) stops advancing; at the next
+        scheduling point it is re-admitted with twice the event capacity
+        if it overflowed and may still regrow, and is otherwise finished
+        with that error code; its slot is released.  Neither stops the
+        other jobs."""
         B = self.B
         pending = deque(sorted(jobs, key=lambda j: j.arrival))
         waiting: deque[Job] = deque()
-        running: dict[int, Job] = {}
+        running: dict[tuple, Job] = {}
         t0 = time.perf_counter()
         busy = 0.0
+        points = 0
         while pending or waiting or running:
             now = time.perf_counter() - t0
             if now > max_seconds:
@@ -133,8 +205,9 @@ class Server:
             for job in list(waiting):
                 if self._admit(job):
                     waiting.remove(job)
-                    job.admitted = time.perf_counter() - t0
-                    running[job.slot] = job
+                    if job.admitted < 0:
+                        job.admitted = time.perf_counter() - t0
+                    running[(job.pool, job.slot)] = job
             if not running:
                 if waiting:
                     # every slot is free and none takes these jobs
@@ -145,22 +218,33 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - now)))
                 continue
             tb = time.perf_counter()
-            B.pmwa_sweep(self.h, self.chunk)
-            for slot, job in list(running.items()):
-                err = B.pmwa_chain_status(self.h, slot)
+            for lv in sorted({k[0] for k in running}):
+                B.pmwa_sweep(self.pools[lv].h, self.chunk)
+            points += 1
+            for key, job in list(running.items()):
+                pl = self.pools[job.pool]
+                err = B.pmwa_chain_status(pl.h, job.slot)
                 if err != 0:
-                    del running[slot]
-                    self._finish(job, t0, error=err)
+                    del running[key]
+                    if err == B.PMWA_EOVERFLOW and job.regrows < self.regrow:
+                        self._regrow(job)
+                        waiting.appendleft(job)
+                    else:
+                        self._finish(job, t0, error=err)
                     continue
-                if B.pmwa_slot_progress(self.h, slot) >= job.sweeps:
-                    del running[slot]
+                if B.pmwa_slot_progress(pl.h, job.slot) >= job.sweeps:
+                    del running[key]
                     self._finish(job, t0)
+                elif self.checkpoint_every and points % self.checkpoint_every == 0:
+                    self._checkpoint(job)
             busy += time.perf_counter() - tb
         wall = time.perf_counter() - t0
         ok = [j for j in jobs if j.error == 0]
         lat = np.array([j.finished - (j.arrival if realtime else 0.0) for j in ok]) if ok else np.zeros(1)
         nv = sum(j.nv for j in ok)
-        return dict(jobs=len(jobs), failed=len(jobs) - len(ok), wall_s=wall, busy_s=busy,
+        return dict(jobs=len(jobs), failed=len(jobs) - len(ok), regrown=sum(j.regrows for j in jobs),
+                    resumed=sum(j.resumes for j in jobs),
+                    wall_s=wall, busy_s=busy,
                     p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
                     vertex_updates=nv, vertex_updates_per_s=nv / wall)
 

@@ -59,3 +59,79 @@ def test_slot_rejects_a_chain_that_does_not_fit():
         assert len(P.pmwa_measure(h, 0)) == 5
     finally:
         P.pmwa_destroy(h)
+
+
+def test_overflow_regrow_replay_equals_a_large_capacity_run():
+    """A job whose event capacity overflows is re-admitted with twice the
+    capacity from its last checkpoint; its final state and every record
+    equal the same job run alone with a large capacity."""
+    from paper_1307_0328_amd import pmwa as P
+    from paper_1307_0328_amd import serve as S
+    from paper_1307_0328_amd import workloads as W
+    shape = W.serving_slot_shape(16, 8.0)
+    params = dict(shape, mu=0.3, seed=21, chain_id=5)
+    other = dict(shape, mu=-0.5, seed=22, chain_id=6)
+    jobs = [S.Job(0, 0.0, 60, params), S.Job(1, 0.0, 45, other)]
+    print("[serving] regrowth: event capacity 24, up to 3 doublings", flush=True)
+    srv = S.Server([shape] * 2, event_cap=24, chunk=5, keep_state=True, regrow=3, checkpoint_every=1)
+    try:
+        rep = srv.run(jobs, realtime=False, max_seconds=120)
+    finally:
+        srv.close()
+    assert rep["failed"] == 0, [j.error for j in jobs]
+    print(f"[serving] regrown {rep['regrown']}, resumed from a checkpoint {rep['resumed']}", flush=True)
+    assert rep["regrown"] >= 1
+    for j in jobs:
+        with P.Sim(P.make_params(**j.params), event_cap=256) as sim:
+            sim.sweep(j.sweeps)
+            alone = sim.get_state()
+            rows = sim.measure()
+        for k in ("bstate", "counts", "ticks", "infos"):
+            np.testing.assert_array_equal(j.state[k], alone[k], err_msg=f"job {j.jid} {k}")
+        assert len(j.rows) == j.sweeps
+        for f in ("nv", "nkink", "nw", "occ2", "nn2", "qimp"):
+            np.testing.assert_array_equal(j.rows[f], rows[f], err_msg=f"job {j.jid} {f}")
+
+
+def test_resume_from_a_checkpoint_in_another_pool():
+    """The path a regrown job takes after a checkpoint: a job runs 12 sweeps
+    in a slot, its state and records go to the host, and it continues in a
+    slot of another handle with a larger event capacity (pmwa_slot_load,
+    then pmwa_set_state with the checkpoint's sweep); the records and the
+    final state equal the job run alone."""
+    from paper_1307_0328_amd import pmwa as P
+    from paper_1307_0328_amd import workloads as W
+    shape = W.serving_slot_shape(16, 8.0)
+    params = dict(shape, mu=0.3, seed=31, chain_id=9)
+    n = params["Lx"] * params["Ly"]
+    o1, o2 = P.pmwa_opts(), P.pmwa_opts()
+    o1.event_cap, o2.event_cap = 128, 256
+    h1 = P.pmwa_create_slots([P.make_params(**shape)], o1)
+    h2 = P.pmwa_create_slots([P.make_params(**shape)] * 2, o2)
+    try:
+        P.pmwa_slot_load(h1, 0, P.make_params(**params), 30)
+        P.pmwa_sweep(h1, 12)
+        assert P.pmwa_chain_status(h1, 0) == 0 and P.pmwa_slot_progress(h1, 0) == 12
+        rows1 = P.pmwa_measure(h1, 0)
+        ckpt = P.pmwa_get_state(h1, 0, n, params["dom_tau"])
+        assert ckpt["sweep"] == 12
+        P.pmwa_slot_release(h1, 0)
+        P.pmwa_slot_load(h2, 1, P.make_params(**params), 30)
+        P.pmwa_set_state(h2, 1, ckpt)
+        P.pmwa_sweep(h2, 25)
+        assert P.pmwa_chain_status(h2, 1) == 0 and P.pmwa_slot_progress(h2, 1) == 30
+        rows2 = P.pmwa_measure(h2, 1)
+        final = P.pmwa_get_state(h2, 1, n, params["dom_tau"])
+    finally:
+        P.pmwa_destroy(h1)
+        P.pmwa_destroy(h2)
+    with P.Sim(P.make_params(**params), event_cap=256) as sim:
+        sim.sweep(30)
+        alone = sim.get_state()
+        rows = sim.measure()
+    for k in ("bstate", "counts", "ticks", "infos"):
+        np.testing.assert_array_equal(final[k], alone[k], err_msg=k)
+    both = np.concatenate([rows1, rows2])
+    assert len(both) == 30
+    for f in ("nv", "nkink", "nw", "occ2", "nn2", "qimp"):
+        np.testing.assert_array_equal(both[f], rows[f], err_msg=f)

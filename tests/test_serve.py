@@ -1,7 +1,9 @@
 """Scheduling of the serving loop on the host, with a stand-in for the
 library: a job that no slot holds is rejected on arrival, a job whose chain
 raises a device error is finished with that error and frees its slot, and
-the other jobs complete."""
+the other jobs complete; with regrowth, an overflowing job is re-admitted
+to a pool of twice the event capacity from its last checkpoint, and its
+records come out whole."""
 import types
 
 import numpy as np
@@ -11,15 +13,20 @@ from paper_1307_0328_amd import serve as S
 
 
 class FakeLib:
-    """Slots advance `chunk` sweeps per pmwa_sweep; a chain with mu == 9.0
-    raises an overflow after its first chunk; a chain larger than the slot
-    shape does not fit."""
+    """Slots advance `chunk` sweeps per pmwa_sweep of their handle; a chain
+    with mu == 9.0 raises an overflow at its sweep 25 unless its handle's
+    event capacity is at least 1024; a chain larger than the slot shape does
+    not fit.  A record's nv is its sweep number, so lost or repeated records
+    show."""
 
     def __init__(self, shapes):
         self.shapes = shapes
-        self.loaded = {}
+        self.caps = {}                # handle -> event capacity
+        self.loaded = {}              # (handle, slot) -> [mu, target]
         self.done = {}
+        self.read = {}
         self.flag = {}
+        self.loads = []
 
     def fits(self, slot, p):
         s = self.shapes[slot]
@@ -28,9 +35,11 @@ class FakeLib:
     def pmwa_slot_load(self, h, slot, p, target):
         if not self.fits(slot, p):
             return P.PMWA_EINVAL
-        self.loaded[slot] = (p.mu, target)
-        self.done[slot] = 0
-        self.flag[slot] = 0
+        self.loaded[(h, slot)] = (p.mu, target)
+        self.done[(h, slot)] = 0
+        self.read[(h, slot)] = 0
+        self.flag[(h, slot)] = 0
+        self.loads.append((self.caps[h], slot))
         return 0
 
 
@@ -41,35 +50,52 @@ def make_backend(shapes):
     B.PMWA_EOVERFLOW = P.PMWA_EOVERFLOW
     B.PmwaError = P.PmwaError
     B.pmwa_opts = P.pmwa_opts
+
+    def create(shapes_, o):
+        h = object()
+        fake.caps[h] = o.event_cap
+        return h
+
     B.make_params = P.make_params
-    B.pmwa_create_slots = lambda shapes_, o: object()
+    B.pmwa_create_slots = create
     B.pmwa_destroy = lambda h: None
     B.pmwa_slot_fits = lambda h, slot, p: fake.fits(slot, p)
     B.lib = lambda: fake
-    chunk = 10
 
     def sweep(h, n):
-        for slot, (mu, target) in fake.loaded.items():
-            if fake.flag.get(slot):
+        for (hh, slot), (mu, target) in fake.loaded.items():
+            key = (hh, slot)
+            if hh is not h or fake.flag.get(key):
                 continue
-            if mu == 9.0 and fake.done[slot] >= chunk:
-                fake.flag[slot] = P.PMWA_EOVERFLOW
+            end = min(target, fake.done[key] + n)
+            if mu == 9.0 and fake.caps[hh] < 1024 and end > 25:
+                fake.done[key] = 25
+                fake.flag[key] = P.PMWA_EOVERFLOW
                 continue
-            fake.done[slot] = min(target, fake.done[slot] + n)
+            fake.done[key] = end
 
     B.pmwa_sweep = sweep
-    B.pmwa_chain_status = lambda h, slot: fake.flag.get(slot, 0)
-    B.pmwa_slot_progress = lambda h, slot: fake.done[slot]
+    B.pmwa_chain_status = lambda h, slot: fake.flag.get((h, slot), 0)
+    B.pmwa_slot_progress = lambda h, slot: fake.done[(h, slot)]
 
     def measure(h, slot):
-        r = np.zeros(fake.done[slot], dtype=P.OBS_DTYPE)
-        r["nv"] = 5
+        key = (h, slot)
+        r = np.zeros(fake.done[key] - fake.read[key], dtype=P.OBS_DTYPE)
+        r["nv"] = np.arange(fake.read[key] + 1, fake.done[key] + 1)
+        fake.read[key] = fake.done[key]
         return r
 
     B.pmwa_measure = measure
+    B.pmwa_get_state = lambda h, slot, n, nt: {"sweep": fake.done[(h, slot)]}
+
+    def set_state(h, slot, st):
+        fake.done[(h, slot)] = st["sweep"]
+        fake.read[(h, slot)] = st["sweep"]
+
+    B.pmwa_set_state = set_state
 
     def release(h, slot):
-        del fake.loaded[slot]
+        del fake.loaded[(h, slot)]
 
     B.pmwa_slot_release = release
     return B, fake
@@ -94,5 +120,36 @@ def test_failed_and_unfit_jobs_do_not_block_the_others():
     for j in jobs:
         assert j.finished >= 0
         if j.error == 0:
-            assert len(j.rows) == j.sweeps and j.nv == 5 * j.sweeps
+            assert list(j.rows["nv"]) == list(range(1, j.sweeps + 1))
     assert not fake.loaded and srv.free == {0, 1}
+
+
+def test_overflow_regrows_from_the_last_checkpoint():
+    shapes = [dict(Lx=16, Ly=16, beta=8.0, dom_x=2, dom_y=2, dom_tau=1)] * 2
+    B, fake = make_backend([P.make_params(**s) for s in shapes])
+    srv = S.Server(shapes, event_cap=256, chunk=10, backend=B, regrow=3, checkpoint_every=1)
+    base = dict(beta=4.0, t=1.0, V=0.0, eta=0.05, dom_x=2, dom_y=2, dom_tau=1)
+    jobs = [S.Job(0, 0.0, 60, dict(base, Lx=16, Ly=16, mu=9.0)),     # overflows below 1024 events
+            S.Job(1, 0.0, 40, dict(base, Lx=16, Ly=16, mu=0.0))]
+    rep = srv.run(jobs, realtime=False, max_seconds=10.0)
+    assert rep["failed"] == 0 and rep["regrown"] == 2 and rep["resumed"] == 2
+    j0 = jobs[0]
+    assert j0.regrows == 2 and j0.pool == 2
+    # the records of every sweep exactly once, across the three pools
+    assert list(j0.rows["nv"]) == list(range(1, 61))
+    assert list(jobs[1].rows["nv"]) == list(range(1, 41))
+    # re-admitted with 512, then 1024 events; restarted from the checkpoint at sweep 20
+    assert [c for c, _ in fake.loads] == [256, 256, 512, 1024]
+    assert not fake.loaded
+
+
+def test_overflow_without_regrowth_fails():
+    shapes = [dict(Lx=16, Ly=16, beta=8.0, dom_x=2, dom_y=2, dom_tau=1)]
+    B, fake = make_backend([P.make_params(**s) for s in shapes])
+    srv = S.Server(shapes, event_cap=256, chunk=10, backend=B, regrow=1, checkpoint_every=0)
+    base = dict(beta=4.0, t=1.0, V=0.0, eta=0.05, dom_x=2, dom_y=2, dom_tau=1)
+    job = S.Job(0, 0.0, 60, dict(base, Lx=16, Ly=16, mu=9.0))
+    rep = srv.run([job], realtime=False, max_seconds=10.0)
+    # one regrowth (to 512) is not enough: the job fails after restarting from scratch
+    assert rep["failed"] == 1 and job.error == P.PMWA_EOVERFLOW and job.regrows == 1
+    assert [c for c, _ in fake.loads] == [256, 512]
