@@ -111,8 +111,9 @@ struct BsVert {
                              // bit6 next vertex on a is the bond's, bit7 on c
     uint32_t m4;             // choice index for (p1, p2) = (x & 1, x >> 1) at bits 4x
     uint32_t S, p12;         // chosen root pattern; actual lower-end occupations
-    int32_t cnt[4];          // worms drawn on each leg (0 for legs redrawn later)
+    uint8_t cnt[4];          // worms drawn on each leg, <= NWL (0 for legs redrawn later)
 };
+static_assert(NWL <= 255, "a leg's worm count is held in one byte");
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)

@@ -865,10 +865,10 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
             maxcap = std::max(maxcap, hc.d.cap);
             maxcapb = std::max(maxcapb, hc.d.capb);
         }
-        // A, B, A2, B2 and eight 16-bit arrays per event; per bond vertex its
-        // record and two indices; the worm-offset pool
+        // A, B and eight 16-bit arrays per event; per bond vertex its record
+        // and two indices; the worm-offset pool
         h->max_capb = maxcapb;
-        h->bs_lds = (size_t)maxcap * (4 * sizeof(uint2) + 8 * sizeof(int16_t)) +
+        h->bs_lds = (size_t)maxcap * (2 * sizeof(uint2) + 8 * sizeof(int16_t)) +
                     (size_t)maxcapb * (sizeof(BsVert) + 2 * sizeof(int)) + (size_t)RW_POOL * sizeof(int32_t) + 16;
         // the spatial update holds a cross bond's two site lists in LDS: a
         // chain with spatial domains needs its event capacity to fit

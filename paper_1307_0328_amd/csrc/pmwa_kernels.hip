@@ -1864,10 +1864,10 @@ PMWA_DEV int rebuild_positions(const uint2* A, int n, const int16_t* pv, const i
     return carry;
 }
 
-// copies the kept objects of A to their positions in A2 (bond vertices get
-// their new occupation above)
+// copies the kept objects of A to their new positions in the site's event
+// array O (stride st; bond vertices get their new occupation above)
 PMWA_DEV void rebuild_copy(const uint2* A, int n, const int16_t* pv, const int16_t* nv, const int16_t* ord_of,
-                           const BsVert* VV, uint32_t dir, int side, const int16_t* pos, uint2* A2)
+                           const BsVert* VV, uint32_t dir, int side, const int16_t* pos, uint2* O, long long st)
 {
     const int lane = (int)threadIdx.x;
     auto is_bv = [&](int j) { return j >= 0 && j < n && !ev_worm(A[j].y) && ev_dir(A[j].y) == dir; };
@@ -1879,15 +1879,16 @@ PMWA_DEV void rebuild_copy(const uint2* A, int n, const int16_t* pv, const int16
                 const uint32_t up = side == 0 ? (S >> 2) & 1u : S >> 3;
                 e.y = (e.y & ~8u) | (up << 3);
             }
-            A2[pos[j]] = e;
+            O[(long long)pos[j] * st] = e;
         } else if (!is_bv(pv[j]) && !is_bv(nv[j])) {
-            A2[pos[j]] = e;
+            O[(long long)pos[j] * st] = e;
         }
     }
 }
 
 // dynamic LDS (cap = event capacity):
-//   A, B, A2, B2           4 x cap uint2
+//   A, B                   2 x cap uint2 (the rebuilt lists go straight to
+//                          the event arrays in device memory)
 //   pvA nvA ordA posA, the same for B      8 x cap int
 //   VA, VB                  2 x cap int
 //   VV                      cap BsVert
@@ -1914,15 +1915,13 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     site_split(C, c, dspc, slc);
     const int cap = C.cap, capb = C.capb;
     const double* sE = C.F;
-    // dynamic LDS: the two site lists and their rebuilt forms (cap events
-    // each), 16-bit links, ranks and new positions per event, then per
-    // vertex of the bond (at most the bond buffer's capacity) its indices
-    // and record, then the worm-offset pool
+    // dynamic LDS: the two site lists (cap events each), 16-bit links, ranks
+    // and new positions per event, then per vertex of the bond (at most the
+    // bond buffer's capacity) its indices and record, then the worm-offset
+    // pool
     uint2* A = reinterpret_cast<uint2*>(smem);
     uint2* B = A + cap;
-    uint2* A2 = B + cap;
-    uint2* B2 = A2 + cap;
-    BsVert* VV = reinterpret_cast<BsVert*>(B2 + cap);
+    BsVert* VV = reinterpret_cast<BsVert*>(B + cap);
     int* VA = reinterpret_cast<int*>(VV + capb);
     int* VB = VA + capb;
     int32_t* pool = VB + capb;
@@ -2081,8 +2080,17 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
     const int nb2 = rebuild_positions(B, nb, pvB, nvB, ordB, VV, (uint32_t)(d + 2), 1, 3, posB);
     if (na2 > cap || nb2 > cap) { if (lane == 0) atomicOr(flag, FL_OVERFLOW); return; }
     __syncthreads();
-    rebuild_copy(A, na, pvA, nvA, ordA, VV, (uint32_t)d, 0, posA, A2);
-    rebuild_copy(B, nb, pvB, nvB, ordB, VV, (uint32_t)(d + 2), 1, posB, B2);
+    // the new lists go straight to the sites' event arrays: their old
+    // contents were copied to A and B at the start, and no other block reads
+    // these two sites in this launch (the stride in a register, and both
+    // addresses before the first store, which would otherwise make the
+    // compiler reload them after it)
+    const long long st = C.nloc;
+    uint2* OA = P.ev + ev_base(C, k, dspa, sla);
+    uint2* OB = P.ev + ev_base(C, k, dspc, slc);
+    asm volatile("" ::"v"(OA), "v"(OB), "v"(st));
+    rebuild_copy(A, na, pvA, nvA, ordA, VV, (uint32_t)d, 0, posA, OA, st);
+    rebuild_copy(B, nb, pvB, nvB, ordB, VV, (uint32_t)(d + 2), 1, posB, OB, st);
     for (int w0 = 0; w0 < 4 * nbv; w0 += 64) {
         const int uvg = w0 + lane;
         int n = 0;
@@ -2109,7 +2117,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
                 else if (g == 1) { const int lo = pvB[VB[v]]; at = lo >= 0 ? posB[lo] + 1 : 0; }
                 else if (g == 2) at = posA[VA[v]] + 1;
                 else at = posB[VB[v]] + 1;
-                uint2* O = (g == 0 || g == 2) ? A2 : B2;
+                uint2* O = (g == 0 || g == 2) ? OA : OB;
                 // the count words again, then the slots (same stream)
                 Stream rs;
                 rs.init(C, sweep, RNG_BSL + (uint32_t)g, unit);
@@ -2120,7 +2128,8 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
                 if (worm_slots<1>(rs, (long long)Vv.l[g], n, o, dirs, flag)) {
                     for (int w = 0; w < n; w++) {
                         const uint32_t occ = (uint32_t)((start_occ + w + 1) & 1);
-                        O[at + w] = make_uint2((uint32_t)(base + o[w]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (occ << 3));
+                        O[(long long)(at + w) * st] =
+                            make_uint2((uint32_t)(base + o[w]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | (occ << 3));
                     }
                 }
                 todo = false;
@@ -2128,21 +2137,7 @@ __global__ void __launch_bounds__(64) k_bspatial(Pools P, const int2* __restrict
             __builtin_amdgcn_wave_barrier();
         }
     }
-    __syncthreads();
-    {
-        // (the stride in a register: a field of C read between the stores
-        // would be read again after each of them, since an event store might
-        // change it, and that read would wait for the stores to complete)
-        const long long st = C.nloc;
-        uint2* OA = P.ev + ev_base(C, k, dspa, sla);
-        uint2* OB = P.ev + ev_base(C, k, dspc, slc);
-        // both addresses before the first store (computed after it, their
-        // loads would wait for the stores to complete)
-        asm volatile("" ::"v"(OA), "v"(OB), "v"(st));
-        for (int j = lane; j < na2; j += 64) OA[(long long)j * st] = A2[j];
-        for (int j = lane; j < nb2; j += 64) OB[(long long)j * st] = B2[j];
-        if (lane == 0) { P.cnt[cua] = na2; P.cnt[cuc] = nb2; }
-    }
+    if (lane == 0) { P.cnt[cua] = na2; P.cnt[cuc] = nb2; }
 }
 
 // ===========================================================================
