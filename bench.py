@@ -143,13 +143,20 @@ class Timed:
 
 
 def kernel_table(res):
-    return {PHASES[i]: float(res["ms"][i]) / max(int(res["launches"][i]), 1) for i in range(7)}
+    """Milliseconds per sweep of each phase: the sum of its launches' durations
+    (with several launch groups, their launches overlap on the device)."""
+    return {PHASES[i]: float(res["ms"][i]) / res["steps"] for i in range(7)}
 
 
 def roofline(res, kernel, workload, hash_now, form=None):
     ph = PHASES.index(kernel)
-    avg_ms = float(res["ms"][ph]) / max(int(res["launches"][ph]), 1)
-    nv, nw = res["nv"] / res["steps"], res["nw"] / res["steps"]
+    launches = max(int(res["launches"][ph]), 1)
+    avg_ms = float(res["ms"][ph]) / launches
+    # a sweep's bytes over its launches (one per launch group): with several
+    # groups each launch takes one group's chains, so this is the average
+    # launch's share
+    per_sweep = launches / res["steps"]
+    nv, nw = res["nv"] / res["steps"] / per_sweep, res["nw"] / res["steps"] / per_sweep
     b = alg_bytes(kernel, nv, nw)
     achieved = b / (avg_ms * 1e-3) / 1e9
     traffic, src = traffic_from_profile(workload, kernel, hash_now, form)
@@ -240,9 +247,9 @@ def worms_general_leg(P, W, reps):
 
 def sweep_traffic(workload, hash_now, form, nv_per, ms_step):
     """HBM bytes of a whole sweep from the committed counter summary (every
-    kernel's bytes per launch, the spatial kernel twice), per vertex and as
-    GB/s over the sweep; None unless the summary matches the sources and the
-    launch form."""
+    kernel's bytes per launch times its launches per sweep), per vertex and
+    as GB/s over the sweep; None unless the summary matches the sources and
+    the launch form."""
     path = os.path.join(ROOT, "profiles", f"k_scatter_{workload}_counters.json")
     if not os.path.exists(path):
         return None
@@ -253,15 +260,17 @@ def sweep_traffic(workload, hash_now, form, nv_per, ms_step):
     entry = rec.get("by_form", {}).get(form) if form is not None else rec
     if not entry or "per_kernel" not in entry:
         return None
-    total = sum(v["bytes"] * (2 if "bspatial" in k else 1) for k, v in entry["per_kernel"].items())
+    total = sum(v["bytes"] * v.get("launches_per_sweep", 2 if "bspatial" in k else 1)
+                for k, v in entry["per_kernel"].items())
     return {"bytes_per_sweep": total, "bytes_per_vertex": total / nv_per,
             "GBps": total / (ms_step * 1e-3) / 1e9, "frac_of_peak": total / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "source": os.path.relpath(path, ROOT)}
 
 
-def batched_form(slab, lds):
+def batched_form(slab, lds, groups=1):
     """Launch form of the 256-chain batch, as the profile summaries name it."""
-    return f"temporal slabs of at most beta*t {slab}, scatter_lds {lds}" if slab else f"one slab, scatter_lds {lds}"
+    f = f"temporal slabs of at most beta*t {slab}, scatter_lds {lds}" if slab else f"one slab, scatter_lds {lds}"
+    return f + (f", {groups} launch groups" if groups > 1 else "")
 
 
 def plain_from_states(P, cfgs, states, steps):
@@ -394,16 +403,16 @@ def main():
                                      "ms_per_step": head["seconds"] * 1e3 / args.steps,
                                      "roofline": roofline(head, "k_scatter", "batched_256", hash_now,
                                                           batched_form(args.slab if args.slab > 0 else None,
-                                                                       args.scatter_lds))}
+                                                                       args.scatter_lds, args.groups))}
     elif run("batched"):
         from paper_1307_0328_amd import autotune as T
-        log("[bench] autotuning the temporal tiling and scattering LDS of the 256-chain batch")
+        log("[bench] autotuning the temporal tiling, scattering LDS and launch groups of the 256-chain batch")
         tuner = T.Tuner(sweeps=20, warmup=100)
-        (slab, lds), batch, table = tuner.tune_tiling(batch)
+        (slab, lds, groups), batch, table = tuner.tune_tiling(batch)
         mode = 0
-        log(f"[bench] 256 chains batched (slabs of at most beta*t {slab}, LDS {lds}): thermalise {args.therm}, "
-            f"warm-up {args.warmup}")
-        tb = Timed(P, batch, scatter_mode=mode, scatter_lds=lds)
+        log(f"[bench] 256 chains batched (slabs of at most beta*t {slab}, LDS {lds}, {groups} launch groups): "
+            f"thermalise {args.therm}, warm-up {args.warmup}")
+        tb = Timed(P, batch, scatter_mode=mode, scatter_lds=lds, groups=groups)
         try:
             tb.advance(args.therm)
             brk = tb.timed(20, timing=0x7F)            # per-kernel breakdown, not the headline
@@ -417,7 +426,7 @@ def main():
             log(f"[bench] graph replay of the same batch, {args.steps} sweeps")
         finally:
             tb.close()
-        tg = Timed(P, batch, scatter_mode=mode, use_graph=True, scatter_lds=lds)
+        tg = Timed(P, batch, scatter_mode=mode, use_graph=True, scatter_lds=lds, groups=groups)
         try:
             for c, st in enumerate(states):
                 tg.sim.set_state(st, c)
@@ -451,18 +460,20 @@ def main():
                        "tiling": ("autotuned: temporal domains ceil(beta*t / %s) per chain" % slab) if slab
                                  else "autotuned: one temporal domain per chain",
                        "dom_tau_per_beta": sorted({f"{c['beta']:g}:{c['dom_tau']}" for c in batch}),
-                       "slab_beta_t": slab, "scatter_lds": lds,
-                       "form": f"batched, one launch per phase for all chains (scatter_lds {lds})"},
-            "roofline": roofline(head, dom, "batched_256", hash_now, batched_form(slab, lds)),
+                       "slab_beta_t": slab, "scatter_lds": lds, "launch_groups": groups,
+                       "form": (f"batched: one launch per phase for all chains of a launch group, {groups} "
+                                f"group(s) on streams of their own (scatter_lds {lds})")},
+            "roofline": roofline(head, dom, "batched_256", hash_now, batched_form(slab, lds, groups)),
             "plain": {"value": pl["nv"] / pl["seconds"], "ms_per_step": pl["seconds"] * 1e3 / args.steps,
                       "form": "one chain per handle, one launch sequence per phase per sweep, no graph, "
                               "same thermalised states, same sweeps",
                       "batched_over_plain": value / (pl["nv"] / pl["seconds"]), "same_work": same_work},
             "graph_form": {"value": gr["nv"] / gr["seconds"], "ms_per_step": gr["seconds"] * 1e3 / args.steps},
-            "autotune_table": [{"slab_beta_t": f[0], "scatter_lds": f[1], "value": v} for f, v in table],
+            "autotune_table": [{"slab_beta_t": f[0], "scatter_lds": f[1], "launch_groups": f[2], "value": v}
+                               for f, v in table],
             "kernel_ms_per_sweep": kern,
             "algorithmic_GBps_per_sweep": 32.0 * nv_per / (ms_step * 1e-3) / 1e9,
-            "measured_traffic_per_sweep": sweep_traffic("batched_256", hash_now, batched_form(slab, lds),
+            "measured_traffic_per_sweep": sweep_traffic("batched_256", hash_now, batched_form(slab, lds, groups),
                                                          nv_per, ms_step),
             "worm_scatterings_per_s": head["attempts"] / head["seconds"],
             "vertices_per_sweep": nv_per,

@@ -108,6 +108,13 @@ typedef struct pmwa_opts {
                                  and joins, so no group's phase waits for
                                  another group's (one graph with G branches when
                                  use_graph).  Results do not depend on it.    */
+    int32_t vertex_rows;      /* occupation changes (kinks and worms) of a site
+                                 in a slab that the vertex kernel stages in LDS
+                                 per lane (8..128); a lane with more walks its
+                                 lists in HBM.  Fewer rows let more blocks share
+                                 a CU.  0: from the expected kinks per site
+                                 and slab (about 2.5 t dbeta), with margin.
+                                 Results do not depend on it.                */
 } pmwa_opts;
 
 /* Raw per-sweep record of one chain (all sums over the whole lattice). */

@@ -6,7 +6,9 @@ launch form:
 - the node store of the scattering kernel (LDS or HBM) and the LDS bytes a
   domain of the LDS form may take (fewer bytes let more domains share a CU;
   the larger domains then take the HBM store);
-- eager launches or graph replay.
+- eager launches or graph replay;
+- for a batch, the number of launch groups (streams whose phases advance
+  independently).
 
 Each candidate is timed on the device (vertex updates per second over a
 few sweeps after a warm-up), and the fastest is kept in a cache keyed by
@@ -101,7 +103,7 @@ def temporal_tiling(chains: list[dict], slab_bt: float | None) -> list[dict]:
 
 
 def measure_rate(chains: list[dict], cand: Candidate | None, sweeps: int = 20, warmup: int = 10,
-                 mode: int = 0, use_graph: bool = False, lds: int = 0) -> float:
+                 mode: int = 0, use_graph: bool = False, lds: int = 0, groups: int = 1) -> float:
     """Vertex updates per second of `chains` (parameter dicts) with the grid
     and launch form of `cand` (None: the chains' own grids and the launch
     form given by `mode` and `use_graph`), timed on the device."""
@@ -113,7 +115,7 @@ def measure_rate(chains: list[dict], cand: Candidate | None, sweeps: int = 20, w
         ps.append(P.make_params(**q))
     if cand is not None:
         mode, use_graph = cand.scatter_mode, cand.use_graph
-    with P.Sim(ps, scatter_mode=mode, use_graph=use_graph, scatter_lds=lds,
+    with P.Sim(ps, scatter_mode=mode, use_graph=use_graph, scatter_lds=lds, groups=groups,
                series_cap=max(64, sweeps + warmup + 8)) as sim:
         sim.sweep(warmup)
         if sim.status() != 0:
@@ -212,28 +214,41 @@ class Tuner:
         return best, table
 
     def tune_tiling(self, chains: list[dict], slab_options=(None, 8.0, 4.0),
-                    lds_options=(24576, 28672, 36864, 45056)):
-        """Temporal tiling and scattering LDS bytes for a whole batch, spatial
-        grids as given: every chain gets ceil(beta*t / slab) temporal domains
-        (slab None: the chains' own), and each (slab, LDS bytes) pair is timed
-        on all chains together.  Smaller slabs put more domains in the LDS
-        node store and give the per-(bond, slab) and per-(site, slab) kernels
-        more units; larger ones keep fewer boundaries.  Returns the best
-        (slab, lds), the tiled chains and the table."""
+                    lds_options=(24576, 28672, 36864, 45056), group_options=(1, 2, 3)):
+        """Temporal tiling, scattering LDS bytes and launch groups for a whole
+        batch, spatial grids as given: every chain gets ceil(beta*t / slab)
+        temporal domains (slab None: the chains' own), and each (slab, LDS
+        bytes) pair is timed on all chains together in one launch group;
+        then the best pair with each number of groups in `group_options`.
+        Smaller slabs put more domains in the LDS node store and give the
+        per-(bond, slab) and per-(site, slab) kernels more units; larger ones
+        keep fewer boundaries.  Groups let one group's phases start while
+        another's slowest units finish.  Returns the best (slab, lds, groups),
+        the tiled chains and the table."""
         table = []
+
+        def timed(tiled, slab, lds, groups):
+            rate = 0.0
+            try:
+                rate = float(self.measure(tiled, None, self.sweeps, self.warmup, mode=0, use_graph=False,
+                                          lds=lds, groups=groups))
+            except P.PmwaError:
+                pass
+            table.append(((slab, lds, groups), rate))
+            return rate
+
         for slab in slab_options:
             tiled = temporal_tiling(chains, slab)
             for lds in lds_options:
-                rate = 0.0
-                try:
-                    rate = float(self.measure(tiled, None, self.sweeps, self.warmup, mode=0, use_graph=False,
-                                              lds=lds))
-                except P.PmwaError:
-                    pass
-                table.append(((slab, lds), rate))
-        best, rate = max(table, key=lambda fr: fr[1])
+                timed(tiled, slab, lds, 1)
+        (slab, lds, _), rate = max(table, key=lambda fr: fr[1])
         if rate <= 0.0:
             raise RuntimeError("autotune: no tiling ran for the batch")
+        tiled = temporal_tiling(chains, slab)
+        for g in group_options:
+            if g != 1:
+                timed(tiled, slab, lds, g)
+        best, _ = max(table, key=lambda fr: fr[1])
         return best, temporal_tiling(chains, best[0]), table
 
     def tune_batch(self, chains: list[dict], fix_spatial=None, fix_tau=None):

@@ -625,7 +625,11 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
     if (h->opts.scatter_mode < 0 || h->opts.scatter_mode > 2 || h->opts.event_cap < 0 ||
         h->opts.event_cap > 32767 || h->opts.regen_mode < 0 || h->opts.regen_mode > 2 ||
         h->opts.vertex_mode < 0 || h->opts.vertex_mode > 3 || h->opts.scatter_lds < 0 ||
-        h->opts.scatter_lds > 160 * 1024 || h->opts.groups < 0 || h->opts.groups > 64) { delete h; return PMWA_EINVAL; }
+        h->opts.scatter_lds > 160 * 1024 || h->opts.groups < 0 || h->opts.groups > 64 ||
+        (h->opts.vertex_rows != 0 && (h->opts.vertex_rows < 8 || h->opts.vertex_rows > 128))) {
+        delete h;
+        return PMWA_EINVAL;
+    }
     h->stream = (hipStream_t)h->opts.stream;
     if (!h->stream) {
         // work goes to a stream of the handle (default priority)
@@ -881,7 +885,26 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         // occupation-changing objects (kinks and worms) of a site in a slab
         // staged in LDS; a lane with more reads its lists from HBM
         const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + VL * sizeof(int32_t));
-        h->v_rows = std::max(8, std::min(std::max(maxcap, 8), 64));
+        // rows per lane: the expected occupation changes of a (site, slab)
+        // plus two standard deviations, in steps of 8.  Kinks dominate: about
+        // 0.6 t per bond and unit time in the hard-core model (its kinetic
+        // energy per bond), four bonds per site; worms add 2 eta per unit
+        // time.  A wavefront whose lanes all fit runs the staged walk, so the
+        // margin matters, but each row costs 512 bytes of the block's LDS and
+        // fewer rows let more blocks share a CU: measured on the 256-chain
+        // batch, 32 rows at slabs of beta*t 8 and 24 at 4 are the fastest
+        // (64 rows: 16-55% slower; 24 and 16 rows: a factor 2 at slabs of 8)
+        int rows = h->opts.vertex_rows;
+        if (rows == 0) {
+            double f = 0.0;
+            for (auto& hc : h->ch) {
+                const double db = hc.p.beta / hc.p.dom_tau;
+                f = std::max(f, 2.5 * hc.p.t * db + 2.0 * hc.p.eta * db + 1.0);
+            }
+            rows = ((int)std::ceil(f + 2.0 * std::sqrt(f)) + 7) & ~7;
+            rows = std::max(16, std::min(rows, std::min(std::max(maxcap, 8), 64)));
+        }
+        h->v_rows = rows;
         h->v_lds = v_fixed + (size_t)h->v_rows * 2 * VL * sizeof(uint32_t);
         if (!r2) r2 = set_lds((const void*)k_vertex, h->v_lds, lds_max);
     }

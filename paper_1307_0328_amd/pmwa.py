@@ -37,7 +37,8 @@ class pmwa_params(C.Structure):
 class pmwa_opts(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("scatter_mode", C.c_int32), ("series_cap", C.c_int32),
                 ("event_cap", C.c_int32), ("use_graph", C.c_int32), ("regen_mode", C.c_int32),
-                ("vertex_mode", C.c_int32), ("scatter_lds", C.c_int32), ("groups", C.c_int32)]
+                ("vertex_mode", C.c_int32), ("scatter_lds", C.c_int32), ("groups", C.c_int32),
+                ("vertex_rows", C.c_int32)]
 
 
 class pmwa_obs(C.Structure):
@@ -330,7 +331,7 @@ class Sim:
     """A handle of one or more chains (convenience around the calls above)."""
 
     def __init__(self, chains, stream=None, scatter_mode=0, series_cap=4096, event_cap=0,
-                 use_graph=False, regen_mode=0, vertex_mode=0, scatter_lds=0, groups=0):
+                 use_graph=False, regen_mode=0, vertex_mode=0, scatter_lds=0, groups=0, vertex_rows=0):
         if isinstance(chains, pmwa_params):
             chains = [chains]
         self.chains = list(chains)
@@ -344,6 +345,7 @@ class Sim:
         o.vertex_mode = vertex_mode
         o.scatter_lds = scatter_lds
         o.groups = groups
+        o.vertex_rows = vertex_rows
         self.h = pmwa_create(self.chains, o)
 
     def close(self):

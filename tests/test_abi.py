@@ -35,3 +35,17 @@ def test_default_event_cap_and_validation():
                 dict(L=4, eta=1.0, beta=9.0), dict(L=4, dom_tau=65)]:
         assert P.pmwa_default_event_cap(P.make_params(**bad)) == P.PMWA_EINVAL, bad
     assert P.lib().pmwa_strerror(P.PMWA_EOVERFLOW).startswith(b"capacity")
+
+
+def test_create_rejects_bad_options_without_a_gpu():
+    """Option ranges are checked before any device call."""
+    import ctypes as C
+    from paper_1307_0328_amd import pmwa as P
+    arr = (P.pmwa_params * 1)(P.make_params(L=8, beta=4.0, dom_x=1, dom_y=1, dom_tau=1))
+    for field, value in [("vertex_rows", 4), ("vertex_rows", 129), ("groups", 65), ("scatter_mode", 3),
+                         ("event_cap", 40000), ("scatter_lds", 200 * 1024), ("vertex_mode", 4)]:
+        o = P.pmwa_opts()
+        setattr(o, field, value)
+        h = C.c_void_p()
+        assert P.lib().pmwa_create(arr, 1, C.byref(o), C.byref(h)) == P.PMWA_EINVAL, field
+        assert not h.value

@@ -87,15 +87,17 @@ def test_temporal_tiling_and_tune_tiling():
     assert T.temporal_tiling(chains, None) == chains
     seen = []
 
-    def fake(cs, cand, sweeps, warmup, mode=0, use_graph=False, lds=0):
+    def fake(cs, cand, sweeps, warmup, mode=0, use_graph=False, lds=0, groups=1):
         assert cand is None and mode == 0 and not use_graph
         taus = tuple(c["dom_tau"] for c in cs)
-        seen.append((taus, lds))
-        # prefer slabs of beta*t 8 with 36 KB
-        return 1e6 * (1.0 + (taus == (1, 1, 2, 1)) + 0.5 * (lds == 36864))
+        seen.append((taus, lds, groups))
+        # prefer slabs of beta*t 8 with 36 KB, then two groups
+        return 1e6 * (1.0 + (taus == (1, 1, 2, 1)) + 0.5 * (lds == 36864) + 0.1 * (groups == 2))
 
     best, tiled, table = T.Tuner(measure=fake).tune_tiling(chains)
-    assert best == (8.0, 36864)
+    assert best == (8.0, 36864, 2)
     assert [c["dom_tau"] for c in tiled] == [1, 1, 2, 1]
     assert [c["chain_id"] for c in tiled] == [0, 1, 2, 3]
-    assert len(table) == len(seen) == 12
+    assert len(table) == len(seen) == 14
+    # groups are tried on the best (slab, lds) pair only
+    assert {s for s in seen if s[2] != 1} == {((1, 1, 2, 1), 36864, 2), ((1, 1, 2, 1), 36864, 3)}

@@ -180,3 +180,24 @@ def test_forced_vertex_paths(vmode):
         ref = ch.series()
         for f in ("nv", "nkink", "nw", "occ2", "nn2"):
             np.testing.assert_array_equal(rows[f], ref[f], err_msg=f)
+
+
+@pytest.mark.parametrize("rows", [8, 16])
+def test_few_vertex_rows(rows):
+    """With few LDS rows per lane (vertex_rows) the lanes whose sites have
+    more occupation changes walk their lists in HBM while the others of the
+    same wavefront take the staged walk: still the oracle's trajectory."""
+    from paper_1307_0328_amd import pmwa as P
+    cfg = dict(L=8, beta=16.0, V=1.0, mu=0.5, eta=0.05, dom_x=2, dom_y=2, dom_tau=2, seed=43)
+    say(f"[equilibrium] vertex_rows={rows} cfg={cfg}")
+    ch = O.Chain(**cfg)
+    with P.Sim(P.make_params(**cfg), vertex_rows=rows) as sim:
+        for _ in range(6):
+            sim.sweep(10)
+            ch.sweep(10)
+            assert sim.status() == 0
+            assert sim.state_hash() == ch.state_hash()
+        rows_dev = sim.measure()
+    ref = ch.series()
+    for f in ("nv", "nkink", "nw", "occ2", "nn2"):
+        np.testing.assert_array_equal(rows_dev[f], ref[f], err_msg=f)
