@@ -885,16 +885,25 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         // occupation-changing objects (kinks and worms) of a site in a slab
         // staged in LDS; a lane with more reads its lists from HBM
         const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + VL * sizeof(int32_t));
-        // rows per lane: the expected occupation changes of a (site, slab)
-        // plus two standard deviations, in steps of 8.  Kinks dominate: about
-        // 0.6 t per bond and unit time in the hard-core model (its kinetic
-        // energy per bond), four bonds per site; worms add 2 eta per unit
-        // time.  A wavefront whose lanes all fit runs the staged walk, so the
-        // margin matters, but each row costs 512 bytes of the block's LDS and
-        // fewer rows let more blocks share a CU: measured on the 256-chain
-        // batch, 32 rows at slabs of beta*t 8 and 24 at 4 are the fastest
-        // (64 rows: 16-55% slower; 24 and 16 rows: a factor 2 at slabs of 8)
+        // rows per lane.  When every block of the vertex launch is resident
+        // at once with 64 rows, LDS does not limit it: 64 (the 64x64 chain,
+        // one block per CU: 32 rows made it 2.5x slower, since a wavefront
+        // waits for its lanes that walk their lists in HBM).  Otherwise the
+        // expected occupation changes of a (site, slab) plus two standard
+        // deviations, in steps of 8.  Kinks dominate: about 0.6 t per bond
+        // and unit time in the hard-core model (its kinetic energy per bond),
+        // four bonds per site; worms add 2 eta per unit time.  Each row costs
+        // 512 bytes of the block's LDS, and fewer rows let more blocks share
+        // a CU: measured on the 256-chain batch, 32 rows at slabs of beta*t 8
+        // and 24 at 4 are the fastest (64 rows: 16-55% slower; 24 and 16
+        // rows: a factor 2 at slabs of 8)
         int rows = h->opts.vertex_rows;
+        int64_t vblocks = 0;
+        for (auto& hc : h->ch) vblocks += (hc.n_units_v + VL - 1) / VL;
+        const size_t lds64 = v_fixed + (size_t)64 * 2 * VL * sizeof(uint32_t);
+        const int64_t resident64 = (int64_t)std::max(prop.multiProcessorCount, 1) *
+                                   std::max<int64_t>(1, (int64_t)(lds_max / lds64));
+        if (rows == 0 && vblocks <= resident64) rows = std::min(std::max(maxcap, 8), 64);
         if (rows == 0) {
             double f = 0.0;
             for (auto& hc : h->ch) {
