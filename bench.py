@@ -414,18 +414,14 @@ def main():
             f"thermalise {args.therm}, warm-up {args.warmup}")
         tb = Timed(P, batch, scatter_mode=mode, scatter_lds=lds, groups=groups)
         try:
-            tb.advance(args.therm)
-            brk = tb.timed(20, timing=0x7F)            # per-kernel breakdown, not the headline
-            kern = kernel_table(brk)
-            dom = max(kern, key=kern.get)
-            tb.advance(args.warmup)
+            tb.advance(args.therm + args.warmup)
             # the other forms start from these states and run the same sweeps
             states = [tb.sim.get_state(c) for c in range(len(batch))]
-            log(f"[bench] headline: {args.steps} sweeps, events around {dom}")
-            head = tb.timed(args.steps, timing=1 << PHASES.index(dom))
-            log(f"[bench] graph replay of the same batch, {args.steps} sweeps")
+            log(f"[bench] headline: {args.steps} sweeps")
+            head = tb.timed(args.steps)
         finally:
             tb.close()
+        log(f"[bench] graph replay of the same batch, {args.steps} sweeps")
         tg = Timed(P, batch, scatter_mode=mode, use_graph=True, scatter_lds=lds, groups=groups)
         try:
             for c, st in enumerate(states):
@@ -433,10 +429,23 @@ def main():
             gr = tg.timed(args.steps)
         finally:
             tg.close()
+        # the kernels' own rates: the same sweeps in one launch group, so that
+        # each launch has the device to itself (with several groups, launches
+        # of different groups overlap and share it), events around every phase
+        log(f"[bench] per-kernel events: one launch group, same states, {args.steps} sweeps")
+        t1 = Timed(P, batch, scatter_mode=mode, scatter_lds=lds, groups=1)
+        try:
+            for c, st in enumerate(states):
+                t1.sim.set_state(st, c)
+            one = t1.timed(args.steps, timing=0x7F)
+        finally:
+            t1.close()
+        kern = kernel_table(one)
+        dom = max(kern, key=kern.get)
         log(f"[bench] plain form: each chain on its own handle, same states, {args.steps} sweeps")
         pl = plain_from_states(P, batch, states, args.steps)
-        # bit-exact trajectories: the three forms did the same work
-        same_work = head["nv"] == gr["nv"] == pl["nv"]
+        # bit-exact trajectories: the four forms did the same work
+        same_work = head["nv"] == gr["nv"] == pl["nv"] == one["nv"]
         value = head["nv"] / head["seconds"]
         ms_step = head["seconds"] * 1e3 / args.steps
         nv_per, nw_per = head["nv"] / args.steps, head["nw"] / args.steps
@@ -463,7 +472,8 @@ def main():
                        "slab_beta_t": slab, "scatter_lds": lds, "launch_groups": groups,
                        "form": (f"batched: one launch per phase for all chains of a launch group, {groups} "
                                 f"group(s) on streams of their own (scatter_lds {lds})")},
-            "roofline": roofline(head, dom, "batched_256", hash_now, batched_form(slab, lds, groups)),
+            "roofline": dict(roofline(one, dom, "batched_256", hash_now, batched_form(slab, lds, 1)),
+                             form="the headline's chains, states and sweeps in one launch group"),
             "plain": {"value": pl["nv"] / pl["seconds"], "ms_per_step": pl["seconds"] * 1e3 / args.steps,
                       "form": "one chain per handle, one launch sequence per phase per sweep, no graph, "
                               "same thermalised states, same sweeps",
@@ -471,9 +481,12 @@ def main():
             "graph_form": {"value": gr["nv"] / gr["seconds"], "ms_per_step": gr["seconds"] * 1e3 / args.steps},
             "autotune_table": [{"slab_beta_t": f[0], "scatter_lds": f[1], "launch_groups": f[2], "value": v}
                                for f, v in table],
+            "one_group_form": {"value": one["nv"] / one["seconds"], "ms_per_step": one["seconds"] * 1e3 / args.steps,
+                               "form": "one launch group, HIP events around every phase (the kernel table and "
+                                       "the roofline come from this run)"},
             "kernel_ms_per_sweep": kern,
             "algorithmic_GBps_per_sweep": 32.0 * nv_per / (ms_step * 1e-3) / 1e9,
-            "measured_traffic_per_sweep": sweep_traffic("batched_256", hash_now, batched_form(slab, lds, groups),
+            "measured_traffic_per_sweep": sweep_traffic("batched_256", hash_now, batched_form(slab, lds, 1),
                                                          nv_per, ms_step),
             "worm_scatterings_per_s": head["attempts"] / head["seconds"],
             "vertices_per_sweep": nv_per,
