@@ -112,8 +112,10 @@ typedef struct pmwa_opts {
                                  in a slab that the vertex kernel stages in LDS
                                  per lane (8..128); a lane with more walks its
                                  lists in HBM.  Fewer rows let more blocks share
-                                 a CU.  0: from the expected kinks per site
-                                 and slab (about 2.5 t dbeta), with margin.
+                                 a CU.  0: 64 when every block of the launch
+                                 is resident at once anyway, else from the
+                                 expected kinks per site and slab (about
+                                 2.5 t dbeta plus two standard deviations).
                                  Results do not depend on it.                */
 } pmwa_opts;
 
