@@ -384,10 +384,18 @@ PMWA_DEV int worm_count(const double* __restrict__ E, double lambda, RS& s, long
     return n;
 }
 
-// the n slots: offsets to off[0], off[ST], ... (sorted), direction bit i to
+// a lane's column of offsets: entries i * ST of an LDS array
+template <int ST>
+struct LdsCol {
+    int32_t* p;
+    PMWA_DEV int32_t get(int i) const { return p[i * ST]; }
+    PMWA_DEV void set(int i, int32_t v) const { p[i * ST] = v; }
+};
+
+// the n slots: offsets to col entries 0..n-1 (sorted), direction bit i to
 // bit i of `dirs`.  Returns false on failure (flagged).
-template <int ST, class RS>
-PMWA_DEV bool worm_slots(RS& s, long long ell, int n, int32_t* off, uint64_t& dirs, unsigned int* flag)
+template <class RS, class Col>
+PMWA_DEV bool worm_slots_col(RS& s, long long ell, int n, const Col& col, uint64_t& dirs, unsigned int* flag)
 {
     dirs = 0;
     for (int i = 0; i < n; i++) {
@@ -397,19 +405,44 @@ PMWA_DEV bool worm_slots(RS& s, long long ell, int n, int32_t* off, uint64_t& di
         do {
             r = (int32_t)below(s.next(), (uint64_t)ell);
             again = false;
-            for (int j = 0; j < i; j++) again |= (off[j * ST] == r);
+            for (int j = 0; j < i; j++) again |= (col.get(j) == r);
         } while (again && ++guard < 100000);
         if (again) { atomicOr(flag, FL_SAMPLER); return false; }
-        off[i * ST] = r;
+        col.set(i, r);
     }
     for (int x = 1; x < n; x++) {            // insertion sort
-        const int32_t t = off[x * ST];
+        const int32_t t = col.get(x);
         int y = x - 1;
-        while (y >= 0 && off[y * ST] > t) {
-            off[(y + 1) * ST] = off[y * ST];
+        while (y >= 0 && col.get(y) > t) {
+            col.set(y + 1, col.get(y));
             y--;
         }
-        off[(y + 1) * ST] = t;
+        col.set(y + 1, t);
+    }
+    for (int i = 0; i < n; i++) dirs |= (s.next() >> 63) << i;
+    return true;
+}
+
+template <int ST, class RS>
+PMWA_DEV bool worm_slots(RS& s, long long ell, int n, int32_t* off, uint64_t& dirs, unsigned int* flag)
+{
+    return worm_slots_col(s, ell, n, LdsCol<ST>{off}, dirs, flag);
+}
+
+// the same draws for n <= 2, the sorted offsets in registers
+template <class RS>
+PMWA_DEV bool worm_slots_reg(RS& s, long long ell, int n, int32_t& r0, int32_t& r1, uint64_t& dirs,
+                             unsigned int* flag)
+{
+    dirs = 0;
+    r0 = (int32_t)below(s.next(), (uint64_t)ell);
+    if (n == 2) {
+        int guard = 0;
+        do {
+            r1 = (int32_t)below(s.next(), (uint64_t)ell);
+        } while (r1 == r0 && ++guard < 100000);
+        if (r1 == r0) { atomicOr(flag, FL_SAMPLER); return false; }
+        if (r1 < r0) { const int32_t t = r0; r0 = r1; r1 = t; }
     }
     for (int i = 0; i < n; i++) dirs |= (s.next() >> 63) << i;
     return true;

@@ -490,18 +490,25 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
 // stream.  The site's old list (old vertices and worms) is overwritten.
 // k_assemble: one lane per (site, slab); k_assemble_w: one wavefront.
 // ===========================================================================
+// a column of worm offsets kept in the .x words of a site's event slots
+// (stride st), where the worms will be written
+struct EvCol {
+    uint2* p;
+    long long st;
+    PMWA_DEV int32_t get(int i) const { return (int32_t)p[i * st].x; }
+    PMWA_DEV void set(int i, int32_t v) const { p[i * st].x = (uint32_t)v; }
+};
+
 __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict__ blk)
 {
     const int2 bt = blk[blockIdx.x];
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
-    // the expm1 table is read from L2 (12 KB of LDS per block instead of 20
-    // lets more lane groups share a CU)
+    // the expm1 table is read from L2, and the kernel holds no LDS: more lane
+    // groups share a CU
     const double* sE = C.F;
-    __shared__ int32_t s_off[NWL * 64];
     if (u >= C.ntau * C.N || !live(P, C, bt.x)) return;
     unsigned int* flag = &P.flags[bt.x];
-    int32_t* off = s_off + threadIdx.x;
     const double lambda = C.lambda;
     const int sl = u % C.nloc;
     const int r = u / C.nloc;
@@ -569,17 +576,27 @@ __global__ void __launch_bounds__(64) k_assemble(Pools P, const int2* __restrict
             q = (int)((best < 2 ? v >> 30 : v >> 31) & 1u);
             above = q ^ (int)((v >> 29) & 1u);
         }
-        uint64_t dirs;
+        uint64_t dirs = 0;
         rs.w = ri << 17;            // interval ri draws from word 2^17 ri on
         rs.blk = 0;
-        const int n = sample_worms(sE, lambda, rs, (long long)hi - lo, p ^ q, off, dirs, flag);
+        // the count, then the slots: one or two in registers; more (rare) are
+        // drawn and sorted in place in the event slots they will occupy
+        const long long ell = (long long)hi - lo;
+        const int n = worm_count(sE, lambda, rs, ell, p ^ q, flag);
         if (n < 0) return;
         if (out + n + (best >= 0 ? 1 : 0) > capu) { atomicOr(flag, FL_OVERFLOW); return; }
+        int32_t r0 = 0, r1 = 0;
+        if (n > 2) {
+            if (!worm_slots_col(rs, ell, n, EvCol{E + (long long)out * st, st}, dirs, flag)) return;
+        } else if (n > 0) {
+            if (!worm_slots_reg(rs, ell, n, r0, r1, dirs, flag)) return;
+        }
         ri++;
         int s = p;
         for (int w = 0; w < n; w++) {
             s ^= 1;
-            E[(long long)out * st] = make_uint2((uint32_t)(lo + off[w * 64]),
+            const int32_t o = n > 2 ? (int32_t)E[(long long)out * st].x : (w == 0 ? r0 : r1);
+            E[(long long)out * st] = make_uint2((uint32_t)(lo + o),
                                                 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3));
             out++;
         }

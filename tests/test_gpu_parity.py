@@ -226,6 +226,41 @@ def test_regeneration_forms_match(regen_mode):
             assert_series_equal(sim.measure(), ch.series(), f"regen {regen_mode} {name}")
 
 
+def longest_worm_run(st):
+    """Most consecutive worms between two other events of a site's list."""
+    best, pos = 0, 0
+    for c in np.asarray(st["counts"]):
+        run = 0
+        for info in np.asarray(st["infos"])[pos:pos + c]:
+            run = run + 1 if info & 1 else 0
+            best = max(best, run)
+        pos += c
+    return best
+
+
+@pytest.mark.parametrize("regen_mode", [1, 2])
+def test_regeneration_with_many_worms_per_interval(regen_mode):
+    """eta * beta near its limit: intervals draw up to ~10 worms, so the lane
+    form's slots take both its register path (one or two worms) and its
+    in-place path in the event slots (three or more); the oracle's
+    trajectory either way."""
+    P = _pm()
+    # small t: few vertices, long intervals, many worms in each
+    cfg = dict(L=8, beta=8.0, t=0.1, V=0.0, mu=0.0, eta=0.9, dom_x=2, dom_y=2, dom_tau=2, seed=57)
+    ch = O.Chain(**cfg)
+    longest = 0
+    with P.Sim(P.make_params(**cfg), regen_mode=regen_mode) as sim:
+        for _ in range(6):
+            sim.sweep(1)
+            ch.sweep(1)
+            assert sim.status() == 0
+            assert sim.state_hash() == ch.state_hash()
+            longest = max(longest, longest_worm_run(ch.get_state()))
+        assert_series_equal(sim.measure(), ch.series(), f"many worms, regen {regen_mode}")
+    # runs of three and more consecutive worms on a site (about 80 per sweep)
+    assert longest >= 3
+
+
 def test_series_ring_drains():
     """More sweeps than the device ring holds: records are drained in order."""
     P = _pm()
