@@ -448,18 +448,6 @@ PMWA_DEV bool worm_slots_reg(RS& s, long long ell, int n, int32_t& r0, int32_t& 
     return true;
 }
 
-// both steps; offsets in one lane's column of an LDS array (stride ST).
-// Returns n, or -1 on failure (flagged).
-template <int ST = 64, class RS>
-PMWA_DEV int sample_worms(const double* __restrict__ E, double lambda, RS& s, long long ell,
-                          int sigma, int32_t* off, uint64_t& dirs, unsigned int* flag)
-{
-    dirs = 0;
-    const int n = worm_count(E, lambda, s, ell, sigma, flag);
-    if (n <= 0) return n;
-    return worm_slots<ST>(s, ell, n, off, dirs, flag) ? n : -1;
-}
-
 // the chain takes part in this sweep
 PMWA_DEV bool live(const Pools& P, const ChainDev& C, int c)
 {

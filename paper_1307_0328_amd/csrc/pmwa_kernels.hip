@@ -1647,15 +1647,39 @@ struct SiteArr {
     }
 };
 
-// writes the n worms of an interval (slot base + off[64 w], direction bit w
-// of dirs) as events from position j0, occupation starting at p
-template <int ST>
-PMWA_DEV void put_worms(SiteArr& A, int j0, int32_t base, const int32_t* off, uint64_t dirs, int n, int p)
+// the sorted slots of an interval's worms: one or two in registers, more in
+// the .x words of a column of event slots (tmp, stride st)
+struct Slots {
+    int n = 0;
+    int32_t r0 = 0, r1 = 0;
+    uint64_t dirs = 0;
+    const uint2* tmp = nullptr;
+    long long st = 0;
+    PMWA_DEV int32_t off(int w) const { return n > 2 ? (int32_t)tmp[w * st].x : (w == 0 ? r0 : r1); }
+};
+
+// the slots of n worms on an interval of ell slots: registers for n <= 2,
+// else the column at tmp.  False on failure (flagged).
+template <class RS>
+PMWA_DEV bool draw_slots(RS& rs, long long ell, int n, uint2* tmp, long long st, Slots& S, unsigned int* flag)
+{
+    S.n = n;
+    S.tmp = tmp;
+    S.st = st;
+    if (n > 2) return worm_slots_col(rs, ell, n, EvCol{tmp, st}, S.dirs, flag);
+    if (n > 0) return worm_slots_reg(rs, ell, n, S.r0, S.r1, S.dirs, flag);
+    return true;
+}
+
+// writes the worms of an interval (slot base + offset, direction bit w of
+// dirs) as events from position j0, occupation starting at p
+PMWA_DEV void put_worms(SiteArr& A, int j0, int32_t base, const Slots& S, int p)
 {
     int s = p;
-    for (int w = 0; w < n; w++) {
+    for (int w = 0; w < S.n; w++) {
         s ^= 1;
-        A.put(j0 + w, make_uint2((uint32_t)(base + off[w * ST]), 1u | ((uint32_t)((dirs >> w) & 1u) << 1) | ((uint32_t)s << 3)));
+        A.put(j0 + w, make_uint2((uint32_t)(base + S.off(w)),
+                                 1u | ((uint32_t)((S.dirs >> w) & 1u) << 1) | ((uint32_t)s << 3)));
     }
 }
 
@@ -1669,9 +1693,9 @@ __global__ void __launch_bounds__(LANES) k_btemporal(Pools P, const int2* __rest
     const ChainDev& C = P.cd[bt.x];
     const int u = bt.y + (int)threadIdx.x;
     // the expm1 table is read from L2 (an LDS copy would take 8 KB more per
-    // group and leave fewer groups per CU)
+    // group and leave fewer groups per CU); worm slots go to registers or to
+    // free event slots, not to LDS
     const double* sE = C.F;
-    __shared__ int32_t s_off[2 * NWL * LANES];
     // the boundary ticks in LDS and the chain fields the loop reads in
     // registers: the loop's event stores could alias fields of C, which
     // would then be read again, after waiting for the stores, at every use
@@ -1691,8 +1715,6 @@ __global__ void __launch_bounds__(LANES) k_btemporal(Pools P, const int2* __rest
     const int site = site_join(C, dsp, sl);
     const int nt = C.ntau;
     const uint32_t sweep = (uint32_t)P.sweep[bt.x];
-    int32_t* o1 = s_off + threadIdx.x;
-    int32_t* o2 = s_off + NWL * LANES + threadIdx.x;
     for (int k = 0; k < nt; k++) {
         Stream rs;
         rs.init_keys(key0, key1, cid, sweep, RNG_BT, (uint32_t)((long long)site * nt + k));
@@ -1706,11 +1728,14 @@ __global__ void __launch_bounds__(LANES) k_btemporal(Pools P, const int2* __rest
                 // the circle is one interval through the boundary
                 const double W[2] = {1.0, 1.0};
                 const int sp = choose(W, u53(rs.next()));
-                uint64_t d1;
-                const int m = sample_worms<LANES>(sE, lambda, rs, Mt, 0, o1, d1, flag);
+                const int m = worm_count(sE, lambda, rs, Mt, 0, flag);
                 if (m < 0) return;
+                // every event is replaced: the slots are drawn where the
+                // worms go
                 if (!Ak.resize(0, Ak.n, m)) { atomicOr(flag, FL_OVERFLOW); return; }
-                put_worms<LANES>(Ak, 0, 0, o1, d1, m, sp);
+                Slots S1;
+                if (!draw_slots(rs, Mt, m, Ak.e, nloc, S1, flag)) return;
+                put_worms(Ak, 0, 0, S1, sp);
                 P.cnt[cuk] = Ak.n;
                 *sk = (uint8_t)sp;
                 continue;
@@ -1738,22 +1763,37 @@ __global__ void __launch_bounds__(LANES) k_btemporal(Pools P, const int2* __rest
         double W[2];
         for (int sp = 0; sp < 2; sp++) W[sp] = fleg(sE, sp ^ q, l1) * fleg(sE, p ^ sp, l2);
         const int sp = choose(W, u53(rs.next()));
-        uint64_t d1, d2;
-        const int m1 = sample_worms<LANES>(sE, lambda, rs, l1, sp ^ q, o1, d1, flag);
+        // each leg's count, then its slots.  More than two slots wait in the
+        // top event slots of the leg's array (leg I_2's below leg I_1's when
+        // there is one array); the resizes then keep the array below them
+        // (a capacity that much smaller, while they are held)
+        const int m1 = worm_count(sE, lambda, rs, l1, sp ^ q, flag);
         if (m1 < 0) return;
-        const int m2 = sample_worms<LANES>(sE, lambda, rs, l2, p ^ sp, o2, d2, flag);
+        const int h1 = m1 > 2 ? m1 : 0;
+        if (Ak.n + h1 > cap) { atomicOr(flag, FL_OVERFLOW); return; }
+        Slots S1, S2;
+        if (!draw_slots(rs, l1, m1, Ak.e + (long long)(cap - h1) * nloc, nloc, S1, flag)) return;
+        const int m2 = worm_count(sE, lambda, rs, l2, p ^ sp, flag);
         if (m2 < 0) return;
+        const int h2 = m2 > 2 ? m2 : 0;
         if (nt == 1) {
             // same array: suffix first, then prefix
+            if (Ak.n + h1 + h2 > cap) { atomicOr(flag, FL_OVERFLOW); return; }
+            if (!draw_slots(rs, l2, m2, Ak.e + (long long)(cap - h1 - h2) * nloc, nloc, S2, flag)) return;
+            Ak.cap = cap - h1 - h2;
             if (!Ak.resize(jl + 1, Ak.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<LANES>(Ak, jl + 1, t2, o2, d2, m2, p);
+            put_worms(Ak, jl + 1, t2, S2, p);
             if (!Ak.resize(0, jv, m1)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<LANES>(Ak, 0, sT[k], o1, d1, m1, sp);
+            put_worms(Ak, 0, sT[k], S1, sp);
             P.cnt[cuk] = Ak.n;
         } else {
+            if (Bk.n + h2 > cap) { atomicOr(flag, FL_OVERFLOW); return; }
+            if (!draw_slots(rs, l2, m2, Bk.e + (long long)(cap - h2) * nloc, nloc, S2, flag)) return;
+            Ak.cap = cap - h1;
+            Bk.cap = cap - h2;
             if (!Ak.resize(0, jv, m1) || !Bk.resize(jl + 1, Bk.n, m2)) { atomicOr(flag, FL_OVERFLOW); return; }
-            put_worms<LANES>(Ak, 0, sT[k], o1, d1, m1, sp);
-            put_worms<LANES>(Bk, jl + 1, t2, o2, d2, m2, p);
+            put_worms(Ak, 0, sT[k], S1, sp);
+            put_worms(Bk, jl + 1, t2, S2, p);
             P.cnt[cuk] = Ak.n;
             P.cnt[cukp] = Bk.n;
         }

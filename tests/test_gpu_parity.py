@@ -238,15 +238,16 @@ def longest_worm_run(st):
     return best
 
 
-@pytest.mark.parametrize("regen_mode", [1, 2])
-def test_regeneration_with_many_worms_per_interval(regen_mode):
-    """eta * beta near its limit: intervals draw up to ~10 worms, so the lane
-    form's slots take both its register path (one or two worms) and its
-    in-place path in the event slots (three or more); the oracle's
-    trajectory either way."""
+@pytest.mark.parametrize("regen_mode,dom_tau", [(1, 2), (2, 2), (1, 1)])
+def test_regeneration_with_many_worms_per_interval(regen_mode, dom_tau):
+    """eta * beta near its limit: intervals draw up to ~10 worms, so the
+    re-generation (lane form) and the temporal boundary update take both
+    their register path for the slots (one or two worms) and their path
+    through event slots (three or more); with one slab also the circle
+    without vertices.  The oracle's trajectory either way."""
     P = _pm()
     # small t: few vertices, long intervals, many worms in each
-    cfg = dict(L=8, beta=8.0, t=0.1, V=0.0, mu=0.0, eta=0.9, dom_x=2, dom_y=2, dom_tau=2, seed=57)
+    cfg = dict(L=8, beta=8.0, t=0.1, V=0.0, mu=0.0, eta=0.9, dom_x=2, dom_y=2, dom_tau=dom_tau, seed=57)
     ch = O.Chain(**cfg)
     longest = 0
     with P.Sim(P.make_params(**cfg), regen_mode=regen_mode) as sim:
