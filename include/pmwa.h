@@ -87,7 +87,11 @@ typedef struct pmwa_opts {
                                  domain fits, else HBM; 2: every domain in HBM */
     int32_t series_cap;       /* per-chain device rows of per-sweep records     */
     int32_t event_cap;        /* events per (site, slab), <= 32767; 0 = from the
-                                 density                                      */
+                                 density.  The temporal boundary update also
+                                 needs room, at the top of a site's array,
+                                 for the slots of a leg that draws three or
+                                 more worms while it places them; running out
+                                 is PMWA_EOVERFLOW like any other excess    */
     int32_t use_graph;        /* 1: replay a captured sweep (hipGraph)          */
     int32_t regen_mode;       /* worm re-generation: 0 auto, 1 a lane per (site,
                                  slab), 2 a wavefront per (site, slab); the
