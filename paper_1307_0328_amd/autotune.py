@@ -219,7 +219,9 @@ class Tuner:
         batch, spatial grids as given: every chain gets ceil(beta*t / slab)
         temporal domains (slab None: the chains' own), and each (slab, LDS
         bytes) pair is timed on all chains together in one launch group;
-        then the best pair with each number of groups in `group_options`.
+        then the best slab with each number of groups in `group_options` and
+        every LDS size (concurrent groups' kernels share each CU's LDS, so the
+        best size can change).
         Smaller slabs put more domains in the LDS node store and give the
         per-(bond, slab) and per-(site, slab) kernels more units; larger ones
         keep fewer boundaries.  Groups let one group's phases start while
@@ -247,7 +249,8 @@ class Tuner:
         tiled = temporal_tiling(chains, slab)
         for g in group_options:
             if g != 1:
-                timed(tiled, slab, lds, g)
+                for l2 in lds_options:
+                    timed(tiled, slab, l2, g)
         best, _ = max(table, key=lambda fr: fr[1])
         return best, temporal_tiling(chains, best[0]), table
 

@@ -22,7 +22,7 @@
 #include "pmwa_device.h"
 
 namespace pmwa {
-__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows, int vmode);
+__global__ void k_vertex(Pools P, const int2* __restrict__ blk, int vs, int cr, int rows, int vmode);
 __global__ void k_assemble_w(Pools P, const int2* __restrict__ blk, int nmax);
 __global__ void k_assemble(Pools P, const int2* __restrict__ blk);
 template <bool HBM_ONLY>
@@ -146,6 +146,7 @@ struct pmwa_handle {
     int bt_lanes = 64;       // lanes per workgroup of the temporal-boundary update (64 or 16)
     int vs = 1;              // candidate column length of the vertex kernel
     int v_rows = 1;          // flips per site staged in LDS by the vertex kernel
+    int v_cr = 1;            // candidate rows per lane of the vertex kernel's LDS
     size_t v_lds = 0;
     int64_t ev_total = 0, site_slabs = 0;
     bool slots = false;
@@ -468,8 +469,8 @@ static int launch_kernel(pmwa_t* h, int phase, const LaunchGroup& g)
     hipStream_t s = g.stream;
     switch (phase) {
     case 1:
-        if (g.nv) hipLaunchKernelGGL(k_vertex, dim3(g.nv), dim3(VL), h->v_lds, s, h->P, g.v, h->vs, h->v_rows,
-                                     h->opts.vertex_mode);
+        if (g.nv) hipLaunchKernelGGL(k_vertex, dim3(g.nv), dim3(VL), h->v_lds, s, h->P, g.v, h->vs, h->v_cr,
+                                     h->v_rows, h->opts.vertex_mode);
         break;
     case 2:
         if (h->regen_wave) {
@@ -884,7 +885,13 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         h->vs = vs;
         // occupation-changing objects (kinks and worms) of a site in a slab
         // staged in LDS; a lane with more reads its lists from HBM
-        const size_t v_fixed = (size_t)vs * (2 * sizeof(double) + VL * sizeof(int32_t));
+        // per lane: candidate rows, 32 (what the register sort takes) or more
+        // if the table is longer than those and the two flip columns, which
+        // a lane with more candidates continues into
+        auto cand_rows = [&](int rw) { return std::min(vs, std::max(32, vs - 2 * rw)); };
+        auto vlds = [&](int rw) {
+            return (size_t)vs * 2 * sizeof(double) + ((size_t)cand_rows(rw) + 2 * (size_t)rw) * VL * sizeof(uint32_t);
+        };
         // rows per lane.  When every block of the vertex launch is resident
         // at once with 64 rows, LDS does not limit it: 64 (the 64x64 chain,
         // one block per CU: 32 rows made it 2.5x slower, since a wavefront
@@ -900,7 +907,7 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
         int rows = h->opts.vertex_rows;
         int64_t vblocks = 0;
         for (auto& hc : h->ch) vblocks += (hc.n_units_v + VL - 1) / VL;
-        const size_t lds64 = v_fixed + (size_t)64 * 2 * VL * sizeof(uint32_t);
+        const size_t lds64 = vlds(64);
         const int64_t resident64 = (int64_t)std::max(prop.multiProcessorCount, 1) *
                                    std::max<int64_t>(1, (int64_t)(lds_max / lds64));
         if (rows == 0 && vblocks <= resident64) rows = std::min(std::max(maxcap, 8), 64);
@@ -914,7 +921,8 @@ static int create_impl(const pmwa_params* chains, int n_chains, const pmwa_opts*
             rows = std::max(16, std::min(rows, std::min(std::max(maxcap, 8), 64)));
         }
         h->v_rows = rows;
-        h->v_lds = v_fixed + (size_t)h->v_rows * 2 * VL * sizeof(uint32_t);
+        h->v_cr = cand_rows(rows);
+        h->v_lds = vlds(rows);
         if (!r2) r2 = set_lds((const void*)k_vertex, h->v_lds, lds_max);
     }
     if (r2) { pmwa_destroy(h); return r2; }

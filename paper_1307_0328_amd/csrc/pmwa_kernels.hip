@@ -362,7 +362,13 @@ PMWA_DEV int2 stage_flips(const uint2* EA, int na, int sa0, uint32_t* FA,
 // doubles), the candidate ticks (one column of vs entries per lane), and the
 // occupation-changing objects of both ends of each lane's bond (two columns
 // of `rows` entries per lane)
-__global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int rows, int vmode)
+// LDS: two rows of the candidate-count table, then per lane a column of cr
+// candidate rows followed by two columns of `rows` flip rows (sites a and c).
+// A lane with more than cr candidates (cr + 2 rows >= the table length)
+// continues its candidate column into its flip columns and walks its site
+// lists in HBM.
+__global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__ blk, int vs, int cr, int rows,
+                                               int vmode)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 bt = blk[blockIdx.x];
@@ -371,7 +377,7 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
     const int u = bt.y + lane;
     double* s_cdf = reinterpret_cast<double*>(smem);
     int32_t* cand = reinterpret_cast<int32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + lane;
-    uint32_t* FA = reinterpret_cast<uint32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + (size_t)vs * VL + lane;
+    uint32_t* FA = reinterpret_cast<uint32_t*>(smem + 2 * (size_t)vs * sizeof(double)) + (size_t)cr * VL + lane;
     uint32_t* FC = FA + (size_t)rows * VL;
     const int k_first = bt.y / (2 * C.N);
 #pragma unroll 4
@@ -406,7 +412,7 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
         // a column is used only with a row to spare: once a count reaches
         // `rows`, later events land on the last row, which then no longer
         // holds the last flip
-        const bool staged = nfa < rows && nfc < rows && !(vmode & 1);
+        bool staged = nfa < rows && nfc < rows && !(vmode & 1);
         const FlipList fla{FA, nfa, B.sa0, d}, flc{FC, nfc, B.sc0, -1};
         const FullList gla{Ea, na, B.st, d}, glc{Ec, nc, B.st, -1};
 
@@ -434,6 +440,9 @@ __global__ void __launch_bounds__(VL) k_vertex(Pools P, const int2* __restrict__
             }
             n = lo;
         }
+        // more candidates than the column's rows: they run on into the flip
+        // columns, and the walk reads the site lists from HBM
+        if (n > cr) staged = false;
         const uint64_t dT = (uint64_t)(Tk1 - Tk);
         // ticks as first drawn; they are the ticks kept unless one repeats
         // a kink of the bond or another candidate.  Up to 32 candidates are

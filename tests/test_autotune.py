@@ -98,6 +98,7 @@ def test_temporal_tiling_and_tune_tiling():
     assert best == (8.0, 36864, 2)
     assert [c["dom_tau"] for c in tiled] == [1, 1, 2, 1]
     assert [c["chain_id"] for c in tiled] == [0, 1, 2, 3]
-    assert len(table) == len(seen) == 14
-    # groups are tried on the best (slab, lds) pair only
-    assert {s for s in seen if s[2] != 1} == {((1, 1, 2, 1), 36864, 2), ((1, 1, 2, 1), 36864, 3)}
+    assert len(table) == len(seen) == 20
+    # groups are tried on the best slab only, with every LDS size
+    assert {s for s in seen if s[2] != 1} == {((1, 1, 2, 1), l, g) for l in (24576, 28672, 36864, 45056)
+                                              for g in (2, 3)}

@@ -158,12 +158,14 @@ def test_plain_4x4_full_run_and_ed():
         assert abs(m - gold[k]) < 4.5 * e, (k, m, e, gold[k])
 
 
-@pytest.mark.parametrize("vmode", [1, 2, 3])
+@pytest.mark.parametrize("vmode", [0, 1, 2, 3])
 def test_forced_vertex_paths(vmode):
     """vertex_mode bit0: every bond walks its site lists in HBM; bit1: every
     candidate set is sorted in its LDS column.  Both give the oracle's
     trajectory, on a beta*t = 16 single-slab chain (up to ~60 candidates
-    per bond) and a 2x2x2 domain grid."""
+    per bond: more than the 32 candidate rows, so those lanes' columns run
+    on into their flip rows, also in the default mode 0) and a 2x2x2 domain
+    grid."""
     from paper_1307_0328_amd import pmwa as P
     cases = [dict(L=8, beta=16.0, V=1.0, mu=0.5, eta=0.05, dom_x=2, dom_y=2, dom_tau=1, seed=41),
              dict(L=8, beta=4.0, V=1.0, mu=0.5, eta=0.2, dom_x=2, dom_y=2, dom_tau=2, seed=42)]
