@@ -203,3 +203,33 @@ def test_few_vertex_rows(rows):
     ref = ch.series()
     for f in ("nv", "nkink", "nw", "occ2", "nn2"):
         np.testing.assert_array_equal(rows_dev[f], ref[f], err_msg=f)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_bench_headline_form_against_the_oracle(graph):
+    """The 256-chain batch in the form the benchmark's tuner picks (slabs of
+    at most beta*t 4, 24 KB of scattering LDS, three launch groups): five of
+    its chains, the two largest among them (12x12-site domains on both node
+    stores), against the oracle run alongside for 200 sweeps from the empty
+    state."""
+    from paper_1307_0328_amd import autotune as T
+    from paper_1307_0328_amd import pmwa as P
+    from paper_1307_0328_amd import workloads as W
+    batch = T.temporal_tiling(W.batched_256(), 4.0)
+    big = [i for i, c in enumerate(batch) if c["Lx"] == 48 and c["beta"] == 16.0][:2]
+    picks = big + [7, 100, 201]
+    orc = {i: O.Chain(**batch[i]) for i in picks}
+    say(f"[equilibrium] headline form, graph={graph}, chains {picks}")
+    with P.Sim([P.make_params(**c) for c in batch], scatter_lds=24576, groups=3, use_graph=graph,
+               series_cap=512) as sim:
+        for step in range(4):
+            sim.sweep(50)
+            assert sim.status() == 0
+            for i in picks:
+                orc[i].sweep(50)
+                assert sim.state_hash(i) == orc[i].state_hash(), f"chain {i} after {50 * (step + 1)} sweeps"
+            say(f"[equilibrium] headline form: sweep {50 * (step + 1)} hashes ok")
+        for i in picks:
+            rows, ref = sim.measure(i), orc[i].series()
+            for f in ("nv", "nkink", "nw", "occ2", "nn2"):
+                np.testing.assert_array_equal(rows[f], ref[f], err_msg=f"chain {i}: {f}")
