@@ -358,12 +358,10 @@ PMWA_DEV int2 stage_flips(const uint2* EA, int na, int sa0, uint32_t* FA,
     return make_int2(fa, fc);
 }
 
-// dynamic LDS: Poisson tables of the first two slabs of the block (2 * vs
-// doubles), the candidate ticks (one column of vs entries per lane), and the
-// occupation-changing objects of both ends of each lane's bond (two columns
-// of `rows` entries per lane)
-// LDS: two rows of the candidate-count table, then per lane a column of cr
-// candidate rows followed by two columns of `rows` flip rows (sites a and c).
+// dynamic LDS: the Poisson tables of the first two slabs of the block (2 * vs
+// doubles), then per lane a column of cr candidate rows followed by two
+// columns of `rows` rows for the occupation-changing objects of both ends of
+// the lane's bond.
 // A lane with more than cr candidates (cr + 2 rows >= the table length)
 // continues its candidate column into its flip columns and walks its site
 // lists in HBM.
