@@ -135,3 +135,38 @@ def test_resume_from_a_checkpoint_in_another_pool():
     assert len(both) == 30
     for f in ("nv", "nkink", "nw", "occ2", "nn2", "qimp"):
         np.testing.assert_array_equal(both[f], rows[f], err_msg=f)
+
+
+def test_memory_budget_pools_equal_alone():
+    """Jobs larger than the base slots run in pools made for their shape
+    within the memory budget (freed when empty), beside the base slot's
+    jobs; every job's state and records equal the job run alone."""
+    from paper_1307_0328_amd import pmwa as P
+    from paper_1307_0328_amd import serve as S
+    from paper_1307_0328_amd import workloads as W
+    small = W.serving_slot_shape(16, 8.0)
+    big = W.serving_slot_shape(32, 8.0)
+    # the 32^2 jobs share one shape (a pool made for a job takes jobs whose
+    # tables are no longer than its first job's)
+    jobs = [S.Job(0, 0.0, 30, dict(big, mu=0.2, seed=31, chain_id=1)),
+            S.Job(1, 0.0, 40, dict(big, mu=0.2, seed=32, chain_id=2)),
+            S.Job(2, 0.0, 25, dict(big, mu=0.2, seed=33, chain_id=3)),
+            S.Job(3, 0.0, 35, dict(small, mu=0.1, seed=34, chain_id=4))]
+    budget = S.footprint_bytes(small, 256) + 2 * S.footprint_bytes(big, 256)
+    print("[serving] memory budget: one 16^2 slot, room for one pool of two 32^2 slots", flush=True)
+    srv = S.Server([small], event_cap=256, chunk=5, keep_state=True, memory_budget=budget, pool_slots=2)
+    try:
+        rep = srv.run(jobs, realtime=False, max_seconds=120)
+        assert rep["failed"] == 0 and rep["pools_made"] == 2 and rep["most_pools"] == 2
+        assert len(srv.pools) == 1
+    finally:
+        srv.close()
+    for j in jobs:
+        with P.Sim(P.make_params(**j.params), event_cap=256) as sim:
+            sim.sweep(j.sweeps)
+            alone = sim.get_state()
+            rows = sim.measure()
+        for k in ("bstate", "counts", "ticks", "infos"):
+            np.testing.assert_array_equal(j.state[k], alone[k], err_msg=f"job {j.jid} {k}")
+        for f in ("nv", "nkink", "nw", "occ2", "nn2", "qimp"):
+            np.testing.assert_array_equal(j.rows[f], rows[f], err_msg=f"job {j.jid} {f}")

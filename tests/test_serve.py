@@ -21,6 +21,8 @@ class FakeLib:
 
     def __init__(self, shapes):
         self.shapes = shapes
+        self.by_h = {}                # handle -> slot shapes
+        self.destroyed = []
         self.caps = {}                # handle -> event capacity
         self.loaded = {}              # (handle, slot) -> [mu, target]
         self.done = {}
@@ -28,12 +30,12 @@ class FakeLib:
         self.flag = {}
         self.loads = []
 
-    def fits(self, slot, p):
-        s = self.shapes[slot]
+    def fits(self, slot, p, h=None):
+        s = (self.by_h.get(h) or self.shapes)[slot]
         return p.Lx <= s.Lx and p.Ly <= s.Ly and p.dom_tau <= s.dom_tau
 
     def pmwa_slot_load(self, h, slot, p, target):
-        if not self.fits(slot, p):
+        if not self.fits(slot, p, h):
             return P.PMWA_EINVAL
         self.loaded[(h, slot)] = (p.mu, target)
         self.done[(h, slot)] = 0
@@ -54,12 +56,13 @@ def make_backend(shapes):
     def create(shapes_, o):
         h = object()
         fake.caps[h] = o.event_cap
+        fake.by_h[h] = list(shapes_)
         return h
 
     B.make_params = P.make_params
     B.pmwa_create_slots = create
-    B.pmwa_destroy = lambda h: None
-    B.pmwa_slot_fits = lambda h, slot, p: fake.fits(slot, p)
+    B.pmwa_destroy = lambda h: fake.destroyed.append(h)
+    B.pmwa_slot_fits = lambda h, slot, p: fake.fits(slot, p, h)
     B.lib = lambda: fake
 
     def sweep(h, n):
@@ -153,3 +156,31 @@ def test_overflow_without_regrowth_fails():
     # one regrowth (to 512) is not enough: the job fails after restarting from scratch
     assert rep["failed"] == 1 and job.error == P.PMWA_EOVERFLOW and job.regrows == 1
     assert [c for c, _ in fake.loads] == [256, 512]
+
+
+def test_memory_budget_admits_jobs_in_pools_of_their_own_shape():
+    """A job that fits no base slot gets a pool of its own shape while the
+    pools' bytes stay within the budget; later jobs of that shape share it or
+    wait for a slot; a job whose own pool would exceed the budget is
+    rejected; a pool made on demand is freed when its last job leaves."""
+    shapes = [dict(Lx=16, Ly=16, beta=8.0, dom_x=2, dom_y=2, dom_tau=1)]
+    B, fake = make_backend([P.make_params(**s) for s in shapes])
+    base = dict(beta=4.0, t=1.0, V=0.0, eta=0.05, dom_x=2, dom_y=2, dom_tau=1)
+    big = dict(base, Lx=32, Ly=32, mu=0.0)
+    budget = S.footprint_bytes(shapes[0], 256) + 2 * S.footprint_bytes(big, 256)
+    srv = S.Server(shapes, chunk=10, backend=B, memory_budget=budget, pool_slots=2)
+    jobs = [S.Job(0, 0.0, 30, dict(big)),
+            S.Job(1, 0.0, 50, dict(big, mu=0.5)),
+            S.Job(2, 0.0, 20, dict(big, mu=1.0)),                # waits for a slot of the pool
+            S.Job(3, 0.0, 20, dict(base, Lx=64, Ly=64, mu=0.0)),  # its own pool exceeds the budget
+            S.Job(4, 0.0, 40, dict(base, Lx=16, Ly=16, mu=0.0))]  # the base slot
+    rep = srv.run(jobs, realtime=False, max_seconds=10.0)
+    err = {j.jid: j.error for j in jobs}
+    assert err == {0: 0, 1: 0, 2: 0, 3: P.PMWA_EINVAL, 4: 0}
+    for j in jobs:
+        if j.error == 0:
+            assert list(j.rows["nv"]) == list(range(1, j.sweeps + 1))
+    # one pool of the 32x32 shape, made once, held two jobs at a time, freed at the end
+    assert rep["pools_made"] == 2 and rep["most_pools"] == 2
+    assert jobs[2].admitted > 0.0 and jobs[2].admitted >= jobs[0].finished - 1e-9
+    assert len(srv.pools) == 1 and len(fake.destroyed) == 1 and not fake.loaded
