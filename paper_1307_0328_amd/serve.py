@@ -212,7 +212,9 @@ class Server:
     def _admit(self, job: Job) -> bool:
         """Best fit among the free slots of the job's capacity level; else,
         within the memory budget, a new pool of the job's own shape."""
-        self._pool(job.pool)
+        p = self.B.make_params(**job.params)
+        if any(self.B.pmwa_slot_fits(self.h, s, p) for s in range(len(self.shapes))):
+            self._pool(job.pool)       # the base shapes at this capacity level, made on first use
         need = footprint_bytes(job.params, self.event_cap << job.pool)
         cands = [(pl.cap_bytes[s], i, pl, s) for i, pl in enumerate(self.pools) if pl.level == job.pool
                  for s in pl.free if pl.cap_bytes[s] >= need]

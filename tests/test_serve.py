@@ -184,3 +184,20 @@ def test_memory_budget_admits_jobs_in_pools_of_their_own_shape():
     assert rep["pools_made"] == 2 and rep["most_pools"] == 2
     assert jobs[2].admitted > 0.0 and jobs[2].admitted >= jobs[0].finished - 1e-9
     assert len(srv.pools) == 1 and len(fake.destroyed) == 1 and not fake.loaded
+
+
+def test_a_job_in_its_own_pool_regrows_into_its_own_pool():
+    """An overflowing job of a shape the base slots do not hold regrows into
+    a pool of its shape at twice the capacity; no base pool is made at that
+    capacity for it, and both of its pools are freed."""
+    shapes = [dict(Lx=16, Ly=16, beta=8.0, dom_x=2, dom_y=2, dom_tau=1)]
+    B, fake = make_backend([P.make_params(**s) for s in shapes])
+    base = dict(beta=4.0, t=1.0, V=0.0, eta=0.05, dom_x=2, dom_y=2, dom_tau=1)
+    job = S.Job(0, 0.0, 60, dict(base, Lx=32, Ly=32, mu=9.0))      # overflows below 1024 events
+    srv = S.Server(shapes, event_cap=512, chunk=10, backend=B, regrow=1, checkpoint_every=1,
+                   memory_budget=1 << 40, pool_slots=1)
+    rep = srv.run([job], realtime=False, max_seconds=10.0)
+    assert rep["failed"] == 0 and job.regrows == 1 and job.resumes == 1
+    assert list(job.rows["nv"]) == list(range(1, 61))
+    assert [c for c, _ in fake.loads] == [512, 1024]
+    assert rep["pools_made"] == 3 and len(srv.pools) == 1 and len(fake.destroyed) == 2
