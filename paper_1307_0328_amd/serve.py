@@ -224,7 +224,14 @@ class Server:
         if self.memory_budget > 0:
             extra = self._own_pool_bytes(job, job.pool)
             if self._used_bytes() + extra <= self.memory_budget:
-                pl = self._make([job.params] * self.pool_slots, job.pool, True)
+                try:
+                    pl = self._make([job.params] * self.pool_slots, job.pool, True)
+                except self.B.PmwaError as e:
+                    # the device has less free memory than the budget assumed:
+                    # the job waits for memory to free up
+                    if e.code != getattr(self.B, "PMWA_ENOMEM", P.PMWA_ENOMEM):
+                        raise
+                    return False
                 if self._load(job, pl, 0) == 0:
                     return True
         return False

@@ -201,3 +201,26 @@ def test_a_job_in_its_own_pool_regrows_into_its_own_pool():
     assert list(job.rows["nv"]) == list(range(1, 61))
     assert [c for c, _ in fake.loads] == [512, 1024]
     assert rep["pools_made"] == 3 and len(srv.pools) == 1 and len(fake.destroyed) == 2
+
+
+def test_a_pool_that_cannot_be_allocated_leaves_the_job_waiting():
+    """When the device cannot allocate a pool the budget allowed, the job
+    waits; once nothing runs and nothing can take it, it is rejected, and
+    the other jobs are unaffected."""
+    shapes = [dict(Lx=16, Ly=16, beta=8.0, dom_x=2, dom_y=2, dom_tau=1)]
+    B, fake = make_backend([P.make_params(**s) for s in shapes])
+    create = B.pmwa_create_slots
+
+    def create_or_fail(shapes_, o):
+        if shapes_[0].Lx > 16:
+            raise P.PmwaError(P.PMWA_ENOMEM, "pmwa_create_slots")
+        return create(shapes_, o)
+
+    B.pmwa_create_slots = create_or_fail
+    base = dict(beta=4.0, t=1.0, V=0.0, eta=0.05, dom_x=2, dom_y=2, dom_tau=1)
+    jobs = [S.Job(0, 0.0, 30, dict(base, Lx=32, Ly=32, mu=0.0)),
+            S.Job(1, 0.0, 20, dict(base, Lx=16, Ly=16, mu=0.0))]
+    srv = S.Server(shapes, chunk=10, backend=B, memory_budget=1 << 40, pool_slots=1)
+    rep = srv.run(jobs, realtime=False, max_seconds=10.0)
+    assert {j.jid: j.error for j in jobs} == {0: P.PMWA_EINVAL, 1: 0}
+    assert rep["pools_made"] == 1 and list(jobs[1].rows["nv"]) == list(range(1, 21))
